@@ -1,0 +1,212 @@
+/*
+ * firls.h - C ABI of the MI355X FIRLS library (libfirls.so).
+ *
+ * FIRLS (Chen, Huang, He, Li: "Fast Iteratively Reweighted Least Squares
+ * Algorithms for Analysis-Based Sparsity Reconstruction") reconstructs an
+ * n x n complex image x from undersampled k-space data b by minimising
+ *
+ *     F(x) = 1/2 ||A x - b||^2 + lambda ||Psi x||_{2,1}        (Section 1, eq. 3)
+ *
+ * with A = R F the masked unitary 2D Fourier transform (Section 5.4) and Psi
+ * either an L-level orthonormal Haar transform Phi with (possibly
+ * overlapping) groups given by a replication matrix G (Section 3.1, eq. 8),
+ * or the periodic forward differences [D1; D2] of total variation
+ * (Section 4.1, eqs. 32-35).  Each outer iteration refreshes the group
+ * weights W (eq. 12 / eq. 37) and runs PCG on the normal equations
+ * (A^H A + lambda Psi^T G^T W G Psi) x = A^H b (eq. 15 / eq. 39) with the
+ * pseudo-diagonal preconditioner (eq. 17) or, for TV, the triangular
+ * factors of the penta-diagonal preconditioner (eqs. 40-43) in red-black
+ * order.  Algorithms 2 and 3 give the loop.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Device pointers are HIP device memory on the current device; host
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns its handle and its workspace.
+ *  - Images and k-space arrays are n x n, row-major, complex interleaved
+ *    (re, im): float2 in FIRLS_FP32 mode, double2 in FIRLS_FP64 mode.
+ *    k-space is unshifted (DC at [0, 0]); F is unitary (1/n both ways).
+ *  - Masks are uint8 n x n (nonzero = sampled).  b is read as mask * b.
+ *  - ``stream`` is a hipStream_t passed as void*; NULL is the null stream.
+ *    Calls enqueue on it and return once their results are on the host
+ *    (reports) or enqueued (operator entry points, see each).
+ *  - Return codes: 0 = success, negative = error (nothing useful was
+ *    written), positive = warning.  firls_last_error() gives a message
+ *    for the calling thread.
+ *  - A handle is not thread-safe: one caller at a time.
+ */
+#ifndef FIRLS_H
+#define FIRLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct firls_handle firls_handle;
+
+enum {
+  FIRLS_OK = 0,
+  FIRLS_E_INVALID = -1,      /* bad argument (message says which) */
+  FIRLS_E_UNSUPPORTED = -2,  /* valid but not built (size, levels) */
+  FIRLS_E_HIP = -3,          /* a HIP runtime call failed */
+  FIRLS_E_NOMEM = -4,        /* device allocation failed */
+  FIRLS_E_NONFINITE = -5,    /* objective became NaN or Inf */
+  FIRLS_W_MAXITER = 1        /* stopped at max_outer before the tolerance */
+};
+
+enum { FIRLS_PSI_HAAR = 0, FIRLS_PSI_TV = 1 };
+enum { FIRLS_FP64 = 0, FIRLS_FP32 = 1 };
+
+/* Preconditioner of the inner PCG.  PAPER is the paper's choice: eq. (17)
+ * for Haar, the triangular factors of eq. (40) for TV.  JACOBI uses
+ * diag(S)^{-1} and NONE is plain CG (the comparisons of Section 5.2). */
+enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
+
+/* One image geometry and regulariser.
+ *   n           image side; n in {16, 32, 48, 64, 96, 128, 192, 256, 384, 512}.
+ *   psi         FIRLS_PSI_HAAR or FIRLS_PSI_TV.
+ *   levels      Haar levels L >= 1, n % 2^L == 0; L <= 4 (FP32) or <= 3
+ *               (FP64).  Ignored for TV.
+ *   n_groups    number of groups s; 0 with NULL pointers selects the
+ *               default map: singletons for Haar (standard sparsity), pixel
+ *               pairs {D1 row p, D2 row p} for TV (isotropic TV, eq. 35).
+ *   group_ptr   host int32[n_groups + 1], CSR offsets (group_ptr[0] = 0).
+ *   group_idx   host int32[group_ptr[n_groups]]: members of each group as
+ *               rows of the transform output.  Haar: Mallat index r * n + c
+ *               of the coefficient (top-left block = coarsest approximation,
+ *               level-l details in [0,h)x[h,2h), [h,2h)x[0,h), [h,2h)^2
+ *               with h = n / 2^l).  TV: p for (D1 x)[p], N + p for
+ *               (D2 x)[p], N = n^2.  A coefficient may sit in several groups
+ *               (overlap through G, Section 3.1, Fig. 1).  Every coefficient
+ *               must be covered by at least one group.
+ * The arrays are copied at create; the caller keeps ownership. */
+typedef struct {
+  int32_t n;
+  int32_t psi;
+  int32_t levels;
+  int32_t n_groups;
+  const int32_t* group_ptr;
+  const int32_t* group_idx;
+} firls_shape;
+
+/* Solver configuration.
+ *   max_slices  largest batch a solve call may pass (>= 1).
+ *   prec        FIRLS_FP32 (vectors float2, PCG scalars and every reduction
+ *               in FP64) or FIRLS_FP64 (everything double).
+ *   eps         smoothing of the weights, eq. (12); > 0 (paper: 1e-10).
+ *   max_outer   T_max: largest number of reweighted solves (>= 0).
+ *   pcg_iters   K: PCG iterations per outer iteration, 1..64 (Section 3.2
+ *               reports 10 to 30 sufficient).
+ *   outer_tol   tau: stop once (F_eps^{k-1} - F_eps^k) <= tau F_eps^k; 0
+ *               runs max_outer solves.
+ *   precond     FIRLS_PC_*. */
+typedef struct {
+  int32_t n_shapes;
+  const firls_shape* shapes;
+  int32_t max_slices;
+  int32_t prec;
+  double eps;
+  int32_t max_outer;
+  int32_t pcg_iters;
+  double outer_tol;
+  int32_t precond;
+} firls_config;
+
+/* One image to reconstruct.  b, mask and x are device pointers of the
+ * layouts above; x is read (when x_is_init != 0, the warm start x^1) and
+ * overwritten with the result.  With x_is_init == 0 the solve starts from
+ * x^1 = A^H b (Section 3.3). lambda > 0. */
+typedef struct {
+  int32_t shape_id;
+  int32_t x_is_init;
+  double lambda;
+  const void* b;
+  const uint8_t* mask;
+  void* x;
+} firls_slice;
+
+/* Per-slice result.  F_eps = 1/2||Ax-b||^2 + lambda sum sqrt(||(Psi x)_g||^2
+ * + eps) and F (eps = 0) of the returned x; rel_change = (F_eps^{prev} -
+ * F_eps) / F_eps at the last evaluation (0 if only one). */
+typedef struct {
+  int32_t status;
+  int32_t outer_iters;
+  int32_t pcg_iters;
+  int32_t converged;
+  double F;
+  double F_eps;
+  double data;
+  double rel_change;
+} firls_report;
+
+/* Build a handle: validates the shapes, copies the group maps to the
+ * device (remapped to the library's tile-major coefficient layout) and
+ * uploads twiddle tables.  Allocates device memory; the per-slice
+ * workspace is allocated on the first solve that needs it. */
+int firls_create(const firls_config* cfg, firls_handle** out);
+
+/* Release the handle and all device memory it owns (NULL is a no-op). */
+int firls_destroy(firls_handle* h);
+
+/* Device bytes the per-slice workspace needs for ``n`` slices of shape
+ * ``shape_id`` (for budgeting; allocation stays internal). */
+size_t firls_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n);
+
+/* FIRLS_OG (Algorithm 2) or FIRLS_TV (Algorithm 3) on one slice.  Blocks
+ * until the report is written. */
+int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_report* report);
+
+/* Many independent slices of any configured shapes in one call; slices of
+ * the same shape share every launch, converged slices drop out at outer
+ * iteration boundaries.  reports[i] belongs to slices[i].  Returns the
+ * worst status (error < 0 first, else the largest warning). */
+int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices,
+                        const firls_slice* slices, firls_report* reports);
+
+/* ---- single-operator entry points (one slice; enqueue only) ----------- */
+
+/* x = A^H b = F^H (mask * b)  (the zero-filled start, Section 3.3). */
+int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id,
+                     const void* b, const uint8_t* mask, void* x);
+
+/* d = diag(G^T W G) for W = W(x) (eq. 12-13 / eq. 37-38), written to the
+ * device array d_out (float or double per prec) in the caller's
+ * transform-row order (Mallat for Haar, [D1; D2] rows for TV); length n^2
+ * (Haar) or 2 n^2 (TV). */
+int firls_op_weights(firls_handle* h, void* stream, int32_t shape_id,
+                     const void* x, void* d_out);
+
+/* q = S p = A^H A p + lambda Psi^T diag(d) Psi p with d = d(x_w)
+ * (eq. 15 / eq. 39). */
+int firls_op_system(firls_handle* h, void* stream, int32_t shape_id,
+                    const uint8_t* mask, double lambda, const void* x_w,
+                    const void* p, void* q);
+
+/* z = P^{-1} r for the configured preconditioner at the weights of x_w
+ * (eq. 17 exactly for Haar; SGS factors of eq. 40 for TV). */
+int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id,
+                     const uint8_t* mask, double lambda, const void* x_w,
+                     const void* r, void* z);
+
+/* Host double[3] = {F_eps(x), F(x), 1/2||Ax - b||^2}; blocks. */
+int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id,
+                       const void* b, const uint8_t* mask, double lambda,
+                       const void* x, double* out3);
+
+/* One reweighted solve: weights from x, then pcg_iters PCG iterations on
+ * eq. (15) / (39) started at x; x is updated in place (one outer
+ * iteration of Algorithm 2 / 3).  Blocks. */
+int firls_op_outer_step(firls_handle* h, void* stream, int32_t shape_id,
+                        const void* b, const uint8_t* mask, double lambda, void* x);
+
+/* Thread-local text of the last error (empty string if none). */
+const char* firls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIRLS_H */

@@ -1,0 +1,721 @@
+// Host side of the C ABI: validation, group-map preparation, workspace,
+// and the outer loop of Algorithms 2 / 3 driving the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "firls.h"
+#include "firls_registry.h"
+
+using namespace firls;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(FIRLS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int rows_of(bool fp64) { return fp64 ? 8 : 16; }
+
+struct Shape {
+  int n = 0, psi = 0, L = 0, n_groups = 0, n_coef = 0;
+  int64_t n_members = 0;
+  int32_t* d_gptr = nullptr;
+  int32_t* d_gidx = nullptr;
+  int32_t* d_tptr = nullptr;
+  int32_t* d_tidx = nullptr;
+  int32_t* d_perm = nullptr;
+  const SizeKernels* sk = nullptr;
+  void* tw = nullptr;
+};
+
+// Position of Mallat coefficient (gr, gc) of an n x n, L-level Haar
+// transform in the tile-major layout: the tile of side 2^L that the
+// coefficient's support lies in, and its place in that tile's own Mallat
+// arrangement.
+int32_t haar_internal_index(int n, int L, int gr, int gc) {
+  const int hL = n >> L;
+  if (gr < hL && gc < hL) return (gr << L) * n + (gc << L);
+  int lev = 1;
+  while (lev < L && std::max(gr, gc) < (n >> lev)) ++lev;
+  const int hg = n >> lev;
+  const int i = gr >= hg ? gr - hg : gr;
+  const int j = gc >= hg ? gc - hg : gc;
+  const int sh = L - lev, ht = 1 << sh;
+  const int I = i >> sh, J = j >> sh;
+  const int lr = (i & (ht - 1)) + (gr >= hg ? ht : 0);
+  const int lc = (j & (ht - 1)) + (gc >= hg ? ht : 0);
+  return ((I << L) + lr) * n + (J << L) + lc;
+}
+
+}  // namespace
+
+struct firls_handle {
+  firls_config cfg{};
+  std::vector<Shape> shapes;
+  bool fp64 = false;
+  size_t elt = 8;    // bytes per complex
+  size_t relt = 4;   // bytes per real
+  std::vector<std::pair<int, void*>> tw;
+  int device = 0;
+
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  int cap_slices = 0;
+  SliceDesc* d_desc = nullptr;
+  SliceState* d_state = nullptr;
+  int32_t* d_list = nullptr;
+  SliceDesc* h_desc = nullptr;
+  SliceState* h_state = nullptr;
+  int32_t* h_list = nullptr;
+  hipEvent_t ev = nullptr;
+
+  size_t slice_bytes(const Shape& s) const {
+    const size_t vec = align256((size_t)s.n * s.n * elt);
+    const size_t nvec = s.psi == PSI_TV ? 6 : 4;
+    return nvec * vec + 2 * align256((size_t)s.n_coef * relt) + align256((size_t)s.n_groups * relt) +
+           align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
+  }
+};
+
+namespace {
+
+void free_batch(firls_handle* h) {
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->d_desc) (void)hipFree(h->d_desc);
+  if (h->d_state) (void)hipFree(h->d_state);
+  if (h->d_list) (void)hipFree(h->d_list);
+  if (h->h_desc) (void)hipHostFree(h->h_desc);
+  if (h->h_state) (void)hipHostFree(h->h_state);
+  if (h->h_list) (void)hipHostFree(h->h_list);
+  h->ws = nullptr;
+  h->ws_cap = 0;
+  h->d_desc = nullptr;
+  h->d_state = nullptr;
+  h->d_list = nullptr;
+  h->h_desc = nullptr;
+  h->h_state = nullptr;
+  h->h_list = nullptr;
+  h->cap_slices = 0;
+}
+
+int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
+  if (bytes > h->ws_cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->ws) HIPCHK(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_cap = 0;
+    if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FIRLS_E_NOMEM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    h->ws_cap = bytes;
+  }
+  // two list copies (all slices, then the zero-filled subset) need 2x
+  const int want = std::max(slices, 2);
+  if (want > h->cap_slices) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->d_desc) HIPCHK(hipFree(h->d_desc));
+    if (h->d_state) HIPCHK(hipFree(h->d_state));
+    if (h->d_list) HIPCHK(hipFree(h->d_list));
+    if (h->h_desc) HIPCHK(hipHostFree(h->h_desc));
+    if (h->h_state) HIPCHK(hipHostFree(h->h_state));
+    if (h->h_list) HIPCHK(hipHostFree(h->h_list));
+    HIPCHK(hipMalloc(&h->d_desc, sizeof(SliceDesc) * want));
+    HIPCHK(hipMalloc(&h->d_state, sizeof(SliceState) * want));
+    HIPCHK(hipMalloc(&h->d_list, sizeof(int32_t) * 2 * want));
+    HIPCHK(hipHostMalloc(&h->h_desc, sizeof(SliceDesc) * want, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h->h_state, sizeof(SliceState) * want, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h->h_list, sizeof(int32_t) * 2 * want, hipHostMallocDefault));
+    h->cap_slices = want;
+  }
+  return FIRLS_OK;
+}
+
+// Carve slice i's workspace at byte offset ``off``.
+void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const firls_slice* sl) {
+  char* base = static_cast<char*>(h->ws) + off;
+  const size_t vec = align256((size_t)s.n * s.n * h->elt);
+  std::memset(&D, 0, sizeof(D));
+  D.r[0] = base;
+  D.p = base + vec;
+  D.q = base + 2 * vec;
+  D.t = base + 3 * vec;
+  size_t o = 4 * vec;
+  if (s.psi == PSI_TV) {
+    D.r[1] = base + o;
+    D.z = base + o + vec;
+    o += 2 * vec;
+  } else {
+    D.r[1] = D.r[0];
+  }
+  D.d = base + o;
+  o += align256((size_t)s.n_coef * h->relt);
+  D.sq = base + o;
+  o += align256((size_t)s.n_coef * h->relt);
+  D.W = base + o;
+  o += align256((size_t)s.n_groups * h->relt);
+  D.parts = reinterpret_cast<double*>(base + o);
+  D.n = s.n;
+  D.shape = 0;
+  if (sl) {
+    D.b = sl->b;
+    D.mask = sl->mask;
+    D.x = sl->x;
+    D.lambda = sl->lambda;
+  }
+}
+
+Params base_params(const firls_handle* h, const Shape& s, int shape_id, const int32_t* list) {
+  Params P{};
+  P.desc = h->d_desc;
+  P.state = h->d_state;
+  P.list = list;
+  P.tw = s.tw;
+  P.shape.gptr = s.d_gptr;
+  P.shape.gidx = s.d_gidx;
+  P.shape.tptr = s.d_tptr;
+  P.shape.tidx = s.d_tidx;
+  P.shape.perm = s.d_perm;
+  P.shape.n_groups = s.n_groups;
+  P.shape.n_coef = s.n_coef;
+  P.n = s.n;
+  P.L = s.L;
+  P.K = h->cfg.pcg_iters;
+  P.Tmax = h->cfg.max_outer;
+  P.precond = h->cfg.precond;
+  P.eps = h->cfg.eps;
+  P.tau = h->cfg.outer_tol;
+  const int R = rows_of(h->fp64);
+  P.npq = s.n / R;
+  P.ndata = s.n / R;
+  P.nrz = s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC);
+  P.nreg = (s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG;
+  (void)shape_id;
+  return P;
+}
+
+#define LAUNCH(fn, P, grid, st)                                                         \
+  do {                                                                                  \
+    hipError_t e_ = (fn)((P), (grid), (st));                                            \
+    if (e_ != hipSuccess) return fail(FIRLS_E_HIP, std::string("launch ") + #fn + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.
+int launch_weights(const firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+  const PrecKernels* pk = prec_kernels(h->fp64);
+  const int R = rows_of(h->fp64);
+  if (s.psi == PSI_HAAR) LAUNCH(s.sk->psi_sq_haar, P, dim3(s.n / R, c), st);
+  else LAUNCH(pk->psi_sq_tv, P, dim3((s.n * s.n + 4 * NT - 1) / (4 * NT), c), st);
+  LAUNCH(pk->group_w, P, dim3(P.nreg, c), st);
+  LAUNCH(pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
+  return FIRLS_OK;
+}
+
+// r0 = A^H b - S x (data term fused), then z0 and <r0, z0>.
+int launch_residual(const firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+  const PrecKernels* pk = prec_kernels(h->fp64);
+  const int R = rows_of(h->fp64);
+  const bool haar = s.psi == PSI_HAAR;
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, c), st);
+  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / R, c), st);
+  LAUNCH(s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / R, c), st);
+  if (haar) LAUNCH(s.sk->update_haar[UP_INIT], P, dim3(s.n / R, c), st);
+  else LAUNCH(pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
+  return FIRLS_OK;
+}
+
+int launch_pcg(const firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
+  const PrecKernels* pk = prec_kernels(h->fp64);
+  const int R = rows_of(h->fp64);
+  const bool haar = s.psi == PSI_HAAR;
+  for (int k = 0; k < h->cfg.pcg_iters; ++k) {
+    P.k = k;
+    LAUNCH(s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / R, c), st);
+    LAUNCH(s.sk->col[COL_SP], P, dim3(s.n / R, c), st);
+    LAUNCH(s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / R, c), st);
+    if (haar) LAUNCH(s.sk->update_haar[UP_STEP], P, dim3(s.n / R, c), st);
+    else LAUNCH(pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
+  }
+  return FIRLS_OK;
+}
+
+int check_slice(const firls_handle* h, const firls_slice& sl) {
+  if (sl.shape_id < 0 || sl.shape_id >= (int)h->shapes.size()) return fail(FIRLS_E_INVALID, "shape_id out of range");
+  if (!(sl.lambda > 0.0) || !std::isfinite(sl.lambda)) return fail(FIRLS_E_INVALID, "lambda must be positive and finite");
+  if (!sl.b || !sl.mask || !sl.x) return fail(FIRLS_E_INVALID, "b, mask and x must be device pointers");
+  return FIRLS_OK;
+}
+
+// The batched outer loop shared by every solve entry point.
+int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
+  if (ns <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
+  if (ns > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
+  if (!sl || !rep) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
+  for (int i = 0; i < ns; ++i) {
+    int rc = check_slice(h, sl[i]);
+    if (rc) return rc;
+  }
+  std::vector<size_t> off(ns);
+  size_t need = 0;
+  for (int i = 0; i < ns; ++i) {
+    off[i] = need;
+    need += h->slice_bytes(h->shapes[sl[i].shape_id]);
+  }
+  int rc = ensure_capacity(h, st, need, ns);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));  // pinned staging below may still feed an earlier copy
+  const int nsh = (int)h->shapes.size();
+  std::vector<std::vector<int>> by_shape(nsh), zf_by_shape(nsh);
+  for (int i = 0; i < ns; ++i) {
+    fill_desc(h, h->h_desc[i], h->shapes[sl[i].shape_id], off[i], &sl[i]);
+    h->h_desc[i].shape = sl[i].shape_id;
+    by_shape[sl[i].shape_id].push_back(i);
+    if (!sl[i].x_is_init) zf_by_shape[sl[i].shape_id].push_back(i);
+  }
+  std::vector<int> lo(nsh), zlo(nsh);
+  int pos = 0;
+  for (int s = 0; s < nsh; ++s) {
+    lo[s] = pos;
+    for (int i : by_shape[s]) h->h_list[pos++] = i;
+  }
+  for (int s = 0; s < nsh; ++s) {
+    zlo[s] = pos;
+    for (int i : zf_by_shape[s]) h->h_list[pos++] = i;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
+
+  const PrecKernels* pk = prec_kernels(h->fp64);
+  const int R = rows_of(h->fp64);
+  {
+    Params P = base_params(h, h->shapes[0], 0, h->d_list);
+    LAUNCH(pk->slice_init, P, dim3(ns), st);
+  }
+  // x^1 = A^H b for slices without a warm start (Section 3.3)
+  for (int s = 0; s < nsh; ++s) {
+    const int c = (int)zf_by_shape[s].size();
+    if (!c) continue;
+    const Shape& S = h->shapes[s];
+    Params P = base_params(h, S, s, h->d_list + zlo[s]);
+    LAUNCH(S.sk->col[COL_AHB], P, dim3(S.n / R, c), st);
+    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / R, c), st);
+  }
+  for (int it = 0; it <= Tmax; ++it) {
+    for (int s = 0; s < nsh; ++s) {
+      const int c = (int)by_shape[s].size();
+      if (!c) continue;
+      const Shape& S = h->shapes[s];
+      Params P = base_params(h, S, s, h->d_list + lo[s]);
+      P.Tmax = Tmax;
+      P.tau = tau;
+      if ((rc = launch_weights(h, S, P, c, st))) return rc;
+      if ((rc = launch_residual(h, S, P, c, st))) return rc;
+      LAUNCH(pk->outer_check, P, dim3(c), st);
+    }
+    HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->ev, st));
+    for (int s = 0; s < nsh; ++s) {
+      const int c = (int)by_shape[s].size();
+      if (!c) continue;
+      const Shape& S = h->shapes[s];
+      Params P = base_params(h, S, s, h->d_list + lo[s]);
+      if ((rc = launch_pcg(h, S, P, c, st))) return rc;
+    }
+    HIPCHK(hipEventSynchronize(h->ev));
+    int active = 0;
+    for (int i = 0; i < ns; ++i) active += h->h_state[i].active;
+    if (!active) break;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost));
+  int worst = FIRLS_OK;
+  for (int i = 0; i < ns; ++i) {
+    const SliceState& S = h->h_state[i];
+    firls_report& r = rep[i];
+    r.status = S.status;
+    r.outer_iters = S.outer;
+    r.pcg_iters = S.pcg;
+    r.converged = S.converged;
+    r.F = S.F;
+    r.F_eps = S.Fe;
+    r.data = S.data;
+    r.rel_change = S.rel;
+    if (S.status < 0 && (worst >= 0 || S.status < worst)) worst = S.status;
+    else if (worst >= 0 && S.status > worst) worst = S.status;
+  }
+  if (worst < 0) g_err = "a slice's objective became non-finite";
+  return worst;
+}
+
+int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
+  const int n = in.n;
+  if (!size_supported(n)) return fail(FIRLS_E_UNSUPPORTED, "image side " + std::to_string(n) + " is not built");
+  s.n = n;
+  s.psi = in.psi;
+  if (in.psi == FIRLS_PSI_HAAR) {
+    const int maxL = h->fp64 ? 3 : 4;
+    if (in.levels < 1) return fail(FIRLS_E_INVALID, "Haar levels must be >= 1");
+    if (in.levels > maxL) return fail(FIRLS_E_UNSUPPORTED, "Haar levels above " + std::to_string(maxL) + " are not built for this precision");
+    if (n % (1 << in.levels)) return fail(FIRLS_E_INVALID, "n must be a multiple of 2^levels");
+    s.L = in.levels;
+    s.n_coef = n * n;
+  } else if (in.psi == FIRLS_PSI_TV) {
+    if (n % TV_TC || n % TV_TR) return fail(FIRLS_E_UNSUPPORTED, "TV needs n to be a multiple of 32");
+    s.L = 0;
+    s.n_coef = 2 * n * n;
+  } else {
+    return fail(FIRLS_E_INVALID, "unknown psi");
+  }
+  // group map (caller order) -> internal order
+  std::vector<int32_t> ptr, idx;
+  if (in.n_groups == 0 && !in.group_ptr && !in.group_idx) {
+    const int N = n * n;
+    if (in.psi == FIRLS_PSI_HAAR) {
+      ptr.resize(N + 1);
+      idx.resize(N);
+      for (int i = 0; i <= N; ++i) ptr[i] = i;
+      for (int i = 0; i < N; ++i) idx[i] = i;
+    } else {
+      ptr.resize(N + 1);
+      idx.resize(2 * N);
+      for (int i = 0; i <= N; ++i) ptr[i] = 2 * i;
+      for (int i = 0; i < N; ++i) {
+        idx[2 * i] = i;
+        idx[2 * i + 1] = N + i;
+      }
+    }
+  } else {
+    if (in.n_groups <= 0 || !in.group_ptr || !in.group_idx) return fail(FIRLS_E_INVALID, "group map needs n_groups > 0 and both arrays");
+    if (in.group_ptr[0] != 0) return fail(FIRLS_E_INVALID, "group_ptr[0] must be 0");
+    ptr.assign(in.group_ptr, in.group_ptr + in.n_groups + 1);
+    for (int g = 0; g < in.n_groups; ++g)
+      if (ptr[g + 1] < ptr[g]) return fail(FIRLS_E_INVALID, "group_ptr must be non-decreasing");
+    idx.assign(in.group_idx, in.group_idx + ptr[in.n_groups]);
+    for (int32_t v : idx)
+      if (v < 0 || v >= s.n_coef) return fail(FIRLS_E_INVALID, "group_idx entry out of range");
+  }
+  s.n_groups = (int)ptr.size() - 1;
+  s.n_members = (int64_t)idx.size();
+  if ((s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many groups");
+  std::vector<int32_t> perm(s.n_coef);
+  if (s.psi == FIRLS_PSI_HAAR) {
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) perm[r * n + c] = haar_internal_index(n, s.L, r, c);
+  } else {
+    for (int i = 0; i < s.n_coef; ++i) perm[i] = i;
+  }
+  for (auto& v : idx) v = perm[v];
+  std::vector<int32_t> tptr(s.n_coef + 1, 0), tidx(idx.size());
+  for (int32_t v : idx) tptr[v + 1]++;
+  for (int i = 0; i < s.n_coef; ++i) tptr[i + 1] += tptr[i];
+  std::vector<int32_t> fillp(tptr.begin(), tptr.end() - 1);
+  for (int g = 0; g < s.n_groups; ++g)
+    for (int j = ptr[g]; j < ptr[g + 1]; ++j) tidx[fillp[idx[j]]++] = g;
+  auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
+    HIPCHK(hipMalloc(dst, std::max<size_t>(1, v.size()) * sizeof(int32_t)));
+    if (!v.empty()) HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return FIRLS_OK;
+  };
+  int rc;
+  if ((rc = up(&s.d_gptr, ptr)) || (rc = up(&s.d_gidx, idx)) || (rc = up(&s.d_tptr, tptr)) ||
+      (rc = up(&s.d_tidx, tidx)) || (rc = up(&s.d_perm, perm)))
+    return rc;
+  s.sk = size_kernels(h->fp64, n);
+  if (!s.sk) return fail(FIRLS_E_UNSUPPORTED, "no kernels for this size");
+  // twiddles exp(-2 pi i k / n), computed in FP64
+  for (auto& e : h->tw)
+    if (e.first == n) s.tw = e.second;
+  if (!s.tw) {
+    std::vector<double> w(2 * n);
+    for (int k = 0; k < n; ++k) {
+      const double a = 2.0 * M_PI * (double)k / (double)n;
+      w[2 * k] = std::cos(a);
+      w[2 * k + 1] = -std::sin(a);
+    }
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, n * h->elt));
+    if (h->fp64) {
+      HIPCHK(hipMemcpy(d, w.data(), n * h->elt, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(w.begin(), w.end());
+      HIPCHK(hipMemcpy(d, f.data(), n * h->elt, hipMemcpyHostToDevice));
+    }
+    h->tw.push_back({n, d});
+    s.tw = d;
+  }
+  return FIRLS_OK;
+}
+
+void destroy_shapes(firls_handle* h) {
+  for (auto& s : h->shapes) {
+    for (int32_t* p : {s.d_gptr, s.d_gidx, s.d_tptr, s.d_tidx, s.d_perm})
+      if (p) (void)hipFree(p);
+  }
+  h->shapes.clear();
+  for (auto& e : h->tw) (void)hipFree(e.second);
+  h->tw.clear();
+}
+
+// Single-slice operator set-up: slot 0 (and 1) of the batch arrays.
+int op_begin(firls_handle* h, hipStream_t st, int shape_id, int slots) {
+  if (shape_id < 0 || shape_id >= (int)h->shapes.size()) return fail(FIRLS_E_INVALID, "shape_id out of range");
+  const Shape& s = h->shapes[shape_id];
+  int rc = ensure_capacity(h, st, slots * h->slice_bytes(s), slots);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < slots; ++i) {
+    fill_desc(h, h->h_desc[i], s, i * h->slice_bytes(s), nullptr);
+    h->h_list[i] = i;
+  }
+  return FIRLS_OK;
+}
+
+int op_upload(firls_handle* h, hipStream_t st, int slots) {
+  HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * slots, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * slots, hipMemcpyHostToDevice, st));
+  return FIRLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* firls_last_error(void) { return g_err.c_str(); }
+
+int firls_create(const firls_config* cfg, firls_handle** out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(FIRLS_E_INVALID, "cfg and out must be non-null");
+  *out = nullptr;
+  if (cfg->n_shapes <= 0 || !cfg->shapes) return fail(FIRLS_E_INVALID, "need at least one shape");
+  if (cfg->max_slices <= 0) return fail(FIRLS_E_INVALID, "max_slices must be positive");
+  if (cfg->prec != FIRLS_FP32 && cfg->prec != FIRLS_FP64) return fail(FIRLS_E_INVALID, "prec must be FIRLS_FP32 or FIRLS_FP64");
+  if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps)) return fail(FIRLS_E_INVALID, "eps must be positive");
+  if (cfg->max_outer < 0) return fail(FIRLS_E_INVALID, "max_outer must be >= 0");
+  if (cfg->pcg_iters < 1 || cfg->pcg_iters > KMAX) return fail(FIRLS_E_INVALID, "pcg_iters must be in 1..64");
+  if (!(cfg->outer_tol >= 0.0)) return fail(FIRLS_E_INVALID, "outer_tol must be >= 0");
+  if (cfg->precond != FIRLS_PC_PAPER) return fail(FIRLS_E_UNSUPPORTED, "only the paper's preconditioner is built");
+  firls_handle* h = new firls_handle();
+  h->cfg = *cfg;
+  h->cfg.shapes = nullptr;
+  h->fp64 = cfg->prec == FIRLS_FP64;
+  h->elt = h->fp64 ? 16 : 8;
+  h->relt = h->fp64 ? 8 : 4;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(FIRLS_E_HIP, "no HIP device");
+  }
+  h->shapes.resize(cfg->n_shapes);
+  for (int i = 0; i < cfg->n_shapes; ++i) {
+    int rc = upload_shape(h, cfg->shapes[i], h->shapes[i]);
+    if (rc) {
+      std::string msg = "shape " + std::to_string(i) + ": " + g_err;
+      destroy_shapes(h);
+      delete h;
+      return fail(rc, msg);
+    }
+  }
+  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess) {
+    destroy_shapes(h);
+    delete h;
+    return fail(FIRLS_E_HIP, "event creation failed");
+  }
+  *out = h;
+  return FIRLS_OK;
+}
+
+int firls_destroy(firls_handle* h) {
+  if (!h) return FIRLS_OK;
+  (void)hipDeviceSynchronize();
+  free_batch(h);
+  destroy_shapes(h);
+  if (h->ev) (void)hipEventDestroy(h->ev);
+  delete h;
+  return FIRLS_OK;
+}
+
+size_t firls_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n) {
+  if (!h || shape_id < 0 || shape_id >= (int)h->shapes.size() || n < 0) return 0;
+  return (size_t)n * h->slice_bytes(h->shapes[shape_id]);
+}
+
+int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_report* report) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  g_err.clear();
+  return run_batch(h, (hipStream_t)stream, 1, slice, report, h->cfg.max_outer, h->cfg.outer_tol);
+}
+
+int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices,
+                        firls_report* reports) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  g_err.clear();
+  return run_batch(h, (hipStream_t)stream, n_slices, slices, reports, h->cfg.max_outer, h->cfg.outer_tol);
+}
+
+int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask, void* x) {
+  if (!h || !b || !mask || !x) return fail(FIRLS_E_INVALID, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = op_begin(h, st, shape_id, 1);
+  if (rc) return rc;
+  h->h_desc[0].b = b;
+  h->h_desc[0].mask = mask;
+  h->h_desc[0].x = x;
+  h->h_desc[0].lambda = 1.0;
+  if ((rc = op_upload(h, st, 1))) return rc;
+  const Shape& s = h->shapes[shape_id];
+  Params P = base_params(h, s, shape_id, h->d_list);
+  const int R = rows_of(h->fp64);
+  LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
+  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.n / R, 1), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return FIRLS_OK;
+}
+
+int firls_op_weights(firls_handle* h, void* stream, int32_t shape_id, const void* x, void* d_out) {
+  if (!h || !x || !d_out) return fail(FIRLS_E_INVALID, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = op_begin(h, st, shape_id, 1);
+  if (rc) return rc;
+  h->h_desc[0].x = const_cast<void*>(x);
+  h->h_desc[0].mask = static_cast<const uint8_t*>(x);  // any readable bytes: only rho uses it
+  h->h_desc[0].lambda = 1.0;
+  if ((rc = op_upload(h, st, 1))) return rc;
+  const Shape& s = h->shapes[shape_id];
+  Params P = base_params(h, s, shape_id, h->d_list);
+  P.out = d_out;
+  LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
+  if ((rc = launch_weights(h, s, P, 1, st))) return rc;
+  LAUNCH(prec_kernels(h->fp64)->export_d, P, dim3((s.n_coef + NT - 1) / NT, 1), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return FIRLS_OK;
+}
+
+int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8_t* mask, double lambda,
+                    const void* x_w, const void* p, void* q) {
+  if (!h || !mask || !x_w || !p || !q) return fail(FIRLS_E_INVALID, "null argument");
+  if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = op_begin(h, st, shape_id, 2);
+  if (rc) return rc;
+  SliceDesc& A = h->h_desc[0];
+  SliceDesc& B = h->h_desc[1];
+  A.x = const_cast<void*>(x_w);
+  A.mask = mask;
+  A.lambda = lambda;
+  B.d = A.d;
+  B.x = const_cast<void*>(p);
+  B.p = const_cast<void*>(p);
+  B.q = q;
+  B.mask = mask;
+  B.lambda = lambda;
+  if ((rc = op_upload(h, st, 2))) return rc;
+  const Shape& s = h->shapes[shape_id];
+  const int R = rows_of(h->fp64);
+  Params PA = base_params(h, s, shape_id, h->d_list);
+  Params PB = base_params(h, s, shape_id, h->d_list + 1);
+  LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
+  if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
+  PB.k = 0;
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.n / R, 1), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return FIRLS_OK;
+}
+
+int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint8_t* mask, double lambda,
+                     const void* x_w, const void* r, void* z) {
+  if (!h || !mask || !x_w || !r || !z) return fail(FIRLS_E_INVALID, "null argument");
+  if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = op_begin(h, st, shape_id, 2);
+  if (rc) return rc;
+  SliceDesc& A = h->h_desc[0];
+  SliceDesc& B = h->h_desc[1];
+  A.x = const_cast<void*>(x_w);
+  A.mask = mask;
+  A.lambda = lambda;
+  B.d = A.d;
+  B.r[0] = const_cast<void*>(r);
+  B.r[1] = const_cast<void*>(r);
+  B.p = z;
+  B.z = z;
+  B.mask = mask;
+  B.lambda = lambda;
+  if ((rc = op_upload(h, st, 2))) return rc;
+  const Shape& s = h->shapes[shape_id];
+  const int R = rows_of(h->fp64);
+  Params PA = base_params(h, s, shape_id, h->d_list);
+  Params PB = base_params(h, s, shape_id, h->d_list + 1);
+  LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
+  if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
+  PB.k = 0;
+  if (s.psi == PSI_HAAR) LAUNCH(s.sk->rowfwd[RF_PCG_HAAR], PB, dim3(s.n / R, 1), st);
+  else LAUNCH(prec_kernels(h->fp64)->update_tv[UP_INIT], PB, dim3(PB.nrz, 1), st);
+  HIPCHK(hipStreamSynchronize(st));
+  return FIRLS_OK;
+}
+
+int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask,
+                       double lambda, const void* x, double* out3) {
+  if (!h || !b || !mask || !x || !out3) return fail(FIRLS_E_INVALID, "null argument");
+  if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = op_begin(h, st, shape_id, 1);
+  if (rc) return rc;
+  SliceDesc& A = h->h_desc[0];
+  A.x = const_cast<void*>(x);
+  A.b = b;
+  A.mask = mask;
+  A.lambda = lambda;
+  if ((rc = op_upload(h, st, 1))) return rc;
+  const Shape& s = h->shapes[shape_id];
+  const int R = rows_of(h->fp64);
+  Params P = base_params(h, s, shape_id, h->d_list);
+  P.Tmax = 0;
+  P.tau = 0.0;
+  LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
+  if ((rc = launch_weights(h, s, P, 1, st))) return rc;
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / R, 1), st);
+  LAUNCH(prec_kernels(h->fp64)->outer_check, P, dim3(1), st);
+  HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out3[0] = h->h_state[0].Fe;
+  out3[1] = h->h_state[0].F;
+  out3[2] = h->h_state[0].data;
+  return FIRLS_OK;
+}
+
+int firls_op_outer_step(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask,
+                        double lambda, void* x) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  firls_slice sl{};
+  sl.shape_id = shape_id;
+  sl.x_is_init = 1;
+  sl.lambda = lambda;
+  sl.b = b;
+  sl.mask = mask;
+  sl.x = x;
+  firls_report rep{};
+  int rc = run_batch(h, (hipStream_t)stream, 1, &sl, &rep, 1, 0.0);
+  return rc < 0 ? rc : FIRLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Precision-only kernels, per-slice bookkeeping kernels and the launcher
+// registry.
+#include <mutex>
+
+#include "firls_inst.h"
+
+namespace firls {
+
+// rho = (number of sampled entries) / n^2, the mean (indeed every entry) of
+// diag(A^H A) for the unitary F (Section 5.4), and a fresh outer-loop state.
+__global__ __launch_bounds__(NT) void k_slice_init(Params P) {
+  __shared__ double red[NT / 64];
+  const int s = P.list[blockIdx.x];
+  const SliceDesc& D = P.desc[s];
+  const int total = D.n * D.n;
+  double cnt = 0.0;
+  for (int i = threadIdx.x; i < total; i += NT) cnt += D.mask[i] != 0 ? 1.0 : 0.0;
+  cnt = block_sum(cnt, red);
+  if (threadIdx.x == 0) {
+    SliceState& S = P.state[s];
+    S.rho = cnt / (double)total;
+    S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
+    S.active = 1;
+    S.outer = S.pcg = S.status = S.converged = S.evals = 0;
+  }
+}
+
+// Objective of the current x and the outer stopping rule.  F_eps = data +
+// lambda sum sqrt(s_g + eps); stop when (F_eps^{prev} - F_eps) <= tau F_eps
+// after the first evaluation, or once Tmax solves are done; otherwise count
+// the solve that follows.
+__global__ __launch_bounds__(NT) void k_outer_check(Params P) {
+  __shared__ double red[NT / 64];
+  const int s = P.list[blockIdx.x];
+  SliceState& S = P.state[s];
+  if (!S.active) return;
+  const SliceDesc& D = P.desc[s];
+  const double data = slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
+  const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg, red);
+  const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg, red);
+  if (threadIdx.x != 0) return;
+  const double Fe = data + D.lambda * re;
+  const double F = data + D.lambda * r0;
+  const bool first = S.evals == 0;
+  const double prev = S.Fe;
+  S.Fe_prev = first ? Fe : prev;
+  S.rel = first ? 0.0 : (prev - Fe) / Fe;
+  S.Fe = Fe;
+  S.F = F;
+  S.data = data;
+  S.evals += 1;
+  if (!isfinite(Fe)) {
+    S.status = -5;  // FIRLS_E_NONFINITE
+    S.active = 0;
+  } else if (!first && P.tau > 0.0 && (prev - Fe) <= P.tau * Fe) {
+    S.converged = 1;
+    S.active = 0;
+  } else if (S.outer >= P.Tmax) {
+    if (P.tau > 0.0) S.status = 1;  // FIRLS_W_MAXITER
+    S.active = 0;
+  } else {
+    S.outer += 1;
+    S.pcg += P.K;
+  }
+}
+
+// d in the caller's coefficient order: out[u] = d[perm[u]].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_export_d(Params P) {
+  const int s = P.list[blockIdx.y];
+  const SliceDesc& D = P.desc[s];
+  const T* d = static_cast<const T*>(D.d);
+  T* out = static_cast<T*>(P.out);
+  const int u = blockIdx.x * NT + threadIdx.x;
+  if (u < P.shape.n_coef) out[u] = d[P.shape.perm[u]];
+}
+
+template <class K>
+hipError_t launch_static(K kern, const Params& P, dim3 g, hipStream_t st) {
+  hipLaunchKernelGGL(kern, g, dim3(NT), 0, st, P);
+  return hipGetLastError();
+}
+
+template <typename T> hipError_t L_psi_sq_tv(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_psi_sq_tv<T>, P, g, st); }
+template <typename T> hipError_t L_group_w(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_group_w<T>, P, g, st); }
+template <typename T> hipError_t L_group_d(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_group_d<T>, P, g, st); }
+template <typename T, int M> hipError_t L_update_tv(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_update_tv<T, M>, P, g, st); }
+template <typename T> hipError_t L_export_d(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_export_d<T>, P, g, st); }
+hipError_t L_slice_init(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_slice_init, P, g, st); }
+hipError_t L_outer_check(const Params& P, dim3 g, hipStream_t st) { return launch_static(k_outer_check, P, g, st); }
+
+template <typename T>
+PrecKernels make_prec() {
+  PrecKernels k{};
+  k.psi_sq_tv = L_psi_sq_tv<T>;
+  k.group_w = L_group_w<T>;
+  k.group_d = L_group_d<T>;
+  k.update_tv[UP_INIT] = L_update_tv<T, UP_INIT>;
+  k.update_tv[UP_STEP] = L_update_tv<T, UP_STEP>;
+  k.export_d = L_export_d<T>;
+  k.slice_init = L_slice_init;
+  k.outer_check = L_outer_check;
+  return k;
+}
+
+#define FIRLS_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define FIRLS_DECL(N) SizeKernels make_size_f32_##N(); SizeKernels make_size_f64_##N();
+FIRLS_SIZES(FIRLS_DECL)
+#undef FIRLS_DECL
+
+namespace {
+struct Tables {
+  SizeKernels f32[10], f64[10];
+  PrecKernels p32, p64;
+};
+constexpr int kSizes[10] = {16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+std::once_flag g_once;
+Tables* g_tables = nullptr;
+
+void build_tables() {
+  static Tables t;
+  int i = 0;
+#define FIRLS_FILL(N)                  \
+  t.f32[i] = make_size_f32_##N();      \
+  t.f64[i] = make_size_f64_##N();      \
+  ++i;
+  FIRLS_SIZES(FIRLS_FILL)
+#undef FIRLS_FILL
+  t.p32 = make_prec<float>();
+  t.p64 = make_prec<double>();
+  g_tables = &t;
+}
+
+int size_index(int n) {
+  for (int i = 0; i < 10; ++i)
+    if (kSizes[i] == n) return i;
+  return -1;
+}
+}  // namespace
+
+bool size_supported(int n) { return size_index(n) >= 0; }
+
+const SizeKernels* size_kernels(bool fp64, int n) {
+  std::call_once(g_once, build_tables);
+  const int i = size_index(n);
+  if (i < 0) return nullptr;
+  return fp64 ? &g_tables->f64[i] : &g_tables->f32[i];
+}
+
+const PrecKernels* prec_kernels(bool fp64) {
+  std::call_once(g_once, build_tables);
+  return fp64 ? &g_tables->p64 : &g_tables->p32;
+}
+
+}  // namespace firls

@@ -1,0 +1,358 @@
+// Device building blocks: complex arithmetic, small DFTs, the LDS-staged
+// mixed-radix FFT used by the row and column passes, tile-local Haar in
+// LDS, and deterministic FP64 workgroup reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "firls_types.h"
+
+namespace firls {
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { return cplx<T>{a, b}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cplx<T> operator*(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T> __device__ __forceinline__ double cabs2(cplx<T> a) {
+  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+template <typename T> __device__ __forceinline__ double cdot(cplx<T> a, cplx<T> b) {  // Re(conj(a) b)
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+
+// cos(2 pi e / 16) and sin(2 pi e / 16), e = 0..15.
+__device__ constexpr double kC16[16] = {
+    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977,
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674};
+__device__ constexpr double kS16[16] = {
+    0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674,
+    1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+    0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674,
+    -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508977};
+
+// exp(-+ 2 pi i e / R) for R dividing 16 (forward: minus sign).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ cplx<T> unit_root(int e) {
+  const int k = (e * (16 / R)) & 15;
+  const T c = (T)kC16[k];
+  const T s = (T)kS16[k];
+  return INV ? cplx<T>{c, s} : cplx<T>{c, -s};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers: X[k] = sum_r v[r] exp(-+2 pi i r k / R).
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool INV> struct SmallDFT;
+
+template <typename T, bool INV> struct SmallDFT<T, 2, INV> {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T, bool INV> struct SmallDFT<T, 3, INV> {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
+    const T h = (T)0.86602540378443865;  // sqrt(3) / 2
+    cplx<T> a = v[0], s = v[1] + v[2], d = v[1] - v[2];
+    cplx<T> m = a - s * (T)0.5;
+    // forward: X1 = m - i h d, X2 = m + i h d; inverse swaps the signs
+    cplx<T> ihd = INV ? cplx<T>{-h * d.y, h * d.x} : cplx<T>{h * d.y, -h * d.x};
+    v[0] = a + s;
+    v[1] = m + ihd;
+    v[2] = m - ihd;
+  }
+};
+
+template <typename T, bool INV> struct SmallDFT<T, 4, INV> {
+  __device__ __forceinline__ static void run(cplx<T>* v) {
+    cplx<T> s0 = v[0] + v[2], d0 = v[0] - v[2];
+    cplx<T> s1 = v[1] + v[3], d1 = v[1] - v[3];
+    // forward multiplies d1 by -i, inverse by +i
+    cplx<T> jd1 = INV ? cplx<T>{-d1.y, d1.x} : cplx<T>{d1.y, -d1.x};
+    v[0] = s0 + s1;
+    v[2] = s0 - s1;
+    v[1] = d0 + jd1;
+    v[3] = d0 - jd1;
+  }
+};
+
+// R = A * B: input n = m + A s, output k = k1 + B k2;
+// X[k1 + B k2] = sum_m w_A^{m k2} ( w_R^{m k1} sum_s v[m + A s] w_B^{s k1} ).
+template <typename T, int A, int B, bool INV>
+__device__ __forceinline__ void dft_composite(cplx<T>* v) {
+  constexpr int R = A * B;
+  cplx<T> y[A][B];
+#pragma unroll
+  for (int m = 0; m < A; ++m) {
+    cplx<T> tmp[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) tmp[s] = v[m + A * s];
+    SmallDFT<T, B, INV>::run(tmp);
+#pragma unroll
+    for (int k1 = 0; k1 < B; ++k1) y[m][k1] = (m * k1 == 0) ? tmp[k1] : cmul(tmp[k1], unit_root<T, R, INV>(m * k1));
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < B; ++k1) {
+    cplx<T> tmp[A];
+#pragma unroll
+    for (int m = 0; m < A; ++m) tmp[m] = y[m][k1];
+    SmallDFT<T, A, INV>::run(tmp);
+#pragma unroll
+    for (int k2 = 0; k2 < A; ++k2) v[k1 + B * k2] = tmp[k2];
+  }
+}
+
+template <typename T, bool INV> struct SmallDFT<T, 8, INV> {
+  __device__ __forceinline__ static void run(cplx<T>* v) { dft_composite<T, 2, 4, INV>(v); }
+};
+template <typename T, bool INV> struct SmallDFT<T, 16, INV> {
+  __device__ __forceinline__ static void run(cplx<T>* v) { dft_composite<T, 4, 4, INV>(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Radix plans.  Forward stages use R0, R1, R2 in order; the inverse uses the
+// reverse order (a Stockham pass accepts any order of the factors).
+// ---------------------------------------------------------------------------
+template <int N> struct Plan;
+template <> struct Plan<16>  { static constexpr int S = 1, R0 = 16, R1 = 1,  R2 = 1; };
+template <> struct Plan<32>  { static constexpr int S = 2, R0 = 8,  R1 = 4,  R2 = 1; };
+template <> struct Plan<48>  { static constexpr int S = 2, R0 = 16, R1 = 3,  R2 = 1; };
+template <> struct Plan<64>  { static constexpr int S = 2, R0 = 16, R1 = 4,  R2 = 1; };
+template <> struct Plan<96>  { static constexpr int S = 3, R0 = 16, R1 = 2,  R2 = 3; };
+template <> struct Plan<128> { static constexpr int S = 2, R0 = 16, R1 = 8,  R2 = 1; };
+template <> struct Plan<192> { static constexpr int S = 3, R0 = 16, R1 = 4,  R2 = 3; };
+template <> struct Plan<256> { static constexpr int S = 2, R0 = 16, R1 = 16, R2 = 1; };
+template <> struct Plan<384> { static constexpr int S = 3, R0 = 16, R1 = 8,  R2 = 3; };
+template <> struct Plan<512> { static constexpr int S = 3, R0 = 16, R1 = 16, R2 = 2; };
+
+// LDS layout of LINES lines of N complex values: one pad slot every 16
+// values and an odd line stride keep both line-major and position-major
+// lane orders free of heavy bank conflicts.
+template <int N> struct LdsLayout {
+  static constexpr int LS = N + N / 16 + 1;
+  __device__ __forceinline__ static int at(int line, int pos) { return line * LS + pos + (pos >> 4); }
+};
+
+enum Map : int { ROWMAP = 0, COLMAP = 1 };
+
+// One Stockham stage (Govindaraju et al. formulation): butterfly j of a
+// line reads v[r] = in[j + r N/R], applies twiddles w_{NS R}^{(j mod NS) r},
+// takes a radix-R DFT and writes out[(j / NS) NS R + j mod NS + r NS].
+template <typename T, int N, int R, int NS, int LINES, int MAP, bool INV>
+struct Stage {
+  static constexpr int NB = N / R;
+  static constexpr int TOT = LINES * NB;
+  static constexpr int ITER = (TOT + NT - 1) / NT;
+
+  __device__ __forceinline__ static void decode(int b, int& line, int& j) {
+    if (MAP == ROWMAP) { line = b / NB; j = b - line * NB; }
+    else { j = b / LINES; line = b - j * LINES; }
+  }
+
+  template <class Src>
+  __device__ __forceinline__ static void load(cplx<T> (&v)[ITER][R], Src& src, const cplx<T>* tw) {
+#pragma unroll
+    for (int i = 0; i < ITER; ++i) {
+      const int b = threadIdx.x + i * NT;
+      if (TOT % NT != 0 && b >= TOT) continue;
+      int line, j;
+      decode(b, line, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src(line, j + r * NB);
+      if (NS > 1) {
+        const int step = (j % NS) * (N / (NS * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cplx<T> w = tw[r * step];
+          if (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      SmallDFT<T, R, INV>::run(v[i]);
+    }
+  }
+
+  template <class Dst>
+  __device__ __forceinline__ static void store(cplx<T> (&v)[ITER][R], Dst& dst) {
+#pragma unroll
+    for (int i = 0; i < ITER; ++i) {
+      const int b = threadIdx.x + i * NT;
+      if (TOT % NT != 0 && b >= TOT) continue;
+      int line, j;
+      decode(b, line, j);
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst(line, base + r * NS, v[i][r]);
+    }
+  }
+};
+
+template <typename T, int N>
+struct LdsIO {
+  cplx<T>* buf;
+  __device__ __forceinline__ cplx<T> operator()(int line, int pos) const { return buf[LdsLayout<N>::at(line, pos)]; }
+  __device__ __forceinline__ void operator()(int line, int pos, cplx<T> v) const { buf[LdsLayout<N>::at(line, pos)] = v; }
+};
+
+// FFT (INV = false: exp(-...), unnormalised) of LINES lines of length N.
+// The first stage reads src(line, pos), the last writes dst(line, pos, v);
+// intermediate stages go through ``lds`` (LINES x LdsLayout<N>::LS).
+// Barriers bracket every LDS phase, so src / dst may themselves be LDS.
+template <typename T, int N, int LINES, int MAP, bool INV, class Src, class Dst>
+__device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src src, Dst dst) {
+  using P = Plan<N>;
+  constexpr int A0 = INV ? (P::S == 3 ? P::R2 : (P::S == 2 ? P::R1 : P::R0)) : P::R0;
+  constexpr int A1 = INV ? (P::S == 3 ? P::R1 : P::R0) : P::R1;
+  constexpr int A2 = INV ? P::R0 : P::R2;
+  LdsIO<T, N> io{lds};
+  using S0 = Stage<T, N, A0, 1, LINES, MAP, INV>;
+  cplx<T> v0[S0::ITER][A0];
+  S0::load(v0, src, tw);
+  __syncthreads();
+  if constexpr (P::S == 1) {
+    S0::store(v0, dst);
+    __syncthreads();
+  } else {
+    S0::store(v0, io);
+    __syncthreads();
+    using S1 = Stage<T, N, A1, A0, LINES, MAP, INV>;
+    cplx<T> v1[S1::ITER][A1];
+    S1::load(v1, io, tw);
+    __syncthreads();
+    if constexpr (P::S == 2) {
+      S1::store(v1, dst);
+      __syncthreads();
+    } else {
+      S1::store(v1, io);
+      __syncthreads();
+      using S2 = Stage<T, N, A2, A0 * A1, LINES, MAP, INV>;
+      cplx<T> v2[S2::ITER][A2];
+      S2::load(v2, io, tw);
+      __syncthreads();
+      S2::store(v2, dst);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-local orthonormal Haar on a band of ROWS x N values in LDS.
+// Every aligned 2^L x 2^L tile is transformed on its own: an L-level Haar
+// of the whole image only mixes pixels inside such tiles.  Within a tile
+// the coefficients are kept in the tile's own Mallat arrangement, so the
+// library's coefficient layout is the image layout with each tile replaced
+// by its transform.  One level maps a 2x2 block [a b; c d] of the current
+// approximation (side s) to (a+b+c+d)/2 at (i, j), (a-b+c-d)/2 at
+// (i, j + s/2), (a+b-c-d)/2 at (i + s/2, j) and (a-b-c+d)/2 at
+// (i + s/2, j + s/2); the matrix is symmetric and its own inverse.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int ROWS, bool INV>
+__device__ __forceinline__ void haar_tiles(cplx<T>* lds, int L) {
+  using Lay = LdsLayout<N>;
+  const int tsz = 1 << L;
+  const int tiles_x = N >> L;
+  for (int it = 0; it < L; ++it) {
+    const int lev = INV ? (L - it) : (it + 1);     // 1 = finest
+    const int s = tsz >> (lev - 1);                // side of the block being split
+    const int h = s >> 1;
+    const int per_tile = h * h;
+    const int total = (ROWS >> L) * tiles_x * per_tile;
+    constexpr int MAXB = (ROWS * N / 4 + NT - 1) / NT;
+    cplx<T> a[MAXB], b[MAXB], c[MAXB], d[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int blk = threadIdx.x + i * NT;
+      if (blk >= total) break;
+      const int tile = blk / per_tile, w = blk - tile * per_tile;
+      const int bi = w / h, bj = w - bi * h;
+      const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+      const int r0 = ty * tsz, c0 = tx * tsz;
+      if (!INV) {
+        a[i] = lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj)];
+        b[i] = lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj + 1)];
+        c[i] = lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj)];
+        d[i] = lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj + 1)];
+      } else {
+        a[i] = lds[Lay::at(r0 + bi, c0 + bj)];
+        b[i] = lds[Lay::at(r0 + bi, c0 + h + bj)];
+        c[i] = lds[Lay::at(r0 + h + bi, c0 + bj)];
+        d[i] = lds[Lay::at(r0 + h + bi, c0 + h + bj)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int blk = threadIdx.x + i * NT;
+      if (blk >= total) break;
+      const int tile = blk / per_tile, w = blk - tile * per_tile;
+      const int bi = w / h, bj = w - bi * h;
+      const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+      const int r0 = ty * tsz, c0 = tx * tsz;
+      const T half = (T)0.5;
+      cplx<T> apb = a[i] + b[i], amb = a[i] - b[i], cpd = c[i] + d[i], cmd = c[i] - d[i];
+      cplx<T> o0 = (apb + cpd) * half, o1 = (amb + cmd) * half;
+      cplx<T> o2 = (apb - cpd) * half, o3 = (amb - cmd) * half;
+      if (!INV) {
+        lds[Lay::at(r0 + bi, c0 + bj)] = o0;
+        lds[Lay::at(r0 + bi, c0 + h + bj)] = o1;
+        lds[Lay::at(r0 + h + bi, c0 + bj)] = o2;
+        lds[Lay::at(r0 + h + bi, c0 + h + bj)] = o3;
+      } else {
+        lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj)] = o0;
+        lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj + 1)] = o1;
+        lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj)] = o2;
+        lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj + 1)] = o3;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  ``red`` is a
+// __shared__ double[NT / 64] scratch.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Sum of ``count`` partials of a slot, in a fixed order.
+__device__ __forceinline__ double slot_sum(const double* slot, int count, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += NT) v += slot[i];
+  return block_sum(v, red);
+}
+
+__device__ __forceinline__ const double* slot_ptr(const SliceDesc& D, int s) { return D.parts + (size_t)s * PMAX; }
+__device__ __forceinline__ double* slot_wptr(const SliceDesc& D, int s) { return D.parts + (size_t)s * PMAX; }
+
+}  // namespace firls

@@ -1,0 +1,75 @@
+// Launchers for one (precision, size) instantiation (internal).
+#pragma once
+#include "firls_kernels.h"
+#include "firls_registry.h"
+
+namespace firls {
+
+template <typename T, int N>
+constexpr size_t lds_bytes() {
+  return (size_t)Geo<T>::ROWS * LdsLayout<N>::LS * sizeof(cplx<T>);
+}
+
+template <class K>
+hipError_t launch_dyn(K kern, size_t lds, const Params& P, dim3 g, hipStream_t st) {
+  hipLaunchKernelGGL(kern, g, dim3(NT), lds, st, P);
+  return hipGetLastError();
+}
+
+#define FIRLS_DYN_LAUNCHER(NAME, KERNEL)                                       \
+  template <typename T, int N, int M>                                          \
+  hipError_t NAME(const Params& P, dim3 g, hipStream_t st) {                   \
+    return launch_dyn(KERNEL<T, N, M>, lds_bytes<T, N>(), P, g, st);           \
+  }
+FIRLS_DYN_LAUNCHER(L_rowfwd, k_rowfwd)
+FIRLS_DYN_LAUNCHER(L_col, k_col)
+FIRLS_DYN_LAUNCHER(L_rowinv, k_rowinv)
+FIRLS_DYN_LAUNCHER(L_update_haar, k_update_haar)
+#undef FIRLS_DYN_LAUNCHER
+
+template <typename T, int N>
+hipError_t L_psi_sq_haar(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_psi_sq_haar<T, N>, lds_bytes<T, N>(), P, g, st);
+}
+
+template <class K>
+void allow_lds(K kern, size_t bytes) {
+  if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int N>
+SizeKernels make_size_kernels() {
+  const size_t b = lds_bytes<T, N>();
+  allow_lds(k_rowfwd<T, N, RF_PLAIN>, b);
+  allow_lds(k_rowfwd<T, N, RF_PCG_HAAR>, b);
+  allow_lds(k_rowfwd<T, N, RF_PCG_Z>, b);
+  allow_lds(k_col<T, N, COL_SP>, b);
+  allow_lds(k_col<T, N, COL_R0>, b);
+  allow_lds(k_col<T, N, COL_AHB>, b);
+  allow_lds(k_rowinv<T, N, RI_PLAIN>, b);
+  allow_lds(k_rowinv<T, N, RI_SP_HAAR>, b);
+  allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
+  allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
+  allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
+  allow_lds(k_psi_sq_haar<T, N>, b);
+  allow_lds(k_update_haar<T, N, UP_INIT>, b);
+  allow_lds(k_update_haar<T, N, UP_STEP>, b);
+  SizeKernels k{};
+  k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;
+  k.rowfwd[RF_PCG_HAAR] = L_rowfwd<T, N, RF_PCG_HAAR>;
+  k.rowfwd[RF_PCG_Z] = L_rowfwd<T, N, RF_PCG_Z>;
+  k.col[COL_SP] = L_col<T, N, COL_SP>;
+  k.col[COL_R0] = L_col<T, N, COL_R0>;
+  k.col[COL_AHB] = L_col<T, N, COL_AHB>;
+  k.rowinv[RI_PLAIN] = L_rowinv<T, N, RI_PLAIN>;
+  k.rowinv[RI_SP_HAAR] = L_rowinv<T, N, RI_SP_HAAR>;
+  k.rowinv[RI_SP_TV] = L_rowinv<T, N, RI_SP_TV>;
+  k.rowinv[RI_R0_HAAR] = L_rowinv<T, N, RI_R0_HAAR>;
+  k.rowinv[RI_R0_TV] = L_rowinv<T, N, RI_R0_TV>;
+  k.psi_sq_haar = L_psi_sq_haar<T, N>;
+  k.update_haar[UP_INIT] = L_update_haar<T, N, UP_INIT>;
+  k.update_haar[UP_STEP] = L_update_haar<T, N, UP_STEP>;
+  return k;
+}
+
+}  // namespace firls

@@ -1,0 +1,448 @@
+// FIRLS kernels (templated; instantiated per precision and image size).
+//
+// One PCG iteration on a batch of slices of one shape is four launches:
+//   k_rowfwd  : z = P^{-1} r (Haar: Phi^T((Phi r)/(rho + lambda d)), eq. 17;
+//               TV: read z), p = z + beta p, then row FFTs of p -> t
+//   k_col     : column FFT, times mask / n^2, column inverse FFT (t in place)
+//   k_rowinv  : row inverse FFTs of t plus lambda Psi^T diag(d) Psi p -> q,
+//               and the partials of <p, q>
+//   k_update  : alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, and the
+//               partials of the next <r, z> (TV: z = M^{-1} r in red-black
+//               order, the factors of eqs. 40-43)
+// so q = S p with S of eq. (15) / eq. (39).  The FP64 partial sums of each
+// inner product are written one per workgroup and summed, in index order,
+// by every workgroup that needs the scalar.
+#pragma once
+#include "firls_dev.h"
+
+namespace firls {
+
+template <typename T> struct Geo {
+  static constexpr int ROWS = sizeof(T) == 4 ? 16 : 8;   // band height of row passes
+  static constexpr int COLS = ROWS;                      // strip width of column passes
+};
+
+#define FIRLS_SLICE_PROLOGUE(idx)                 \
+  const int s_ = P.list[idx];                    \
+  if (!P.state[s_].active) return;               \
+  const SliceDesc& D = P.desc[s_];
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// lambda (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c), periodic forward
+// differences (D1 v)[r,c] = v[r+1,c] - v[r,c], (D2 v)[r,c] = v[r,c+1] - v[r,c].
+template <typename T>
+__device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, const T* w2, int n, int r, int c) {
+  const int rp = r + 1 == n ? 0 : r + 1, rm = r == 0 ? n - 1 : r - 1;
+  const int cp = c + 1 == n ? 0 : c + 1, cm = c == 0 ? n - 1 : c - 1;
+  const cplx<T> v0 = v[r * n + c];
+  const T a = w1[r * n + c], b = w1[rm * n + c], e = w2[r * n + c], f = w2[r * n + cm];
+  return (v0 - v[rp * n + c]) * a + (v0 - v[rm * n + c]) * b + (v0 - v[r * n + cp]) * e + (v0 - v[r * n + cm]) * f;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
+  constexpr int ROWS = Geo<T>::ROWS;
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  const C* tw = static_cast<const C*>(P.tw);
+  C* t = static_cast<C*>(D.t) + off;
+  auto gdst = [&](int l, int q, C v) { t[l * N + q] = v; };
+  if constexpr (MODE == RF_PLAIN) {
+    const C* x = static_cast<const C*>(D.x) + off;
+    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
+  } else {
+    double beta = 0.0;
+    if (P.k > 0) {
+      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz, red);
+      beta = rzo > 0.0 ? rz / rzo : 0.0;
+    }
+    const T bt = (T)beta;
+    C* p = static_cast<C*>(D.p) + off;
+    if constexpr (MODE == RF_PCG_HAAR) {
+      const C* r = static_cast<const C*>(D.r[0]) + off;
+      const T* d = static_cast<const T*>(D.d) + off;
+      const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = r[i];
+      __syncthreads();
+      haar_tiles<T, N, ROWS, false>(lds, P.L);
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
+        const int a = Lay::at(i / N, i % N);
+        lds[a] = lds[a] * ((T)1 / (rho + lam * d[i]));
+      }
+      __syncthreads();
+      haar_tiles<T, N, ROWS, true>(lds, P.L);
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
+        const int a = Lay::at(i / N, i % N);
+        const C pn = P.k > 0 ? lds[a] + p[i] * bt : lds[a];   // p is not read at k = 0
+        p[i] = pn;
+        lds[a] = pn;
+      }
+    } else {
+      const C* z = static_cast<const C*>(D.z) + off;
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
+        const C pn = P.k > 0 ? z[i] + p[i] * bt : z[i];
+        p[i] = pn;
+        lds[Lay::at(i / N, i % N)] = pn;
+      }
+    }
+    __syncthreads();
+    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_col(Params P) {
+  constexpr int COLS = Geo<T>::COLS;
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const int col0 = blockIdx.x * COLS;
+  const C* tw = static_cast<const C*>(P.tw);
+  C* t = static_cast<C*>(D.t);
+  const uint8_t* m = D.mask;
+  auto gsrc = [&](int c, int row) { return t[(size_t)row * N + col0 + c]; };
+  auto gdst = [&](int c, int row, C v) { t[(size_t)row * N + col0 + c] = v; };
+  LdsIO<T, N> io{lds};
+  const T sn = (T)1 / (T)N;
+  if constexpr (MODE == COL_SP) {
+    const T sc = sn * sn;
+    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+      lds[Lay::at(c, row)] = m[(size_t)row * N + col0 + c] ? v * sc : C{(T)0, (T)0};
+    });
+    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+  } else if constexpr (MODE == COL_R0) {
+    // k = (F x) at the sampled entries; keep m (b - k) / n for the inverse
+    // and accumulate 1/2 ||m F x - b||^2.
+    const C* b = static_cast<const C*>(D.b);
+    double acc = 0.0;
+    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+      const size_t g = (size_t)row * N + col0 + c;
+      C u{(T)0, (T)0};
+      if (m[g]) {
+        u = b[g] - v * sn;
+        acc += cabs2(u);
+        u = u * sn;
+      }
+      lds[Lay::at(c, row)] = u;
+    });
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_DATA)[blockIdx.x] = 0.5 * tot;
+    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+  } else {
+    const C* b = static_cast<const C*>(D.b);
+    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, [&](int c, int row) {
+      const size_t g = (size_t)row * N + col0 + c;
+      return m[g] ? b[g] * sn : C{(T)0, (T)0};
+    }, gdst);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_rowinv(Params P) {
+  constexpr int ROWS = Geo<T>::ROWS;
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const int row0 = blockIdx.x * ROWS;
+  const size_t off = (size_t)row0 * N;
+  const C* tw = static_cast<const C*>(P.tw);
+  const C* tin = static_cast<const C*>(D.t) + off;
+  auto gsrc = [&](int l, int q) { return tin[l * N + q]; };
+  if constexpr (MODE == RI_PLAIN) {
+    C* x = static_cast<C*>(D.x) + off;
+    fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C v) { x[l * N + q] = v; });
+  } else {
+    constexpr bool SP = (MODE == RI_SP_HAAR || MODE == RI_SP_TV);
+    constexpr bool HAAR = (MODE == RI_SP_HAAR || MODE == RI_R0_HAAR);
+    // v: the vector the regulariser acts on; out: q (S p) or r (A^H b - S x)
+    const C* vfull = static_cast<const C*>(SP ? D.p : D.x);
+    const C* v = vfull + off;
+    C* out = static_cast<C*>(SP ? D.q : D.r[0]) + off;
+    const T lam = (T)D.lambda;
+    const T sgn = SP ? (T)1 : (T)-1;
+    double acc = 0.0;
+    if constexpr (HAAR) {
+      const T* d = static_cast<const T*>(D.d) + off;
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = v[i];
+      __syncthreads();
+      haar_tiles<T, N, ROWS, false>(lds, P.L);
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
+        const int a = Lay::at(i / N, i % N);
+        lds[a] = lds[a] * (lam * d[i]);
+      }
+      __syncthreads();
+      haar_tiles<T, N, ROWS, true>(lds, P.L);
+      for (int i = threadIdx.x; i < ROWS * N; i += NT) out[i] = lds[Lay::at(i / N, i % N)] * sgn;
+      __syncthreads();
+      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
+        const int i = l * N + q;
+        const C o = out[i] + val;
+        out[i] = o;
+        if (SP) acc += cdot(v[i], o);
+      });
+    } else {
+      const T* w1 = static_cast<const T*>(D.d);
+      const T* w2 = w1 + (size_t)N * N;
+      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
+        const int i = l * N + q;
+        const C o = val + tv_normal<T>(vfull, w1, w2, N, row0 + l, q) * (lam * sgn);
+        out[i] = o;
+        if (SP) acc += cdot(v[i], o);
+      });
+    }
+    if constexpr (SP) {
+      const double tot = block_sum(acc, red);
+      if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[blockIdx.x] = tot;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// |Phi x|^2 per coefficient (Haar, tile-major layout).
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
+  constexpr int ROWS = Geo<T>::ROWS;
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  const C* x = static_cast<const C*>(D.x) + off;
+  T* sq = static_cast<T*>(D.sq) + off;
+  for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = x[i];
+  __syncthreads();
+  haar_tiles<T, N, ROWS, false>(lds, P.L);
+  for (int i = threadIdx.x; i < ROWS * N; i += NT) sq[i] = (T)cabs2(lds[Lay::at(i / N, i % N)]);
+}
+
+// Haar PCG update: alpha step (UP_STEP) and <r, z> = sum |Phi r|^2 / (rho + lambda d).
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_update_haar(Params P) {
+  constexpr int ROWS = Geo<T>::ROWS;
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  C* r = static_cast<C*>(D.r[0]) + off;
+  const T* d = static_cast<const T*>(D.d) + off;
+  if constexpr (MODE == UP_STEP) {
+    const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+    const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+    const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
+    C* x = static_cast<C*>(D.x) + off;
+    const C* p = static_cast<const C*>(D.p) + off;
+    const C* q = static_cast<const C*>(D.q) + off;
+    for (int i = threadIdx.x; i < ROWS * N; i += NT) {
+      x[i] = x[i] + p[i] * al;
+      const C rn = r[i] - q[i] * al;
+      r[i] = rn;
+      lds[Lay::at(i / N, i % N)] = rn;
+    }
+  } else {
+    for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = r[i];
+  }
+  __syncthreads();
+  haar_tiles<T, N, ROWS, false>(lds, P.L);
+  const double rho = P.state[s_].rho, lam = D.lambda;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < ROWS * N; i += NT)
+    acc += cabs2(lds[Lay::at(i / N, i % N)]) / (rho + lam * (double)d[i]);
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[blockIdx.x] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Precision-only kernels (no FFT size).
+// ---------------------------------------------------------------------------
+
+// |D1 x|^2 and |D2 x|^2 per pixel (TV).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
+  using C = cplx<T>;
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const int n = P.n;
+  const C* x = static_cast<const C*>(D.x);
+  T* sq = static_cast<T*>(D.sq);
+  const int total = n * n;
+  for (int i = blockIdx.x * NT * 4 + threadIdx.x, e = 0; e < 4 && i < total; ++e, i += NT) {
+    const int r = i / n, c = i - r * n;
+    const int rp = r + 1 == n ? 0 : r + 1, cp = c + 1 == n ? 0 : c + 1;
+    const C v = x[i];
+    sq[i] = (T)cabs2(x[rp * n + c] - v);
+    sq[total + i] = (T)cabs2(x[r * n + cp] - v);
+  }
+}
+
+// W_g = (sum_{j in g} |z_j|^2 + eps)^{-1/2} (eq. 12 / eq. 37) and the
+// penalty partials sum sqrt(s_g + eps), sum sqrt(s_g).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_group_w(Params P) {
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const T* sq = static_cast<const T*>(D.sq);
+  T* W = static_cast<T*>(D.W);
+  const int ng = P.shape.n_groups;
+  double ae = 0.0, a0 = 0.0;
+#pragma unroll
+  for (int e = 0; e < GROUPS_PER_WG / NT; ++e) {
+    const int g = blockIdx.x * GROUPS_PER_WG + e * NT + threadIdx.x;
+    if (g < ng) {
+      double s = 0.0;
+      for (int j = P.shape.gptr[g]; j < P.shape.gptr[g + 1]; ++j) s += (double)sq[P.shape.gidx[j]];
+      const double v = sqrt(s + P.eps);
+      W[g] = (T)(1.0 / v);
+      ae += v;
+      a0 += sqrt(s);
+    }
+  }
+  ae = block_sum(ae, red);
+  a0 = block_sum(a0, red);
+  if (threadIdx.x == 0) {
+    slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
+    slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
+  }
+}
+
+// d_j = sum over groups containing j of W_g (diag(G^T W G), eq. 13).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_group_d(Params P) {
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const T* W = static_cast<const T*>(D.W);
+  T* d = static_cast<T*>(D.d);
+  const int nc = P.shape.n_coef;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int j = blockIdx.x * NT * 4 + e * NT + threadIdx.x;
+    if (j < nc) {
+      double s = 0.0;
+      for (int t = P.shape.tptr[j]; t < P.shape.tptr[j + 1]; ++t) s += (double)W[P.shape.tidx[t]];
+      d[j] = (T)s;
+    }
+  }
+}
+
+// TV preconditioner z = M^{-1} r with M = (D + L) D^{-1} (D + U) the
+// symmetric Gauss-Seidel factors of P = rho I + lambda (D1^T W1 D1 +
+// D2^T W2 D2) (eq. 40; the L and U of eqs. 42-43) in red-black order:
+//   y_red = r / a;  y_black = (r - sum P_pq y_q) / a;
+//   z_black = y_black;  z_red = y_red - (sum P_pq z_q) / a.
+// Each workgroup owns a TV_TR x TV_TC tile and recomputes a two-pixel halo
+// of r (and a three-pixel halo of the weights) in LDS.  In UP_STEP mode
+// the residual is read from r[k & 1] and written to r[(k + 1) & 1], so a
+// halo never sees a neighbour's update.
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_update_tv(Params P) {
+  using C = cplx<T>;
+  constexpr int H = 2, RR = TV_TR + 2 * H, RC = TV_TC + 2 * H, WR = RR + 1, WC = RC + 1;
+  __shared__ C rn[RR * RC];
+  __shared__ C y[RR * RC];
+  __shared__ T av[RR * RC];
+  __shared__ T w1[WR * WC];
+  __shared__ T w2[WR * WC];
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const int n = P.n;
+  const int tiles_x = n / TV_TC;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int r0 = ty * TV_TR, c0 = tx * TV_TC;
+  const int par = (MODE == UP_STEP) ? (P.k & 1) : 0;
+  const C* rin = static_cast<const C*>(D.r[par]);
+  const T* d1 = static_cast<const T*>(D.d);
+  const T* d2 = d1 + (size_t)n * n;
+  T al = (T)0;
+  if constexpr (MODE == UP_STEP) {
+    const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+    const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+    al = (T)(pq > 0.0 ? rz / pq : 0.0);
+  }
+  const C* q = static_cast<const C*>(D.q);
+  for (int i = threadIdx.x; i < WR * WC; i += NT) {
+    const int lr = i / WC, lc = i - lr * WC;
+    const size_t g = (size_t)wrapi(r0 - H - 1 + lr, n) * n + wrapi(c0 - H - 1 + lc, n);
+    w1[i] = d1[g];
+    w2[i] = d2[g];
+  }
+  for (int i = threadIdx.x; i < RR * RC; i += NT) {
+    const int lr = i / RC, lc = i - lr * RC;
+    const size_t g = (size_t)wrapi(r0 - H + lr, n) * n + wrapi(c0 - H + lc, n);
+    C v = rin[g];
+    if (MODE == UP_STEP) v = v - q[g] * al;
+    rn[i] = v;
+  }
+  __syncthreads();
+  const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
+  // weights around region cell (lr, lc): W1(p) at w(lr+1, lc+1), W1(p-e1) at
+  // w(lr, lc+1), W2(p) at w(lr+1, lc+1), W2(p-e2) at w(lr+1, lc).
+#define W1P(lr, lc) w1[((lr) + 1) * WC + (lc) + 1]
+#define W1M(lr, lc) w1[(lr) * WC + (lc) + 1]
+#define W2P(lr, lc) w2[((lr) + 1) * WC + (lc) + 1]
+#define W2M(lr, lc) w2[((lr) + 1) * WC + (lc)]
+  for (int i = threadIdx.x; i < RR * RC; i += NT) {
+    const int lr = i / RC, lc = i - lr * RC;
+    const T a = rho + lam * (W1P(lr, lc) + W1M(lr, lc) + W2P(lr, lc) + W2M(lr, lc));
+    av[i] = a;
+    const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
+    if (red_cell) y[i] = rn[i] * ((T)1 / a);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (RR - 2) * (RC - 2); i += NT) {
+    const int lr = 1 + i / (RC - 2), lc = 1 + i % (RC - 2);
+    const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
+    if (!red_cell) {
+      const int o = lr * RC + lc;
+      const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
+      y[o] = (rn[o] + s * lam) * ((T)1 / av[o]);
+    }
+  }
+  __syncthreads();
+  C* z = static_cast<C*>(D.z);
+  C* rout = static_cast<C*>(D.r[par ^ 1]);
+  C* x = static_cast<C*>(D.x);
+  const C* p = static_cast<const C*>(D.p);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < TV_TR * TV_TC; i += NT) {
+    const int lr = H + i / TV_TC, lc = H + i % TV_TC;
+    const int o = lr * RC + lc;
+    const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
+    C zz = y[o];
+    if (red_cell) {
+      const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
+      zz = zz + s * (lam / av[o]);
+    }
+    const size_t g = (size_t)(r0 + lr - H) * n + (c0 + lc - H);
+    z[g] = zz;
+    acc += cdot(rn[o], zz);
+    if (MODE == UP_STEP) {
+      rout[g] = rn[o];
+      x[g] = x[g] + p[g] * al;
+    }
+  }
+#undef W1P
+#undef W1M
+#undef W2P
+#undef W2M
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[blockIdx.x] = tot;
+}
+
+}  // namespace firls

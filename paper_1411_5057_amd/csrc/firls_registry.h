@@ -1,0 +1,35 @@
+// Host-side tables of kernel launchers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "firls_types.h"
+
+namespace firls {
+
+using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
+
+// Kernels that depend on the image side (FFT length).
+struct SizeKernels {
+  Launcher rowfwd[3];
+  Launcher col[3];
+  Launcher rowinv[5];
+  Launcher psi_sq_haar;
+  Launcher update_haar[2];
+};
+
+// Kernels that depend on the precision only.
+struct PrecKernels {
+  Launcher psi_sq_tv;
+  Launcher group_w;
+  Launcher group_d;
+  Launcher update_tv[2];
+  Launcher export_d;
+  Launcher slice_init;
+  Launcher outer_check;
+};
+
+// nullptr if the size is not built for that precision.
+const SizeKernels* size_kernels(bool fp64, int n);
+const PrecKernels* prec_kernels(bool fp64);
+bool size_supported(int n);
+
+}  // namespace firls

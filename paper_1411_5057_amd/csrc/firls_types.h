@@ -1,0 +1,107 @@
+// Shared host/device structures of the FIRLS library (internal).
+#pragma once
+#include <stdint.h>
+
+namespace firls {
+
+constexpr int NT = 256;          // threads per workgroup (4 wave64)
+constexpr int KMAX = 64;         // largest PCG iteration count per outer iteration
+constexpr int PMAX = 512;        // partial sums per slot per slice
+constexpr int GROUPS_PER_WG = 1024;
+constexpr int TV_TR = 16;        // TV preconditioner tile rows
+constexpr int TV_TC = 32;        // TV preconditioner tile columns
+
+// Slots of the per-slice FP64 partial-sum area.  Every slot holds up to
+// PMAX partials, each written by exactly one workgroup, and every consumer
+// sums them in index order, so all reductions are deterministic.
+enum Slot : int {
+  SLOT_DATA = 0,      // 1/2 ||m F x - b||^2 partials (column pass)
+  SLOT_REG_EPS = 1,   // sum sqrt(s_g + eps)        (group pass)
+  SLOT_REG0 = 2,      // sum sqrt(s_g)              (group pass)
+  SLOT_PQ0 = 3,       // <p_k, S p_k>, k = 0..KMAX-1
+  SLOT_RZ0 = 3 + KMAX,  // <r_k, z_k>, k = 0..KMAX
+  SLOT_COUNT = 3 + KMAX + KMAX + 1
+};
+
+enum Psi : int { PSI_HAAR = 0, PSI_TV = 1 };
+enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
+
+// Kernel variants (template modes).
+enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2 };
+enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2 };
+enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
+enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
+
+// Per-slice device pointers.  Caller-owned: b, mask, x.  The rest is
+// library workspace.  Complex vectors are n x n interleaved (re, im) of the
+// working precision; d / sq are real arrays of the transform's size (n^2
+// for Haar in the tile-major coefficient layout, 2 n^2 for TV); W is per
+// group.
+struct SliceDesc {
+  const void* b;
+  const uint8_t* mask;
+  void* x;
+  void* r[2];
+  void* p;
+  void* q;
+  void* t;
+  void* z;
+  void* d;
+  void* sq;
+  void* W;
+  double* parts;
+  double lambda;
+  int32_t n;
+  int32_t shape;
+};
+
+// Per-slice device state of the outer loop (FP64 scalars on the device).
+struct SliceState {
+  double rho;        // mean diag(A^H A) = sampled fraction
+  double Fe;         // F_eps at the last evaluation
+  double F;          // F (eps = 0) at the last evaluation
+  double data;       // 1/2 ||A x - b||^2 at the last evaluation
+  double Fe_prev;    // F_eps at the evaluation before
+  double rel;        // (Fe_prev - Fe) / Fe
+  int32_t active;    // 1 while the slice still iterates
+  int32_t outer;     // reweighted solves done
+  int32_t pcg;       // PCG iterations done
+  int32_t status;    // 0, FIRLS_W_MAXITER, FIRLS_E_NONFINITE
+  int32_t converged;
+  int32_t evals;     // objective evaluations done
+};
+
+// Group map of one shape on the device (internal coefficient indices).
+struct ShapeDev {
+  const int32_t* gptr;   // [n_groups + 1]
+  const int32_t* gidx;   // members
+  const int32_t* tptr;   // [n_coef + 1] coefficient -> groups (transpose)
+  const int32_t* tidx;
+  const int32_t* perm;   // user coefficient index -> internal index
+  int32_t n_groups;
+  int32_t n_coef;
+};
+
+// Kernel parameters (passed by value).
+struct Params {
+  const SliceDesc* desc;
+  SliceState* state;
+  const int32_t* list;   // slice ids; blockIdx.y indexes it
+  const void* tw;        // twiddles exp(-2 pi i k / n), k < n
+  ShapeDev shape;
+  int32_t n;
+  int32_t L;             // Haar levels
+  int32_t k;             // PCG iteration index
+  int32_t K;             // PCG iterations per outer iteration
+  int32_t Tmax;
+  int32_t precond;
+  int32_t nrz;           // partial counts of the <r,z>, <p,q>, data and penalty slots
+  int32_t npq;
+  int32_t ndata;
+  int32_t nreg;
+  double eps;
+  double tau;
+  void* out;             // op entry points: extra output
+};
+
+}  // namespace firls

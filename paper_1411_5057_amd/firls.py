@@ -1,0 +1,269 @@
+"""ctypes binding of libfirls.so (include/firls.h), same names as the C ABI.
+
+Only argument marshalling lives here: every step of a solve runs in the HIP
+kernels of the library.  Device buffers are torch tensors on the current
+HIP device (``torch.cuda``); streams are torch streams.  There is no CPU
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfirls.so")
+
+FIRLS_OK = 0
+FIRLS_E_INVALID = -1
+FIRLS_E_UNSUPPORTED = -2
+FIRLS_E_HIP = -3
+FIRLS_E_NOMEM = -4
+FIRLS_E_NONFINITE = -5
+FIRLS_W_MAXITER = 1
+FIRLS_PSI_HAAR = 0
+FIRLS_PSI_TV = 1
+FIRLS_FP64 = 0
+FIRLS_FP32 = 1
+FIRLS_PC_PAPER = 0
+FIRLS_PC_JACOBI = 1
+FIRLS_PC_NONE = 2
+
+EXPORTED = (
+    "firls_create", "firls_destroy", "firls_workspace_bytes", "firls_solve",
+    "firls_solve_batched", "firls_op_adjoint", "firls_op_weights",
+    "firls_op_system", "firls_op_precond", "firls_op_objective",
+    "firls_op_outer_step", "firls_last_error",
+)
+
+
+class firls_shape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("psi", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("n_groups", ctypes.c_int32), ("group_ptr", ctypes.POINTER(ctypes.c_int32)),
+                ("group_idx", ctypes.POINTER(ctypes.c_int32))]
+
+
+class firls_config(ctypes.Structure):
+    _fields_ = [("n_shapes", ctypes.c_int32), ("shapes", ctypes.POINTER(firls_shape)),
+                ("max_slices", ctypes.c_int32), ("prec", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("outer_tol", ctypes.c_double), ("precond", ctypes.c_int32)]
+
+
+class firls_slice(ctypes.Structure):
+    _fields_ = [("shape_id", ctypes.c_int32), ("x_is_init", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("b", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class firls_report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("F", ctypes.c_double), ("F_eps", ctypes.c_double),
+                ("data", ctypes.c_double), ("rel_change", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfirls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1411_5057_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "firls_create": ([ctypes.POINTER(firls_config), ctypes.POINTER(vp)], ctypes.c_int),
+        "firls_destroy": ([vp], ctypes.c_int),
+        "firls_workspace_bytes": ([vp, i32, i32], ctypes.c_size_t),
+        "firls_solve": ([vp, vp, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
+        "firls_solve_batched": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
+        "firls_op_adjoint": ([vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "firls_op_weights": ([vp, vp, i32, vp, vp], ctypes.c_int),
+        "firls_op_system": ([vp, vp, i32, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "firls_op_precond": ([vp, vp, i32, vp, dbl, vp, vp, vp], ctypes.c_int),
+        "firls_op_objective": ([vp, vp, i32, vp, vp, dbl, vp, ctypes.POINTER(dbl)], ctypes.c_int),
+        "firls_op_outer_step": ([vp, vp, i32, vp, vp, dbl, vp], ctypes.c_int),
+        "firls_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def firls_last_error() -> str:
+    return load().firls_last_error().decode()
+
+
+class FirlsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where} failed with {code}: {firls_last_error()}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> int:
+    if code < 0:
+        raise FirlsError(code, where)
+    return code
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def firls_create(cfg: firls_config) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().firls_create(ctypes.byref(cfg), ctypes.byref(h)), "firls_create")
+    return h
+
+
+def firls_destroy(h) -> int:
+    return load().firls_destroy(h)
+
+
+def firls_workspace_bytes(h, shape_id: int, n: int) -> int:
+    return int(load().firls_workspace_bytes(h, shape_id, n))
+
+
+def firls_solve(h, stream, sl: firls_slice, rep: firls_report) -> int:
+    return _check(load().firls_solve(h, stream, ctypes.byref(sl), ctypes.byref(rep)), "firls_solve")
+
+
+def firls_solve_batched(h, stream, n: int, slices, reports) -> int:
+    return _check(load().firls_solve_batched(h, stream, n, slices, reports), "firls_solve_batched")
+
+
+def firls_op_adjoint(h, stream, shape_id, b, mask, x) -> int:
+    return _check(load().firls_op_adjoint(h, stream, shape_id, b, mask, x), "firls_op_adjoint")
+
+
+def firls_op_weights(h, stream, shape_id, x, d_out) -> int:
+    return _check(load().firls_op_weights(h, stream, shape_id, x, d_out), "firls_op_weights")
+
+
+def firls_op_system(h, stream, shape_id, mask, lam, x_w, p, q) -> int:
+    return _check(load().firls_op_system(h, stream, shape_id, mask, lam, x_w, p, q), "firls_op_system")
+
+
+def firls_op_precond(h, stream, shape_id, mask, lam, x_w, r, z) -> int:
+    return _check(load().firls_op_precond(h, stream, shape_id, mask, lam, x_w, r, z), "firls_op_precond")
+
+
+def firls_op_objective(h, stream, shape_id, b, mask, lam, x):
+    out = (ctypes.c_double * 3)()
+    _check(load().firls_op_objective(h, stream, shape_id, b, mask, lam, x, out), "firls_op_objective")
+    return tuple(out)
+
+
+def firls_op_outer_step(h, stream, shape_id, b, mask, lam, x) -> int:
+    return _check(load().firls_op_outer_step(h, stream, shape_id, b, mask, lam, x), "firls_op_outer_step")
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer over torch tensors
+# ---------------------------------------------------------------------------
+
+class Shape:
+    """Python description of a firls_shape (group map as int32 numpy CSR)."""
+
+    def __init__(self, n: int, psi: str, levels: int = 0, group_ptr=None, group_idx=None):
+        self.n, self.psi, self.levels = int(n), psi, int(levels)
+        self.group_ptr = None if group_ptr is None else np.ascontiguousarray(group_ptr, dtype=np.int32)
+        self.group_idx = None if group_idx is None else np.ascontiguousarray(group_idx, dtype=np.int32)
+
+    def c(self) -> firls_shape:
+        s = firls_shape()
+        s.n = self.n
+        s.psi = FIRLS_PSI_HAAR if self.psi == "haar" else FIRLS_PSI_TV
+        s.levels = self.levels
+        if self.group_ptr is not None:
+            s.n_groups = len(self.group_ptr) - 1
+            s.group_ptr = self.group_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            s.group_idx = self.group_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        return s
+
+
+class Solver:
+    """Owns a firls_handle.  Tensors: b, x complex64 (FP32) / complex128
+    (FP64) n x n on the GPU, mask uint8 n x n."""
+
+    def __init__(self, shapes: Sequence[Shape], *, prec: str = "fp32", max_slices: int = 1,
+                 eps: float = 1e-10, max_outer: int = 50, pcg_iters: int = 20,
+                 outer_tol: float = 0.0, precond: int = FIRLS_PC_PAPER):
+        self.shapes = list(shapes)
+        self._cshapes = (firls_shape * len(self.shapes))(*[s.c() for s in self.shapes])
+        cfg = firls_config()
+        cfg.n_shapes = len(self.shapes)
+        cfg.shapes = self._cshapes
+        cfg.max_slices = max_slices
+        cfg.prec = FIRLS_FP32 if prec == "fp32" else FIRLS_FP64
+        cfg.eps = eps
+        cfg.max_outer = max_outer
+        cfg.pcg_iters = pcg_iters
+        cfg.outer_tol = outer_tol
+        cfg.precond = precond
+        self.cfg = cfg
+        self.prec = prec
+        self.handle = firls_create(cfg)
+
+    def close(self):
+        if self.handle:
+            firls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, mask, x, lam: float, shape_id: int = 0, x_is_init: bool = False, stream=None) -> dict:
+        sl = firls_slice(shape_id, int(x_is_init), float(lam), _ptr(b), _ptr(mask), _ptr(x))
+        rep = firls_report()
+        firls_solve(self.handle, _stream(stream), sl, rep)
+        return rep.as_dict()
+
+    def solve_batched(self, items: List[dict], stream=None) -> List[dict]:
+        """items: dicts with b, mask, x, lam, shape_id (0), x_is_init (False)."""
+        n = len(items)
+        arr = (firls_slice * n)()
+        for i, it in enumerate(items):
+            arr[i] = firls_slice(int(it.get("shape_id", 0)), int(bool(it.get("x_is_init", False))),
+                                 float(it["lam"]), _ptr(it["b"]), _ptr(it["mask"]), _ptr(it["x"]))
+        reps = (firls_report * n)()
+        firls_solve_batched(self.handle, _stream(stream), n, arr, reps)
+        return [r.as_dict() for r in reps]
+
+    # single-operator entry points
+    def adjoint(self, b, mask, x, shape_id=0, stream=None):
+        firls_op_adjoint(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), _ptr(x))
+
+    def weights(self, x, d_out, shape_id=0, stream=None):
+        firls_op_weights(self.handle, _stream(stream), shape_id, _ptr(x), _ptr(d_out))
+
+    def system(self, mask, lam, x_w, p, q, shape_id=0, stream=None):
+        firls_op_system(self.handle, _stream(stream), shape_id, _ptr(mask), float(lam), _ptr(x_w), _ptr(p), _ptr(q))
+
+    def precond(self, mask, lam, x_w, r, z, shape_id=0, stream=None):
+        firls_op_precond(self.handle, _stream(stream), shape_id, _ptr(mask), float(lam), _ptr(x_w), _ptr(r), _ptr(z))
+
+    def objective(self, b, mask, lam, x, shape_id=0, stream=None):
+        return firls_op_objective(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
+
+    def outer_step(self, b, mask, lam, x, shape_id=0, stream=None):
+        firls_op_outer_step(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))

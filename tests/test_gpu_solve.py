@@ -1,0 +1,139 @@
+"""GPU parity of whole FIRLS solves (Algorithms 2 and 3) against the oracle.
+
+Bars: FP64 runs agree with the FP64 oracle to 1e-10 relative objective;
+FP32 runs (FP64 scalars) to 1e-5 relative objective, evaluated by the
+oracle on the GPU's own result.  Solves use a fixed number of outer
+iterations unless the stop rule itself is under test.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.firls import Operators, firls
+from tests.gpu_util import dev_complex, dev_mask, rel, shape_of, to_np, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+OBJ_TOL = {"fp32": 1e-5, "fp64": 1e-10}
+
+
+def run_gpu(prob, prec, T, K, tau=0.0, x1=None):
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    s = F.Solver([shape_of(prob)], prec=prec, max_outer=T, pcg_iters=K, outer_tol=tau, eps=prob.eps)
+    b, m = dev_complex(prob.b, prec), dev_mask(prob.mask)
+    x = dev_complex(x1, prec) if x1 is not None else torch.zeros_like(b)
+    rep = s.solve(b, m, x, prob.lam, x_is_init=x1 is not None)
+    return to_np(x), rep
+
+
+def check(prob, prec, T, K, tau=0.0, x1=None):
+    x, rep = run_gpu(prob, prec, T, K, tau, x1)
+    ops = Operators.from_problem(prob)
+    ref = firls(ops, T, K, tau=tau, x1=x1)
+    fe_gpu = ops.objective(x)[0]
+    assert rep["status"] >= 0
+    assert abs(fe_gpu - ref.F_eps) <= OBJ_TOL[prec] * ref.F_eps, (fe_gpu, ref.F_eps)
+    # the objective the GPU reports for its own x
+    assert abs(rep["F_eps"] - fe_gpu) <= OBJ_TOL[prec] * fe_gpu
+    return x, rep, ref
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cfg0_fp64(seed):
+    """64^2, 3-level Haar, singleton groups, FP64: 30 outer x 20 PCG."""
+    p = synth.cfg0(seed)
+    x, rep, ref = check(p, "fp64", 30, 20)
+    assert rel(x, ref.x) < 1e-8
+    assert rep["outer_iters"] == 30 and rep["pcg_iters"] == 600
+
+
+@pytest.mark.parametrize("n,seed", [(64, 0), (128, 1), (192, 2)])
+def test_tree_groups_fp32(n, seed):
+    p = synth.make_problem(n, seed, psi="haar", levels=4, groups="quadtree", lam=0.035,
+                           sigma=0.01, frac=0.2)
+    check(p, "fp32", 10, 20)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [64, 96])
+def test_tv(n, prec):
+    p = synth.make_problem(n, 5, psi="tv", levels=0, groups="tv_iso", lam=0.01, sigma=0.005,
+                           n_ellipses=12, mask_kind="radial", frac=0.15, ramp=True)
+    x, rep, ref = check(p, prec, 8, 20)
+    if prec == "fp64":
+        assert rel(x, ref.x) < 1e-8
+
+
+def test_tv_anisotropic_groups():
+    p = synth.make_problem(64, 6, psi="tv", levels=0, groups="tv_aniso", lam=0.01, sigma=0.005)
+    check(p, "fp32", 6, 15)
+
+
+def test_warm_start_and_stop_rule():
+    p = synth.make_problem(64, 7, psi="haar", levels=3, groups="quadtree", lam=0.035, sigma=0.01, frac=0.2)
+    ops = Operators.from_problem(p)
+    x1 = firls(ops, 3, 20).x
+    check(p, "fp64", 4, 20, x1=x1)
+    x, rep = run_gpu(p, "fp64", 60, 20, tau=1e-4)
+    ref = firls(ops, 60, 20, tau=1e-4)
+    assert rep["converged"] == 1 and ref.converged
+    assert rep["outer_iters"] == ref.outer_iters
+    assert abs(rep["F_eps"] - ref.F_eps) <= 1e-10 * ref.F_eps
+
+
+def test_batched_uneven_mixed():
+    """Slices of several sizes and both regularisers in one call; each
+    slice must match its own oracle solve."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 11, psi="haar", levels=4, groups="quadtree", lam=0.03, sigma=0.01, frac=0.2),
+             synth.make_problem(96, 12, psi="tv", levels=0, groups="tv_iso", lam=0.01, sigma=0.01, frac=0.25),
+             synth.make_problem(128, 13, psi="haar", levels=4, groups="quadtree", lam=0.02, sigma=0.02, frac=0.3),
+             synth.make_problem(64, 14, psi="haar", levels=4, groups="quadtree", lam=0.05, sigma=0.01, frac=0.2),
+             synth.make_problem(64, 15, psi="tv", levels=0, groups="tv_iso", lam=0.02, sigma=0.01, frac=0.2)]
+    shapes = [shape_of(probs[0]), shape_of(probs[1]), shape_of(probs[2]), shape_of(probs[4])]
+    sid = [0, 1, 2, 0, 3]
+    T, K = 6, 15
+    s = F.Solver(shapes, prec="fp32", max_slices=len(probs), max_outer=T, pcg_iters=K)
+    items = []
+    for p, i in zip(probs, sid):
+        b = dev_complex(p.b, "fp32")
+        items.append(dict(b=b, mask=dev_mask(p.mask), x=torch.zeros_like(b), lam=p.lam, shape_id=i))
+    reps = s.solve_batched(items)
+    for p, it, rep in zip(probs, items, reps):
+        ops = Operators.from_problem(p)
+        ref = firls(ops, T, K)
+        fe = ops.objective(to_np(it["x"]))[0]
+        assert abs(fe - ref.F_eps) <= 1e-5 * ref.F_eps
+        assert rep["outer_iters"] == T
+
+
+def test_deterministic():
+    p = synth.make_problem(128, 21, psi="haar", levels=4, groups="quadtree", lam=0.035, sigma=0.01, frac=0.2)
+    x1, r1 = run_gpu(p, "fp32", 5, 20)
+    x2, r2 = run_gpu(p, "fp32", 5, 20)
+    assert np.array_equal(x1, x2) and r1["F_eps"] == r2["F_eps"]
+
+
+def test_outer_steps_monotone():
+    """Theorem 2 on the GPU: F_eps never increases across outer steps."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    p = synth.make_problem(128, 22, psi="tv", levels=0, groups="tv_iso", lam=0.01, sigma=0.01, frac=0.2)
+    s = F.Solver([shape_of(p)], prec="fp32", max_outer=1, pcg_iters=5)
+    b, m = dev_complex(p.b, "fp32"), dev_mask(p.mask)
+    x = torch.empty_like(b)
+    s.adjoint(b, m, x)
+    vals = [s.objective(b, m, p.lam, x)[0]]
+    for _ in range(8):
+        s.outer_step(b, m, p.lam, x)
+        vals.append(s.objective(b, m, p.lam, x)[0])
+    assert all(vals[i + 1] <= vals[i] * (1 + 1e-6) for i in range(len(vals) - 1)), vals
+
+
+def test_full_size_tree_config():
+    """256^2 tree-group workload (the benchmark's slice shape) at 5 outer
+    iterations, compared over the whole image."""
+    p = synth.cfg1(0)
+    check(p, "fp32", 5, 20)
