@@ -1,0 +1,190 @@
+"""Benchmark: batched FIRLS_OG solves at 256^2 on one MI355X.
+
+One step = one call of firls_solve_batched on B slices of the tree-group
+CS-MRI workload (256 x 256 ellipse phantoms, 20% variable-density k-space
+mask, sigma 0.01, 4-level Haar, each coefficient grouped with its quadtree
+parent, lambda 0.035, eps 1e-10, FP32 vectors with FP64 scalars, 20 PCG
+iterations per outer iteration), every slice started from A^H b and run
+until its relative objective decrease falls below tau (calibrated so that
+the final objective is within 1e-4 of the optimum) or 50 outer iterations.
+Inputs are generated and uploaded before the timed region.
+
+Prints one JSON line with solves/s, the roofline of the dominant kernel
+(HIP-event durations measured during the timed steps), the achieved
+algorithmic HBM rate of the whole path, the gap to the optimum of every
+slice, and the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s at 256² CS-MRI to 1e-4 rel. objective, learned vs plain; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per pixel per launch of each PCG kernel class for a
+# Haar slice in FP32 (c64 = 8 B, r32 = 4 B, u8 mask = 1 B), the minimum each
+# kernel must stream:
+#   rowfwd : read r, d, p; write p, t         (p not read at k = 0)
+#   col    : read t, mask; write t
+#   rowinv : read t, p, d; write q
+#   update : read x, p, q, r, d; write x, r
+def bytes_per_px(cls: str, K: int) -> float:
+    return {
+        "rowfwd": (28.0 + 36.0 * (K - 1)) / K,
+        "col": 17.0,
+        "rowinv": 28.0,
+        "update": 52.0,
+        "psi_sq": 12.0,        # read x; write |Phi x|^2
+        "group_w": 10.0,       # read |z|^2 of members (~2 per group), write W
+        "group_d": 12.0,       # read W of the groups of each coefficient (~2), write d
+        "r0_rowfwd": 16.0,     # read x; write t
+        "r0_col": 25.0,        # read t, mask, b; write t
+        "r0_rowinv": 28.0,     # read t, x, d; write r
+        "r0_update": 12.0,     # read r, d
+        "adjoint": 33.0,       # read b, mask; write t; read t; write x
+    }.get(cls, 0.0)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--slices", type=int, default=256)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--pcg", type=int, default=20)
+    ap.add_argument("--max-outer", type=int, default=50)
+    ap.add_argument("--tau", type=float, default=1e-5)
+    ap.add_argument("--ref-outer", type=int, default=300,
+                    help="outer iterations of the reference solve that estimates the optimum")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-gap", action="store_true")
+    return ap.parse_args()
+
+
+def make_inputs(B, n, torch):
+    import synth
+    bs, ms, lams = [], [], []
+    for s in range(B):
+        p = synth.cfg1(s, n=n)
+        bs.append(p.b)
+        ms.append(p.mask)
+        lams.append(p.lam)
+    b = torch.from_numpy(np.stack(bs)).to(torch.complex64).cuda().contiguous()
+    m = torch.from_numpy(np.stack(ms)).cuda().contiguous()
+    return p, b, m, lams
+
+
+def cpu_baseline(n, tau, max_outer, K):
+    """The FP64 oracle, untouched, on one slice of the same workload."""
+    import synth
+    from oracle.firls import Operators, firls
+    p = synth.cfg1(0, n=n)
+    ops = Operators.from_problem(p)
+    t0 = time.perf_counter()
+    rep = firls(ops, max_outer, K, tau=tau)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 slice (seed 0) of the same workload, {rep.outer_iters} outer x {K} PCG, "
+                      f"numpy FP64, single process; {dt:.1f} s per solve"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(slices are independent, so several GPUs would each run their own batch)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1411_5057_amd import firls as F
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B, n, K = a.slices, a.n, a.pcg
+    p0, b, m, lams = make_inputs(B, n, torch)
+    shape = F.Shape(n, "haar", 4, p0.group_ptr, p0.group_idx)
+    solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
+                      outer_tol=a.tau, eps=1e-10)
+    x = torch.zeros_like(b)
+    stream = torch.cuda.current_stream()
+    items = [dict(b=b[i], mask=m[i], x=x[i], lam=lams[i]) for i in range(B)]
+
+    for _ in range(a.warmup):
+        solver.solve_batched(items)
+    torch.cuda.synchronize()
+    if not a.no_profile:
+        solver.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        reps = solver.solve_batched(items)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = solver.profile_read() if not a.no_profile else {}
+    solver.profile(False)
+
+    value = B * a.steps / dt
+    outer = np.array([r["outer_iters"] for r in reps])
+    pcg = np.array([r["pcg_iters"] for r in reps])
+    fe = np.array([r["F_eps"] for r in reps])
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded ellipse phantoms, VD masks, complex Gaussian noise)",
+        "config": {"workload": f"tree-group FIRLS_OG, {n}x{n}, 20% VD mask, sigma 0.01, 4-level Haar, "
+                               f"quadtree-pair groups, lambda 0.035, eps 1e-10, {B} slices per step, "
+                               f"{K} PCG per outer, stop at rel. F_eps decrease {a.tau:g} (max {a.max_outer})",
+                   "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer},
+        "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
+        "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
+        "converged_frac": float(np.mean([r["converged"] for r in reps])),
+    }
+    if prof:
+        npx = n * n
+        tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
+        out["hbm_gbs_algorithmic"] = tot_bytes / dt / 1e9
+        pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update")}
+        dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
+        v = prof[dom]
+        per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]
+        avg_s = v["ms"] / v["launches"] / 1e3
+        ach = per_launch_bytes / avg_s / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": avg_s * 1e6, "bytes_per_launch": per_launch_bytes}
+        out["kernel_ms"] = {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]}
+        gpu_ms = sum(v["ms"] for v in prof.values())
+        out["kernel_time_frac_of_wall"] = gpu_ms / 1e3 / dt
+    if not a.no_gap:
+        # optimum estimate: the same slices, tau = 0, ref_outer outer iterations
+        ref = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.ref_outer, pcg_iters=K,
+                       outer_tol=0.0, eps=1e-10)
+        xr = torch.zeros_like(b)
+        rr = ref.solve_batched([dict(b=b[i], mask=m[i], x=xr[i], lam=lams[i]) for i in range(B)])
+        fstar = np.array([r["F_eps"] for r in rr])
+        gap = (fe - fstar) / fstar
+        out["gap_to_optimum"] = {"max": float(gap.max()), "p99": float(np.quantile(gap, 0.99)),
+                                 "median": float(np.median(gap)), "frac_le_1e-4": float(np.mean(gap <= 1e-4)),
+                                 "reference": f"same slices, {a.ref_outer} outer iterations, tau = 0"}
+        ref.close()
+    if not a.no_cpu:
+        cb = cpu_baseline(n, a.tau, a.max_outer, K)
+        cb["cores"] = 1
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

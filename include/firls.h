@@ -28,8 +28,7 @@
  *    k-space is unshifted (DC at [0, 0]); F is unitary (1/n both ways).
  *  - Masks are uint8 n x n (nonzero = sampled).  b is read as mask * b.
  *  - ``stream`` is a hipStream_t passed as void*; NULL is the null stream.
- *    Calls enqueue on it and return once their results are on the host
- *    (reports) or enqueued (operator entry points, see each).
+ *    Every call enqueues its work on it and returns once that work is done.
  *  - Return codes: 0 = success, negative = error (nothing useful was
  *    written), positive = warning.  firls_last_error() gives a message
  *    for the calling thread.
@@ -80,8 +79,8 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
  *               level-l details in [0,h)x[h,2h), [h,2h)x[0,h), [h,2h)^2
  *               with h = n / 2^l).  TV: p for (D1 x)[p], N + p for
  *               (D2 x)[p], N = n^2.  A coefficient may sit in several groups
- *               (overlap through G, Section 3.1, Fig. 1).  Every coefficient
- *               must be covered by at least one group.
+ *               (overlap through G, Section 3.1, Fig. 1); a coefficient in
+ *               no group is not penalised.
  * The arrays are copied at create; the caller keeps ownership. */
 typedef struct {
   int32_t n;
@@ -166,7 +165,7 @@ int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_r
 int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices,
                         const firls_slice* slices, firls_report* reports);
 
-/* ---- single-operator entry points (one slice; enqueue only) ----------- */
+/* ---- single-operator entry points (one slice; each blocks until done) -- */
 
 /* x = A^H b = F^H (mask * b)  (the zero-filled start, Section 3.3). */
 int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id,
@@ -201,6 +200,43 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id,
  * iteration of Algorithm 2 / 3).  Blocks. */
 int firls_op_outer_step(firls_handle* h, void* stream, int32_t shape_id,
                         const void* b, const uint8_t* mask, double lambda, void* x);
+
+/* ---- instrumentation -------------------------------------------------- */
+
+/* Kernel classes timed by firls_profile (index into the stats array). */
+enum {
+  FIRLS_PROF_INIT = 0,      /* per-slice state and rho */
+  FIRLS_PROF_AHB = 1,       /* zero-filled start A^H b (two passes) */
+  FIRLS_PROF_PSI_SQ = 2,    /* |Psi x|^2 */
+  FIRLS_PROF_GROUP_W = 3,   /* group weights W and penalty partials */
+  FIRLS_PROF_GROUP_D = 4,   /* d = diag(G^T W G) */
+  FIRLS_PROF_R0_ROWFWD = 5, /* residual A^H b - S x: row FFT */
+  FIRLS_PROF_R0_COL = 6,    /*   column pass with the data term */
+  FIRLS_PROF_R0_ROWINV = 7, /*   row inverse FFT + regulariser */
+  FIRLS_PROF_R0_UPDATE = 8, /*   z0 and <r0, z0> */
+  FIRLS_PROF_CHECK = 9,     /* objective and stop rule */
+  FIRLS_PROF_ROWFWD = 10,   /* PCG: z = P^{-1} r, p = z + beta p, row FFT */
+  FIRLS_PROF_COL = 11,      /* PCG: column FFT, mask, column inverse FFT */
+  FIRLS_PROF_ROWINV = 12,   /* PCG: row inverse FFT + regulariser, <p, q> */
+  FIRLS_PROF_UPDATE = 13,   /* PCG: x, r update and <r, z> */
+  FIRLS_PROF_CLASSES = 14
+};
+
+typedef struct {
+  char name[32];
+  int64_t launches;        /* launches timed */
+  int64_t slice_launches;  /* sum over those launches of the active slices */
+  double ms;               /* sum of HIP-event durations */
+} firls_kernel_stat;
+
+/* enable != 0: time every kernel launch of the solve entry points with a
+ * HIP event pair on the solve's stream and accumulate per class (resets
+ * the totals).  enable == 0 stops timing (totals are kept until the next
+ * enable).  Timing adds two event records per launch. */
+int firls_profile(firls_handle* h, int32_t enable);
+
+/* Copy up to n class totals into out; returns the number written. */
+int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out);
 
 /* Thread-local text of the last error (empty string if none). */
 const char* firls_last_error(void);

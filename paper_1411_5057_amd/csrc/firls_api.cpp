@@ -85,6 +85,20 @@ struct firls_handle {
   int32_t* h_list = nullptr;
   hipEvent_t ev = nullptr;
 
+  // Opt-in per-launch timing (firls_profile): one event pair per launch.
+  struct ProfRec {
+    int cls, group, it, phase, count;
+    hipEvent_t a, b;
+  };
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<ProfRec> recs;
+  int ctx_group = 0, ctx_it = 0, ctx_phase = 0, ctx_count = 0;
+  double prof_ms[FIRLS_PROF_CLASSES] = {};
+  int64_t prof_launches[FIRLS_PROF_CLASSES] = {};
+  int64_t prof_units[FIRLS_PROF_CLASSES] = {};
+
   size_t slice_bytes(const Shape& s) const {
     const size_t vec = align256((size_t)s.n * s.n * elt);
     const size_t nvec = s.psi == PSI_TV ? 6 : 4;
@@ -216,42 +230,86 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
     if (e_ != hipSuccess) return fail(FIRLS_E_HIP, std::string("launch ") + #fn + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+hipEvent_t prof_event(firls_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Launch with optional timing; ``cls`` is a FIRLS_PROF_* class.
+#define KLAUNCH(h, cls, fn, P, grid, st)                                                \
+  do {                                                                                  \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                                              \
+    if ((h)->profiling) {                                                               \
+      a_ = prof_event(h);                                                               \
+      b_ = prof_event(h);                                                               \
+      if (a_) (void)hipEventRecord(a_, (st));                                           \
+    }                                                                                   \
+    LAUNCH(fn, P, grid, st);                                                            \
+    if (a_ && b_) {                                                                     \
+      (void)hipEventRecord(b_, (st));                                                   \
+      (h)->recs.push_back({(cls), (h)->ctx_group, (h)->ctx_it, (h)->ctx_phase, (h)->ctx_count, a_, b_}); \
+    }                                                                                   \
+  } while (0)
+
 // Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.
-int launch_weights(const firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int R = rows_of(h->fp64);
-  if (s.psi == PSI_HAAR) LAUNCH(s.sk->psi_sq_haar, P, dim3(s.n / R, c), st);
-  else LAUNCH(pk->psi_sq_tv, P, dim3((s.n * s.n + 4 * NT - 1) / (4 * NT), c), st);
-  LAUNCH(pk->group_w, P, dim3(P.nreg, c), st);
-  LAUNCH(pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
+  if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.n / R, c), st);
+  else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3((s.n * s.n + 4 * NT - 1) / (4 * NT), c), st);
+  KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
+  KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
   return FIRLS_OK;
 }
 
 // r0 = A^H b - S x (data term fused), then z0 and <r0, z0>.
-int launch_residual(const firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+int launch_residual(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int R = rows_of(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, c), st);
-  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / R, c), st);
-  LAUNCH(s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / R, c), st);
-  if (haar) LAUNCH(s.sk->update_haar[UP_INIT], P, dim3(s.n / R, c), st);
-  else LAUNCH(pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / R, c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / R, c), st);
+  if (haar) KLAUNCH(h, FIRLS_PROF_R0_UPDATE, s.sk->update_haar[UP_INIT], P, dim3(s.n / R, c), st);
+  else KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
   return FIRLS_OK;
 }
 
-int launch_pcg(const firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
+int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int R = rows_of(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
   for (int k = 0; k < h->cfg.pcg_iters; ++k) {
     P.k = k;
-    LAUNCH(s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / R, c), st);
-    LAUNCH(s.sk->col[COL_SP], P, dim3(s.n / R, c), st);
-    LAUNCH(s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / R, c), st);
-    if (haar) LAUNCH(s.sk->update_haar[UP_STEP], P, dim3(s.n / R, c), st);
-    else LAUNCH(pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
+    KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / R, c), st);
+    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[COL_SP], P, dim3(s.n / R, c), st);
+    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / R, c), st);
+    if (haar) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar[UP_STEP], P, dim3(s.n / R, c), st);
+    else KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
   }
+  return FIRLS_OK;
+}
+
+// Fold the timed launches of one run_batch into the per-class totals.
+// Units are active slices: a launch at outer iteration ``it`` counts the
+// slices of its group still active when it ran.
+int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg) {
+  for (const auto& r : h->recs) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    int units = r.count;
+    if (r.phase == 1 && r.it > 0) units = act_pcg[r.it - 1][r.group];
+    if (r.phase == 2) units = act_pcg[r.it][r.group];
+    h->prof_ms[r.cls] += ms;
+    h->prof_launches[r.cls] += 1;
+    h->prof_units[r.cls] += units;
+  }
+  h->recs.clear();
+  h->ev_used = 0;
   return FIRLS_OK;
 }
 
@@ -303,9 +361,14 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
 
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int R = rows_of(h->fp64);
+  std::vector<std::vector<int>> act_pcg;
+  h->ctx_phase = 0;
+  h->ctx_it = 0;
+  h->ctx_group = 0;
+  h->ctx_count = ns;
   {
     Params P = base_params(h, h->shapes[0], 0, h->d_list);
-    LAUNCH(pk->slice_init, P, dim3(ns), st);
+    KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(ns), st);
   }
   // x^1 = A^H b for slices without a warm start (Section 3.3)
   for (int s = 0; s < nsh; ++s) {
@@ -313,10 +376,14 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     if (!c) continue;
     const Shape& S = h->shapes[s];
     Params P = base_params(h, S, s, h->d_list + zlo[s]);
-    LAUNCH(S.sk->col[COL_AHB], P, dim3(S.n / R, c), st);
-    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / R, c), st);
+    h->ctx_group = s;
+    h->ctx_count = c;
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.n / R, c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.n / R, c), st);
   }
   for (int it = 0; it <= Tmax; ++it) {
+    h->ctx_it = it;
+    h->ctx_phase = 1;
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
@@ -324,25 +391,35 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       Params P = base_params(h, S, s, h->d_list + lo[s]);
       P.Tmax = Tmax;
       P.tau = tau;
+      h->ctx_group = s;
+      h->ctx_count = c;
       if ((rc = launch_weights(h, S, P, c, st))) return rc;
       if ((rc = launch_residual(h, S, P, c, st))) return rc;
-      LAUNCH(pk->outer_check, P, dim3(c), st);
+      KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
     }
     HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
     HIPCHK(hipEventRecord(h->ev, st));
+    h->ctx_phase = 2;
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
       const Shape& S = h->shapes[s];
       Params P = base_params(h, S, s, h->d_list + lo[s]);
+      h->ctx_group = s;
+      h->ctx_count = c;
       if ((rc = launch_pcg(h, S, P, c, st))) return rc;
     }
     HIPCHK(hipEventSynchronize(h->ev));
     int active = 0;
-    for (int i = 0; i < ns; ++i) active += h->h_state[i].active;
+    act_pcg.emplace_back(nsh, 0);
+    for (int i = 0; i < ns; ++i) {
+      active += h->h_state[i].active;
+      act_pcg.back()[sl[i].shape_id] += h->h_state[i].active;
+    }
     if (!active) break;
   }
   HIPCHK(hipStreamSynchronize(st));
+  if (h->profiling && (rc = prof_collect(h, act_pcg))) return rc;
   HIPCHK(hipMemcpy(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost));
   int worst = FIRLS_OK;
   for (int i = 0; i < ns; ++i) {
@@ -545,6 +622,7 @@ int firls_destroy(firls_handle* h) {
   free_batch(h);
   destroy_shapes(h);
   if (h->ev) (void)hipEventDestroy(h->ev);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return FIRLS_OK;
 }
@@ -565,6 +643,35 @@ int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices, const f
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
   g_err.clear();
   return run_batch(h, (hipStream_t)stream, n_slices, slices, reports, h->cfg.max_outer, h->cfg.outer_tol);
+}
+
+int firls_profile(firls_handle* h, int32_t enable) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  h->profiling = enable != 0;
+  for (int c = 0; c < FIRLS_PROF_CLASSES; ++c) {
+    h->prof_ms[c] = 0.0;
+    h->prof_launches[c] = 0;
+    h->prof_units[c] = 0;
+  }
+  h->recs.clear();
+  h->ev_used = 0;
+  return FIRLS_OK;
+}
+
+int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out) {
+  if (!h || !out || n < 0) return fail(FIRLS_E_INVALID, "null argument");
+  static const char* names[FIRLS_PROF_CLASSES] = {
+      "init", "adjoint", "psi_sq", "group_w", "group_d", "r0_rowfwd", "r0_col", "r0_rowinv",
+      "r0_update", "check", "rowfwd", "col", "rowinv", "update"};
+  const int m = std::min<int>(n, FIRLS_PROF_CLASSES);
+  for (int c = 0; c < m; ++c) {
+    std::memset(&out[c], 0, sizeof(out[c]));
+    std::strncpy(out[c].name, names[c], sizeof(out[c].name) - 1);
+    out[c].launches = h->prof_launches[c];
+    out[c].slice_launches = h->prof_units[c];
+    out[c].ms = h->prof_ms[c];
+  }
+  return m;
 }
 
 int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask, void* x) {

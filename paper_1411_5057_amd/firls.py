@@ -35,8 +35,9 @@ EXPORTED = (
     "firls_create", "firls_destroy", "firls_workspace_bytes", "firls_solve",
     "firls_solve_batched", "firls_op_adjoint", "firls_op_weights",
     "firls_op_system", "firls_op_precond", "firls_op_objective",
-    "firls_op_outer_step", "firls_last_error",
+    "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
 )
+PROF_CLASSES = 14
 
 
 class firls_shape(ctypes.Structure):
@@ -55,6 +56,11 @@ class firls_config(ctypes.Structure):
 class firls_slice(ctypes.Structure):
     _fields_ = [("shape_id", ctypes.c_int32), ("x_is_init", ctypes.c_int32), ("lambda_", ctypes.c_double),
                 ("b", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class firls_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("slice_launches", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class firls_report(ctypes.Structure):
@@ -90,6 +96,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_op_precond": ([vp, vp, i32, vp, dbl, vp, vp, vp], ctypes.c_int),
         "firls_op_objective": ([vp, vp, i32, vp, vp, dbl, vp, ctypes.POINTER(dbl)], ctypes.c_int),
         "firls_op_outer_step": ([vp, vp, i32, vp, vp, dbl, vp], ctypes.c_int),
+        "firls_profile": ([vp, i32], ctypes.c_int),
+        "firls_profile_read": ([vp, i32, ctypes.POINTER(firls_kernel_stat)], ctypes.c_int),
         "firls_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -172,6 +180,17 @@ def firls_op_objective(h, stream, shape_id, b, mask, lam, x):
 
 def firls_op_outer_step(h, stream, shape_id, b, mask, lam, x) -> int:
     return _check(load().firls_op_outer_step(h, stream, shape_id, b, mask, lam, x), "firls_op_outer_step")
+
+
+def firls_profile(h, enable: bool) -> int:
+    return _check(load().firls_profile(h, int(enable)), "firls_profile")
+
+
+def firls_profile_read(h) -> dict:
+    arr = (firls_kernel_stat * PROF_CLASSES)()
+    m = _check(load().firls_profile_read(h, PROF_CLASSES, arr), "firls_profile_read")
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "slice_launches": arr[i].slice_launches,
+                                   "ms": arr[i].ms} for i in range(m)}
 
 
 # ---------------------------------------------------------------------------
@@ -264,6 +283,12 @@ class Solver:
 
     def objective(self, b, mask, lam, x, shape_id=0, stream=None):
         return firls_op_objective(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
+
+    def profile(self, enable: bool):
+        firls_profile(self.handle, enable)
+
+    def profile_read(self) -> dict:
+        return firls_profile_read(self.handle)
 
     def outer_step(self, b, mask, lam, x, shape_id=0, stream=None):
         firls_op_outer_step(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
