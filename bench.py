@@ -69,6 +69,11 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gap", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1411_5057_amd", "weights", "warmstart_256.f32"),
+                    help="warm-start network parameters (float32, ABI order); skipped if missing")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -112,6 +117,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     B, n, K = a.slices, a.n, a.pcg
+    if a.copy_calib_mb:
+        src = torch.ones(a.copy_calib_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p0, b, m, lams = make_inputs(B, n, torch)
     shape = F.Shape(n, "haar", 4, p0.group_ptr, p0.group_idx)
     solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
@@ -132,6 +143,26 @@ def main():
     dt = time.perf_counter() - t0
     prof = solver.profile_read() if not a.no_profile else {}
     solver.profile(False)
+
+    learned = None
+    if not a.no_learned and os.path.exists(a.weights) and n == 256:
+        net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4"))
+        xl = torch.zeros_like(b)
+        items_l = [dict(b=b[i], mask=m[i], x=xl[i], lam=lams[i]) for i in range(B)]
+        for _ in range(a.warmup):
+            solver.solve_batched_learned(net, items_l)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            reps_l, used = solver.solve_batched_learned(net, items_l)
+        torch.cuda.synchronize()
+        dtl = time.perf_counter() - t1
+        outer_l = np.array([r["outer_iters"] for r in reps_l])
+        learned = {"value": B * a.steps / dtl, "unit": "solves/s", "ms_per_step": 1e3 * dtl / a.steps,
+                   "outer_iters_mean": float(outer_l.mean()), "outer_iters_max": int(outer_l.max()),
+                   "learned_start_kept_frac": float(np.mean(used)),
+                   "fe": np.array([r["F_eps"] for r in reps_l]), "weights": os.path.relpath(a.weights, ROOT)}
+        net.close()
 
     value = B * a.steps / dt
     outer = np.array([r["outer_iters"] for r in reps])
@@ -177,7 +208,15 @@ def main():
         out["gap_to_optimum"] = {"max": float(gap.max()), "p99": float(np.quantile(gap, 0.99)),
                                  "median": float(np.median(gap)), "frac_le_1e-4": float(np.mean(gap <= 1e-4)),
                                  "reference": f"same slices, {a.ref_outer} outer iterations, tau = 0"}
+        if learned is not None:
+            gl = (learned["fe"] - fstar) / fstar
+            learned["gap_to_optimum"] = {"max": float(gl.max()), "p99": float(np.quantile(gl, 0.99)),
+                                         "frac_le_1e-4": float(np.mean(gl <= 1e-4))}
         ref.close()
+    if learned is not None:
+        learned.pop("fe")
+        learned["speedup_vs_plain"] = learned["value"] / value
+        out["learned"] = learned
     if not a.no_cpu:
         cb = cpu_baseline(n, a.tau, a.max_outer, K)
         cb["cores"] = 1

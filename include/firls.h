@@ -67,8 +67,7 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
 /* One image geometry and regulariser.
  *   n           image side; n in {16, 32, 48, 64, 96, 128, 192, 256, 384, 512}.
  *   psi         FIRLS_PSI_HAAR or FIRLS_PSI_TV.
- *   levels      Haar levels L >= 1, n % 2^L == 0; L <= 4 (FP32) or <= 3
- *               (FP64).  Ignored for TV.
+ *   levels      Haar levels, 1 <= L <= 4, n % 2^L == 0.  Ignored for TV.
  *   n_groups    number of groups s; 0 with NULL pointers selects the
  *               default map: singletons for Haar (standard sparsity), pixel
  *               pairs {D1 row p, D2 row p} for TV (isotropic TV, eq. 35).
@@ -200,6 +199,69 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id,
  * iteration of Algorithm 2 / 3).  Blocks. */
 int firls_op_outer_step(firls_handle* h, void* stream, int32_t shape_id,
                         const void* b, const uint8_t* mask, double lambda, void* x);
+
+/* ---- learned warm start -------------------------------------------------- */
+
+/* A small convolutional network gives the start x0 = A^H b + f(A^H b) of
+ * FIRLS (the paper starts from A^H b, Section 3.3; any start keeps
+ * Theorems 1-3).  f: five 3x3 "same" convolutions, channels 2 -> 32 -> 32 ->
+ * 32 -> 32 -> 2, ReLU after the first four, on the real and imaginary parts
+ * (bfloat16 weights and activations, FP32 accumulation on MFMA).  Parameter
+ * order (28930 floats): for each layer W[dy][dx][cin][cout] then b[cout]. */
+typedef struct firls_cnn firls_cnn;
+
+int32_t firls_cnn_param_count(void);
+
+/* Network for n x n images (n % 32 == 0) and batches up to max_batch. */
+int firls_cnn_create(int32_t n, int32_t max_batch, firls_cnn** out);
+int firls_cnn_destroy(firls_cnn* net);
+
+/* Copy host float[28930] parameters in (resets the Adam state) / out. */
+int firls_cnn_set_params(firls_cnn* net, const float* params);
+int firls_cnn_get_params(const firls_cnn* net, float* params);
+
+/* x0 = zf + f(zf) for a batch: zf, x0 device complex64 [batch, n, n]. */
+int firls_cnn_forward(firls_cnn* net, void* stream, int32_t batch, const void* zf, void* x0);
+
+/* Loss mean |x0 - label|^2 over pixels and real/imaginary parts, and its
+ * gradient with respect to the parameters (host float[28930], may be NULL);
+ * label device complex64 [batch, n, n].  Parameters unchanged. */
+int firls_cnn_gradients(firls_cnn* net, void* stream, int32_t batch, const void* zf, const void* label,
+                        float* grad, double* loss);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on the FP32
+ * master parameters with learning rate lr; *loss gets the pre-step loss. */
+int firls_cnn_train_step(firls_cnn* net, void* stream, int32_t batch, const void* zf, const void* label,
+                         float lr, double* loss);
+
+/* firls_solve_batched started from the network: every slice (FP32 handle,
+ * image side = the network's) gets x = A^H b and x0 = x + f(x); x0 is kept
+ * where F_eps(x0) <= F_eps(A^H b), else A^H b (used_learned[i] = 1 / 0, may
+ * be NULL); then FIRLS runs from there with the handle's tolerance. */
+int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, int32_t n_slices,
+                                const firls_slice* slices, firls_report* reports, int32_t* used_learned);
+
+/* ---- execution tuning --------------------------------------------------- */
+
+/* Each outer iteration launches two fixed blocks of kernels (reweighting +
+ * residual + stop test, then the PCG iterations); by default both are
+ * captured once as HIP graphs and replayed (enable = 0 launches them
+ * directly).  With the null stream the library works on its own stream,
+ * ordered after the null stream's earlier work. */
+int firls_set_graphs(firls_handle* h, int32_t enable);
+
+/* Solve batches in sub-batches of ``chunk`` slices, one after the other
+ * (0: the whole batch at once).  Smaller sub-batches keep their working
+ * set in the device's last-level cache. */
+int firls_set_chunk(firls_handle* h, int32_t chunk);
+
+/* Time a few outer iterations of these slices for candidate sub-batch sizes
+ * (whole batch, 256, 128, 64, 32) and keep the fastest (written to
+ * *chosen, may be NULL).  Every x is restored afterwards.  With the
+ * environment variable FIRLS_TUNE_CACHE naming a file, a previous choice
+ * for the same shape mix and batch size is reused, and new choices are
+ * appended. */
+int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen);
 
 /* ---- instrumentation -------------------------------------------------- */
 

@@ -3,6 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -10,6 +15,7 @@
 
 #include "firls.h"
 #include "firls_registry.h"
+#include "cnn_types.h"
 
 using namespace firls;
 
@@ -30,7 +36,6 @@ int fail(int code, const std::string& msg) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int rows_of(bool fp64) { return fp64 ? 8 : 16; }
 
 struct Shape {
   int n = 0, psi = 0, L = 0, n_groups = 0, n_coef = 0;
@@ -45,25 +50,36 @@ struct Shape {
 };
 
 // Position of Mallat coefficient (gr, gc) of an n x n, L-level Haar
-// transform in the tile-major layout: the tile of side 2^L that the
-// coefficient's support lies in, and its place in that tile's own Mallat
-// arrangement.
+// transform in the library's in-place layout: a level-l detail sits in the
+// tile of side 2^L its support lies in, at the pixel where the in-place
+// transform leaves it (row offset 2^(l-1) for a vertical detail, column
+// offset 2^(l-1) for a horizontal one, within the 2^l block it summarises);
+// the coarsest approximation sits at the tile's top-left pixel.
 int32_t haar_internal_index(int n, int L, int gr, int gc) {
   const int hL = n >> L;
   if (gr < hL && gc < hL) return (gr << L) * n + (gc << L);
   int lev = 1;
   while (lev < L && std::max(gr, gc) < (n >> lev)) ++lev;
   const int hg = n >> lev;
-  const int i = gr >= hg ? gr - hg : gr;
-  const int j = gc >= hg ? gc - hg : gc;
-  const int sh = L - lev, ht = 1 << sh;
+  const bool vert = gr >= hg, horz = gc >= hg;
+  const int i = vert ? gr - hg : gr;
+  const int j = horz ? gc - hg : gc;
+  const int sh = L - lev;
   const int I = i >> sh, J = j >> sh;
-  const int lr = (i & (ht - 1)) + (gr >= hg ? ht : 0);
-  const int lc = (j & (ht - 1)) + (gc >= hg ? ht : 0);
-  return ((I << L) + lr) * n + (J << L) + lc;
+  const int s = ((i & ((1 << sh) - 1)) << lev) + (vert ? 1 << (lev - 1) : 0);
+  const int c = ((j & ((1 << sh) - 1)) << lev) + (horz ? 1 << (lev - 1) : 0);
+  return ((I << L) + s) * n + (J << L) + c;
 }
 
 }  // namespace
+
+namespace firls {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int cnn_forward(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0);
+int cnn_image_side(const firls_cnn* c);
+int cnn_max_batch(const firls_cnn* c);
+bool cnn_ready(const firls_cnn* c);
+}  // namespace firls
 
 struct firls_handle {
   firls_config cfg{};
@@ -85,6 +101,30 @@ struct firls_handle {
   int32_t* h_list = nullptr;
   hipEvent_t ev = nullptr;
 
+  // graph replay of the per-outer-iteration launch blocks
+  bool use_graphs = true;
+  hipStream_t own = nullptr;          // work stream when the caller passes the null stream
+  hipEvent_t ev_in = nullptr;
+  struct GraphKey {
+    std::vector<int> counts;
+    int Tmax = -1;
+    double tau = -1.0;
+    void* ws = nullptr;
+    void* desc = nullptr;
+    hipStream_t stream = nullptr;
+    bool operator==(const GraphKey& o) const {
+      return counts == o.counts && Tmax == o.Tmax && tau == o.tau && ws == o.ws && desc == o.desc && stream == o.stream;
+    }
+  } gkey;
+  hipGraphExec_t g_prep = nullptr, g_pcg = nullptr;
+  // sub-batch size chosen by firls_autotune (0: the whole batch at once)
+  int chunk = 0;
+
+  // learned-start staging: zero-filled and network starts [S, n, n] complex,
+  // per-slice output pointers and a copy of the slice states
+  void* ws_learn = nullptr;
+  size_t ws_learn_cap = 0;
+
   // Opt-in per-launch timing (firls_profile): one event pair per launch.
   struct ProfRec {
     int cls, group, it, phase, count;
@@ -103,13 +143,24 @@ struct firls_handle {
     const size_t vec = align256((size_t)s.n * s.n * elt);
     const size_t nvec = s.psi == PSI_TV ? 6 : 4;
     return nvec * vec + 2 * align256((size_t)s.n_coef * relt) + align256((size_t)s.n_groups * relt) +
-           align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
+           align256((size_t)s.n * s.n / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
   }
 };
 
 namespace {
 
+void drop_graphs(firls_handle* h) {
+  if (h->g_prep) (void)hipGraphExecDestroy(h->g_prep);
+  if (h->g_pcg) (void)hipGraphExecDestroy(h->g_pcg);
+  h->g_prep = h->g_pcg = nullptr;
+  h->gkey = firls_handle::GraphKey{};
+}
+
 void free_batch(firls_handle* h) {
+  drop_graphs(h);
+  if (h->ws_learn) (void)hipFree(h->ws_learn);
+  h->ws_learn = nullptr;
+  h->ws_learn_cap = 0;
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_desc) (void)hipFree(h->d_desc);
   if (h->d_state) (void)hipFree(h->d_state);
@@ -129,6 +180,7 @@ void free_batch(firls_handle* h) {
 }
 
 int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
+  if (bytes > h->ws_cap || std::max(slices, 2) > h->cap_slices) drop_graphs(h);
   if (bytes > h->ws_cap) {
     HIPCHK(hipStreamSynchronize(st));
     if (h->ws) HIPCHK(hipFree(h->ws));
@@ -184,6 +236,8 @@ void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const 
   o += align256((size_t)s.n_coef * h->relt);
   D.W = base + o;
   o += align256((size_t)s.n_groups * h->relt);
+  D.mbits = reinterpret_cast<uint16_t*>(base + o);
+  o += align256((size_t)s.n * s.n / 8);
   D.parts = reinterpret_cast<double*>(base + o);
   D.n = s.n;
   D.shape = 0;
@@ -215,9 +269,9 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.precond = h->cfg.precond;
   P.eps = h->cfg.eps;
   P.tau = h->cfg.outer_tol;
-  const int R = rows_of(h->fp64);
+  const int R = band_rows(s.n);
   P.npq = s.n / R;
-  P.ndata = s.n / R;
+  P.ndata = s.n / strip_cols(h->fp64);
   P.nrz = s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC);
   P.nreg = (s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG;
   (void)shape_id;
@@ -258,8 +312,8 @@ hipEvent_t prof_event(firls_handle* h) {
 // Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.
 int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int R = rows_of(h->fp64);
-  if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.n / R, c), st);
+  const int C = strip_cols(h->fp64);
+  if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.n / band_rows(s.n), c), st);
   else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3((s.n * s.n + 4 * NT - 1) / (4 * NT), c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
@@ -269,26 +323,26 @@ int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipS
 // r0 = A^H b - S x (data term fused), then z0 and <r0, z0>.
 int launch_residual(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
-  KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, c), st);
-  KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / R, c), st);
-  KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / R, c), st);
-  if (haar) KLAUNCH(h, FIRLS_PROF_R0_UPDATE, s.sk->update_haar[UP_INIT], P, dim3(s.n / R, c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / band_rows(s.n), c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
+  KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / band_rows(s.n), c), st);
+  if (haar) KLAUNCH(h, FIRLS_PROF_R0_UPDATE, s.sk->update_haar[UP_INIT], P, dim3(s.n / band_rows(s.n), c), st);
   else KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
   return FIRLS_OK;
 }
 
 int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
   for (int k = 0; k < h->cfg.pcg_iters; ++k) {
     P.k = k;
-    KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / R, c), st);
-    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[COL_SP], P, dim3(s.n / R, c), st);
-    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / R, c), st);
-    if (haar) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar[UP_STEP], P, dim3(s.n / R, c), st);
+    KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / band_rows(s.n), c), st);
+    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[COL_SP], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / band_rows(s.n), c), st);
+    if (haar) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar[UP_STEP], P, dim3(s.n / band_rows(s.n), c), st);
     else KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
   }
   return FIRLS_OK;
@@ -320,8 +374,8 @@ int check_slice(const firls_handle* h, const firls_slice& sl) {
   return FIRLS_OK;
 }
 
-// The batched outer loop shared by every solve entry point.
-int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
+// The batched outer loop shared by every solve entry point (one sub-batch).
+int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
   if (ns <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
   if (ns > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
   if (!sl || !rep) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
@@ -360,7 +414,7 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
   HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
 
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   std::vector<std::vector<int>> act_pcg;
   h->ctx_phase = 0;
   h->ctx_it = 0;
@@ -378,12 +432,10 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     Params P = base_params(h, S, s, h->d_list + zlo[s]);
     h->ctx_group = s;
     h->ctx_count = c;
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.n / R, c), st);
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.n / R, c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
   }
-  for (int it = 0; it <= Tmax; ++it) {
-    h->ctx_it = it;
-    h->ctx_phase = 1;
+  auto enqueue_prep = [&]() -> int {
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
@@ -393,13 +445,14 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       P.tau = tau;
       h->ctx_group = s;
       h->ctx_count = c;
-      if ((rc = launch_weights(h, S, P, c, st))) return rc;
-      if ((rc = launch_residual(h, S, P, c, st))) return rc;
+      int r2;
+      if ((r2 = launch_weights(h, S, P, c, st))) return r2;
+      if ((r2 = launch_residual(h, S, P, c, st))) return r2;
       KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
     }
-    HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(h->ev, st));
-    h->ctx_phase = 2;
+    return FIRLS_OK;
+  };
+  auto enqueue_pcg = [&]() -> int {
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
@@ -407,8 +460,52 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       Params P = base_params(h, S, s, h->d_list + lo[s]);
       h->ctx_group = s;
       h->ctx_count = c;
-      if ((rc = launch_pcg(h, S, P, c, st))) return rc;
+      int r2;
+      if ((r2 = launch_pcg(h, S, P, c, st))) return r2;
     }
+    return FIRLS_OK;
+  };
+  // Every outer iteration launches the same two blocks with the same
+  // arguments, so they are captured once as graphs and replayed.
+  const bool graphs = h->use_graphs && !h->profiling && st != nullptr;
+  if (graphs) {
+    firls_handle::GraphKey key;
+    for (int s = 0; s < nsh; ++s) key.counts.push_back((int)by_shape[s].size());
+    key.Tmax = Tmax;
+    key.tau = tau;
+    key.ws = h->ws;
+    key.desc = h->d_desc;
+    key.stream = st;
+    if (!(key == h->gkey) || !h->g_prep || !h->g_pcg) {
+      drop_graphs(h);
+      hipGraph_t gp = nullptr, gq = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_prep();
+      hipError_t e1 = hipStreamEndCapture(st, &gp);
+      if (rc) return rc;
+      HIPCHK(e1);
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_pcg();
+      hipError_t e2 = hipStreamEndCapture(st, &gq);
+      if (rc) return rc;
+      HIPCHK(e2);
+      HIPCHK(hipGraphInstantiate(&h->g_prep, gp, nullptr, nullptr, 0));
+      HIPCHK(hipGraphInstantiate(&h->g_pcg, gq, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gp);
+      (void)hipGraphDestroy(gq);
+      h->gkey = key;
+    }
+  }
+  for (int it = 0; it <= Tmax; ++it) {
+    h->ctx_it = it;
+    h->ctx_phase = 1;
+    if (graphs) HIPCHK(hipGraphLaunch(h->g_prep, st));
+    else if ((rc = enqueue_prep())) return rc;
+    HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->ev, st));
+    h->ctx_phase = 2;
+    if (graphs) HIPCHK(hipGraphLaunch(h->g_pcg, st));
+    else if ((rc = enqueue_pcg())) return rc;
     HIPCHK(hipEventSynchronize(h->ev));
     int active = 0;
     act_pcg.emplace_back(nsh, 0);
@@ -440,13 +537,40 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
   return worst;
 }
 
+// Runs the slices in sub-batches of h->chunk (all at once when 0) on the
+// caller's stream, or on the library's own stream ordered after the null
+// stream when the caller passes the null stream (graphs need a capturable
+// stream).
+int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
+  hipStream_t ws = st;
+  if (!st && h->use_graphs) {
+    if (!h->own) {
+      HIPCHK(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(h->ev_in, nullptr));
+    HIPCHK(hipStreamWaitEvent(h->own, h->ev_in, 0));
+    ws = h->own;
+  }
+  const int chunk = h->chunk > 0 ? h->chunk : ns;
+  int worst = FIRLS_OK;
+  for (int c0 = 0; c0 < ns; c0 += chunk) {
+    const int cn = std::min(chunk, ns - c0);
+    int rc = run_chunk(h, ws, cn, sl + c0, rep + c0, Tmax, tau);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  if (ws != st) HIPCHK(hipStreamSynchronize(ws));
+  return worst;
+}
+
 int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   const int n = in.n;
   if (!size_supported(n)) return fail(FIRLS_E_UNSUPPORTED, "image side " + std::to_string(n) + " is not built");
   s.n = n;
   s.psi = in.psi;
   if (in.psi == FIRLS_PSI_HAAR) {
-    const int maxL = h->fp64 ? 3 : 4;
+    const int maxL = 4;
     if (in.levels < 1) return fail(FIRLS_E_INVALID, "Haar levels must be >= 1");
     if (in.levels > maxL) return fail(FIRLS_E_UNSUPPORTED, "Haar levels above " + std::to_string(maxL) + " are not built for this precision");
     if (n % (1 << in.levels)) return fail(FIRLS_E_INVALID, "n must be a multiple of 2^levels");
@@ -622,6 +746,8 @@ int firls_destroy(firls_handle* h) {
   free_batch(h);
   destroy_shapes(h);
   if (h->ev) (void)hipEventDestroy(h->ev);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->own) (void)hipStreamDestroy(h->own);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return FIRLS_OK;
@@ -686,10 +812,10 @@ int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void
   if ((rc = op_upload(h, st, 1))) return rc;
   const Shape& s = h->shapes[shape_id];
   Params P = base_params(h, s, shape_id, h->d_list);
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
-  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.n / R, 1), st);
-  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.n / C, 1), st);
+  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.n / band_rows(s.n), 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
 }
@@ -733,15 +859,15 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
   B.lambda = lambda;
   if ((rc = op_upload(h, st, 2))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   Params PA = base_params(h, s, shape_id, h->d_list);
   Params PB = base_params(h, s, shape_id, h->d_list + 1);
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
   if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
   PB.k = 0;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.n / R, 1), st);
-  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.n / R, 1), st);
-  LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.n / band_rows(s.n), 1), st);
+  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.n / C, 1), st);
+  LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.n / band_rows(s.n), 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
 }
@@ -767,13 +893,13 @@ int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint
   B.lambda = lambda;
   if ((rc = op_upload(h, st, 2))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   Params PA = base_params(h, s, shape_id, h->d_list);
   Params PB = base_params(h, s, shape_id, h->d_list + 1);
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
   if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
   PB.k = 0;
-  if (s.psi == PSI_HAAR) LAUNCH(s.sk->rowfwd[RF_PCG_HAAR], PB, dim3(s.n / R, 1), st);
+  if (s.psi == PSI_HAAR) LAUNCH(s.sk->rowfwd[RF_PCG_HAAR], PB, dim3(s.n / band_rows(s.n), 1), st);
   else LAUNCH(prec_kernels(h->fp64)->update_tv[UP_INIT], PB, dim3(PB.nrz, 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
@@ -793,20 +919,256 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const vo
   A.lambda = lambda;
   if ((rc = op_upload(h, st, 1))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int R = rows_of(h->fp64);
+  const int C = strip_cols(h->fp64);
   Params P = base_params(h, s, shape_id, h->d_list);
   P.Tmax = 0;
   P.tau = 0.0;
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
   if ((rc = launch_weights(h, s, P, 1, st))) return rc;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / R, 1), st);
-  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / R, 1), st);
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / band_rows(s.n), 1), st);
+  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / C, 1), st);
   LAUNCH(prec_kernels(h->fp64)->outer_check, P, dim3(1), st);
   HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   out3[0] = h->h_state[0].Fe;
   out3[1] = h->h_state[0].F;
   out3[2] = h->h_state[0].data;
+  return FIRLS_OK;
+}
+
+int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, int32_t n_slices,
+                                const firls_slice* slices, firls_report* reports, int32_t* used_learned) {
+  if (!h || !net) return fail(FIRLS_E_INVALID, "null handle or network");
+  g_err.clear();
+  if (h->fp64) return fail(FIRLS_E_UNSUPPORTED, "the learned start is built for FIRLS_FP32");
+  if (!cnn_ready(net)) return fail(FIRLS_E_INVALID, "network parameters not set");
+  if (n_slices <= 0 || n_slices > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices out of range");
+  if (!slices || !reports) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
+  const int n = cnn_image_side(net);
+  for (int i = 0; i < n_slices; ++i) {
+    int rc = check_slice(h, slices[i]);
+    if (rc) return rc;
+    if (h->shapes[slices[i].shape_id].n != n) return fail(FIRLS_E_INVALID, "every slice must have the network's image size");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int ns = n_slices;
+  const size_t np = (size_t)n * n;
+  const size_t stage = align256(np * 8 * ns);
+  const size_t need = 2 * stage + align256(sizeof(void*) * ns) + align256(sizeof(SliceState) * ns);
+  if (need > h->ws_learn_cap) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->ws_learn) HIPCHK(hipFree(h->ws_learn));
+    h->ws_learn = nullptr;
+    h->ws_learn_cap = 0;
+    if (hipMalloc(&h->ws_learn, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FIRLS_E_NOMEM, "staging allocation failed");
+    }
+    h->ws_learn_cap = need;
+  }
+  char* base = static_cast<char*>(h->ws_learn);
+  char* zf = base;
+  char* x0 = base + stage;
+  void** outs = reinterpret_cast<void**>(base + 2 * stage);
+  SliceState* st_zero = reinterpret_cast<SliceState*>(base + 2 * stage + align256(sizeof(void*) * ns));
+  // candidates evaluated through the batch machinery: descs whose x points
+  // into a staging buffer
+  std::vector<firls_slice> tmp(slices, slices + ns);
+  std::vector<size_t> off(ns);
+  size_t wneed = 0;
+  for (int i = 0; i < ns; ++i) {
+    off[i] = wneed;
+    wneed += h->slice_bytes(h->shapes[slices[i].shape_id]);
+  }
+  int rc = ensure_capacity(h, st, wneed, ns);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(st));
+  const int nsh = (int)h->shapes.size();
+  std::vector<std::vector<int>> by_shape(nsh);
+  for (int i = 0; i < ns; ++i) by_shape[slices[i].shape_id].push_back(i);
+  std::vector<int> lo(nsh);
+  int pos = 0;
+  for (int s = 0; s < nsh; ++s) {
+    lo[s] = pos;
+    for (int i : by_shape[s]) h->h_list[pos++] = i;
+  }
+  auto upload = [&](char* xbuf) -> int {
+    for (int i = 0; i < ns; ++i) {
+      tmp[i].x = xbuf + (size_t)i * np * 8;
+      fill_desc(h, h->h_desc[i], h->shapes[slices[i].shape_id], off[i], &tmp[i]);
+    }
+    HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
+    return FIRLS_OK;
+  };
+  auto evaluate = [&]() -> int {   // F_eps of every slice's x into the states
+    for (int s = 0; s < nsh; ++s) {
+      const int c = (int)by_shape[s].size();
+      if (!c) continue;
+      const Shape& S = h->shapes[s];
+      Params P = base_params(h, S, s, h->d_list + lo[s]);
+      P.Tmax = 0;
+      P.tau = 0.0;
+      LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
+      int r2 = launch_weights(h, S, P, c, st);
+      if (r2) return r2;
+      LAUNCH(S.sk->rowfwd[RF_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+      LAUNCH(S.sk->col[COL_R0], P, dim3(S.n / strip_cols(false), c), st);
+      LAUNCH(prec_kernels(false)->outer_check, P, dim3(c), st);
+    }
+    return FIRLS_OK;
+  };
+  const bool prof = h->profiling;
+  h->profiling = false;
+  // 1. zero-filled starts A^H b
+  if ((rc = upload(zf))) return rc;
+  for (int s = 0; s < nsh; ++s) {
+    const int c = (int)by_shape[s].size();
+    if (!c) continue;
+    const Shape& S = h->shapes[s];
+    Params P = base_params(h, S, s, h->d_list + lo[s]);
+    LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
+    LAUNCH(S.sk->col[COL_AHB], P, dim3(S.n / strip_cols(false), c), st);
+    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+  }
+  // 2. network starts x0 = zf + f(zf), in network batches
+  const int mb = cnn_max_batch(net);
+  for (int b0 = 0; b0 < ns; b0 += mb) {
+    const int bn = std::min(mb, ns - b0);
+    if ((rc = cnn_forward(net, st, bn, zf + (size_t)b0 * np * 8, x0 + (size_t)b0 * np * 8))) return rc;
+  }
+  // 3. objectives of both candidates, 4. keep the better one in each x
+  if ((rc = evaluate())) return rc;
+  HIPCHK(hipMemcpyAsync(st_zero, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
+  if ((rc = upload(x0))) return rc;
+  if ((rc = evaluate())) return rc;
+  std::vector<void*> hx(ns);
+  for (int i = 0; i < ns; ++i) hx[i] = slices[i].x;
+  HIPCHK(hipMemcpyAsync(outs, hx.data(), sizeof(void*) * ns, hipMemcpyHostToDevice, st));
+  cnn::ChooseArgs ca{st_zero, h->d_state, zf, x0, outs, n};
+  HIPCHK(cnn::launch_choose(ca, ns, st));
+  std::vector<SliceState> s0(ns), s1(ns);
+  HIPCHK(hipMemcpyAsync(s0.data(), st_zero, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(s1.data(), h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (used_learned)
+    for (int i = 0; i < ns; ++i) used_learned[i] = s1[i].Fe <= s0[i].Fe ? 1 : 0;
+  h->profiling = prof;
+  // 5. FIRLS from the chosen starts
+  for (int i = 0; i < ns; ++i) tmp[i] = slices[i], tmp[i].x_is_init = 1;
+  return run_batch(h, st, ns, tmp.data(), reports, h->cfg.max_outer, h->cfg.outer_tol);
+}
+
+int firls_set_graphs(firls_handle* h, int32_t enable) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  h->use_graphs = enable != 0;
+  drop_graphs(h);
+  return FIRLS_OK;
+}
+
+int firls_set_chunk(firls_handle* h, int32_t chunk) {
+  if (!h || chunk < 0) return fail(FIRLS_E_INVALID, "bad argument");
+  h->chunk = chunk;
+  return FIRLS_OK;
+}
+
+int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen) {
+  if (!h || !slices || n_slices <= 0) return fail(FIRLS_E_INVALID, "bad argument");
+  if (n_slices > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
+  g_err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < n_slices; ++i) {
+    int rc = check_slice(h, slices[i]);
+    if (rc) return rc;
+  }
+  // cache key: the batch's shape mix, precision, PCG length and batch size
+  std::ostringstream ks;
+  ks << "prec=" << (h->fp64 ? 64 : 32) << " K=" << h->cfg.pcg_iters << " slices=" << n_slices;
+  {
+    std::vector<int> cnt(h->shapes.size(), 0);
+    for (int i = 0; i < n_slices; ++i) cnt[slices[i].shape_id]++;
+    for (size_t s = 0; s < cnt.size(); ++s)
+      if (cnt[s]) ks << " n" << h->shapes[s].n << "psi" << h->shapes[s].psi << "L" << h->shapes[s].L << "x" << cnt[s];
+  }
+  const std::string key = ks.str();
+  const char* cache = std::getenv("FIRLS_TUNE_CACHE");
+  if (cache) {
+    std::ifstream in(cache);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t bar = line.rfind('|');
+      if (bar != std::string::npos && line.substr(0, bar) == key) {
+        h->chunk = std::atoi(line.c_str() + bar + 1);
+        if (chosen) *chosen = h->chunk;
+        return FIRLS_OK;
+      }
+    }
+  }
+  // snapshot every x (trials overwrite it) and time a few outer iterations
+  // per candidate sub-batch size; each candidate runs twice, the second run
+  // (graphs already captured) is timed
+  size_t bytes = 0;
+  std::vector<size_t> xb(n_slices);
+  for (int i = 0; i < n_slices; ++i) {
+    const int n = h->shapes[slices[i].shape_id].n;
+    xb[i] = (size_t)n * n * h->elt;
+    bytes += xb[i];
+  }
+  void* snap = nullptr;
+  if (hipMalloc(&snap, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FIRLS_E_NOMEM, "autotune snapshot allocation failed");
+  }
+  auto copy_all = [&](bool save) -> int {
+    size_t o = 0;
+    for (int i = 0; i < n_slices; ++i) {
+      char* sp = static_cast<char*>(snap) + o;
+      if (save) HIPCHK(hipMemcpyAsync(sp, slices[i].x, xb[i], hipMemcpyDeviceToDevice, st));
+      else HIPCHK(hipMemcpyAsync(slices[i].x, sp, xb[i], hipMemcpyDeviceToDevice, st));
+      o += xb[i];
+    }
+    return FIRLS_OK;
+  };
+  int rc = copy_all(true);
+  std::vector<int> cands = {0};
+  for (int c : {256, 128, 64, 32})
+    if (c < n_slices) cands.push_back(c);
+  std::vector<firls_report> rep(n_slices);
+  const int T = std::max(1, std::min(3, h->cfg.max_outer));
+  double best = 1e300;
+  int best_c = 0;
+  const bool prof = h->profiling;
+  h->profiling = false;
+  for (int c : cands) {
+    if (rc) break;
+    h->chunk = c;
+    double t = 0.0;
+    for (int rep_i = 0; rep_i < 2 && !rc; ++rep_i) {
+      if ((rc = copy_all(false))) break;
+      if (hipStreamSynchronize(st) != hipSuccess) { rc = fail(FIRLS_E_HIP, "sync failed"); break; }
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = run_batch(h, st, n_slices, slices, rep.data(), T, 0.0);
+      if (rc > 0) rc = 0;
+      if (hipStreamSynchronize(st) != hipSuccess) rc = fail(FIRLS_E_HIP, "sync failed");
+      t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!rc && t < best) {
+      best = t;
+      best_c = c;
+    }
+  }
+  h->profiling = prof;
+  if (!rc) rc = copy_all(false);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(snap);
+  if (rc) return rc;
+  h->chunk = best_c;
+  if (chosen) *chosen = best_c;
+  if (cache) {
+    std::ofstream out(cache, std::ios::app);
+    out << key << "|" << best_c << "\n";
+  }
   return FIRLS_OK;
 }
 

@@ -12,9 +12,20 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
   const SliceDesc& D = P.desc[s];
-  const int total = D.n * D.n;
+  const int n = D.n, total = n * n;
+  // count the samples and pack the mask: word [c16][row] holds columns
+  // 16 c16 .. 16 c16 + 15 of the row, bit c = column 16 c16 + c
   double cnt = 0.0;
-  for (int i = threadIdx.x; i < total; i += NT) cnt += D.mask[i] != 0 ? 1.0 : 0.0;
+  const int words = total / 16;
+  for (int w = threadIdx.x; w < words; w += NT) {
+    const int c16 = w / n, row = w - c16 * n;
+    const uint8_t* src = D.mask + (size_t)row * n + c16 * 16;
+    unsigned int bits = 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) bits |= (src[c] != 0 ? 1u : 0u) << c;
+    D.mbits[w] = (uint16_t)bits;
+    cnt += (double)__popc(bits);
+  }
   cnt = block_sum(cnt, red);
   if (threadIdx.x == 0) {
     SliceState& S = P.state[s];

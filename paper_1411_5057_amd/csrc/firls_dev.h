@@ -250,77 +250,71 @@ __device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src s
 }
 
 // ---------------------------------------------------------------------------
-// Tile-local orthonormal Haar on a band of ROWS x N values in LDS.
-// Every aligned 2^L x 2^L tile is transformed on its own: an L-level Haar
-// of the whole image only mixes pixels inside such tiles.  Within a tile
-// the coefficients are kept in the tile's own Mallat arrangement, so the
-// library's coefficient layout is the image layout with each tile replaced
-// by its transform.  One level maps a 2x2 block [a b; c d] of the current
-// approximation (side s) to (a+b+c+d)/2 at (i, j), (a-b+c-d)/2 at
-// (i, j + s/2), (a+b-c-d)/2 at (i + s/2, j) and (a-b-c+d)/2 at
-// (i + s/2, j + s/2); the matrix is symmetric and its own inverse.
+// Register-resident tile-local orthonormal Haar.
+//
+// An L-level Haar of the whole image only mixes pixels inside aligned
+// tiles of side 2^L, so every tile is transformed on its own.  A thread
+// holds v[s], s < 16, the 16 rows of one image column inside a 16-row
+// group; neighbouring columns sit in neighbouring lanes.  One level with
+// stride st = 2^(lev-1) maps each 2x2 block [a b; c d] of the current
+// approximation (rows s, s+st; columns c, c+st, s and c multiples of 2st) to
+//   left column : (a+b+c+d)/2 at row s, (a+b-c-d)/2 at row s+st
+//   right column: (a-b+c-d)/2 at row s, (a-b-c+d)/2 at row s+st,
+// keeping every coefficient on the pixel position it is computed on (the
+// in-place, interleaved layout).  This 2x2 map is symmetric and its own
+// inverse, so the inverse transform applies the same level step with the
+// levels in reverse order.  Rows pair inside the thread; columns pair with
+// lane ^ st through cross-lane shuffles.  The library's coefficient layout
+// (weights d, |Psi x|^2) is this in-place layout.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int ROWS, bool INV>
-__device__ __forceinline__ void haar_tiles(cplx<T>* lds, int L) {
-  using Lay = LdsLayout<N>;
-  const int tsz = 1 << L;
-  const int tiles_x = N >> L;
-  for (int it = 0; it < L; ++it) {
-    const int lev = INV ? (L - it) : (it + 1);     // 1 = finest
-    const int s = tsz >> (lev - 1);                // side of the block being split
-    const int h = s >> 1;
-    const int per_tile = h * h;
-    const int total = (ROWS >> L) * tiles_x * per_tile;
-    constexpr int MAXB = (ROWS * N / 4 + NT - 1) / NT;
-    cplx<T> a[MAXB], b[MAXB], c[MAXB], d[MAXB];
+template <typename T>
+__device__ __forceinline__ cplx<T> shfl_xor_c(cplx<T> v, int m) {
+  return cplx<T>{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+}
+
+template <int ST, typename T>
+__device__ __forceinline__ void haar_level(cplx<T> (&v)[16], int col) {
+  const bool active = (col & (ST - 1)) == 0;
+  const bool right = (col & ST) != 0;
+  const T h = (T)0.5;
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-      const int blk = threadIdx.x + i * NT;
-      if (blk >= total) break;
-      const int tile = blk / per_tile, w = blk - tile * per_tile;
-      const int bi = w / h, bj = w - bi * h;
-      const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-      const int r0 = ty * tsz, c0 = tx * tsz;
-      if (!INV) {
-        a[i] = lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj)];
-        b[i] = lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj + 1)];
-        c[i] = lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj)];
-        d[i] = lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj + 1)];
-      } else {
-        a[i] = lds[Lay::at(r0 + bi, c0 + bj)];
-        b[i] = lds[Lay::at(r0 + bi, c0 + h + bj)];
-        c[i] = lds[Lay::at(r0 + h + bi, c0 + bj)];
-        d[i] = lds[Lay::at(r0 + h + bi, c0 + h + bj)];
-      }
+  for (int s = 0; s < 16; s += 2 * ST) {
+    const cplx<T> S = v[s] + v[s + ST];
+    const cplx<T> D = v[s] - v[s + ST];
+    const cplx<T> So = shfl_xor_c(S, ST);
+    const cplx<T> Do = shfl_xor_c(D, ST);
+    if (active) {
+      v[s] = (right ? So - S : S + So) * h;
+      v[s + ST] = (right ? Do - D : D + Do) * h;
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-      const int blk = threadIdx.x + i * NT;
-      if (blk >= total) break;
-      const int tile = blk / per_tile, w = blk - tile * per_tile;
-      const int bi = w / h, bj = w - bi * h;
-      const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-      const int r0 = ty * tsz, c0 = tx * tsz;
-      const T half = (T)0.5;
-      cplx<T> apb = a[i] + b[i], amb = a[i] - b[i], cpd = c[i] + d[i], cmd = c[i] - d[i];
-      cplx<T> o0 = (apb + cpd) * half, o1 = (amb + cmd) * half;
-      cplx<T> o2 = (apb - cpd) * half, o3 = (amb - cmd) * half;
-      if (!INV) {
-        lds[Lay::at(r0 + bi, c0 + bj)] = o0;
-        lds[Lay::at(r0 + bi, c0 + h + bj)] = o1;
-        lds[Lay::at(r0 + h + bi, c0 + bj)] = o2;
-        lds[Lay::at(r0 + h + bi, c0 + h + bj)] = o3;
-      } else {
-        lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj)] = o0;
-        lds[Lay::at(r0 + 2 * bi, c0 + 2 * bj + 1)] = o1;
-        lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj)] = o2;
-        lds[Lay::at(r0 + 2 * bi + 1, c0 + 2 * bj + 1)] = o3;
-      }
-    }
-    __syncthreads();
   }
 }
+
+template <bool INV, typename T>
+__device__ __forceinline__ void haar_col(cplx<T> (&v)[16], int L, int col) {
+  if (!INV) {
+    if (L >= 1) haar_level<1>(v, col);
+    if (L >= 2) haar_level<2>(v, col);
+    if (L >= 3) haar_level<4>(v, col);
+    if (L >= 4) haar_level<8>(v, col);
+  } else {
+    if (L >= 4) haar_level<8>(v, col);
+    if (L >= 3) haar_level<4>(v, col);
+    if (L >= 2) haar_level<2>(v, col);
+    if (L >= 1) haar_level<1>(v, col);
+  }
+}
+
+// Work units of a band of ROWS rows and N columns: unit u covers column
+// u % N of the 16-row group u / N.  Thread t owns units t, t + NT, ...
+template <int N, int ROWS>
+struct Units {
+  static constexpr int COUNT = (ROWS / 16) * N;
+  static constexpr int PER = (COUNT + NT - 1) / NT;
+  __device__ __forceinline__ static bool valid(int k) { return COUNT % NT == 0 || (int)threadIdx.x + k * NT < COUNT; }
+  __device__ __forceinline__ static int col(int k) { return ((int)threadIdx.x + k * NT) % N; }
+  __device__ __forceinline__ static int row(int k) { return (((int)threadIdx.x + k * NT) / N) * 16; }
+};
 
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions.

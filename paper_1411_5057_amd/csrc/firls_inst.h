@@ -5,9 +5,15 @@
 
 namespace firls {
 
+// Dynamic LDS of the row passes (band_rows(N) lines) and of the column
+// pass (strip_cols lines).
 template <typename T, int N>
 constexpr size_t lds_bytes() {
-  return (size_t)Geo<T>::ROWS * LdsLayout<N>::LS * sizeof(cplx<T>);
+  return (size_t)band_rows(N) * LdsLayout<N>::LS * sizeof(cplx<T>);
+}
+template <typename T, int N>
+constexpr size_t lds_col_bytes() {
+  return (size_t)Geo<T>::COLS * LdsLayout<N>::LS * sizeof(cplx<T>);
 }
 
 template <class K>
@@ -22,14 +28,20 @@ hipError_t launch_dyn(K kern, size_t lds, const Params& P, dim3 g, hipStream_t s
     return launch_dyn(KERNEL<T, N, M>, lds_bytes<T, N>(), P, g, st);           \
   }
 FIRLS_DYN_LAUNCHER(L_rowfwd, k_rowfwd)
-FIRLS_DYN_LAUNCHER(L_col, k_col)
 FIRLS_DYN_LAUNCHER(L_rowinv, k_rowinv)
-FIRLS_DYN_LAUNCHER(L_update_haar, k_update_haar)
 #undef FIRLS_DYN_LAUNCHER
 
+template <typename T, int N, int M>
+hipError_t L_col(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_col<T, N, M>, lds_col_bytes<T, N>(), P, g, st);
+}
+template <typename T, int N, int M>
+hipError_t L_update_haar(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_update_haar<T, N, M>, 0, P, g, st);
+}
 template <typename T, int N>
 hipError_t L_psi_sq_haar(const Params& P, dim3 g, hipStream_t st) {
-  return launch_dyn(k_psi_sq_haar<T, N>, lds_bytes<T, N>(), P, g, st);
+  return launch_dyn(k_psi_sq_haar<T, N>, 0, P, g, st);
 }
 
 template <class K>
@@ -43,17 +55,15 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowfwd<T, N, RF_PLAIN>, b);
   allow_lds(k_rowfwd<T, N, RF_PCG_HAAR>, b);
   allow_lds(k_rowfwd<T, N, RF_PCG_Z>, b);
-  allow_lds(k_col<T, N, COL_SP>, b);
-  allow_lds(k_col<T, N, COL_R0>, b);
-  allow_lds(k_col<T, N, COL_AHB>, b);
+  const size_t bc = lds_col_bytes<T, N>();
+  allow_lds(k_col<T, N, COL_SP>, bc);
+  allow_lds(k_col<T, N, COL_R0>, bc);
+  allow_lds(k_col<T, N, COL_AHB>, bc);
   allow_lds(k_rowinv<T, N, RI_PLAIN>, b);
   allow_lds(k_rowinv<T, N, RI_SP_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
   allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
-  allow_lds(k_psi_sq_haar<T, N>, b);
-  allow_lds(k_update_haar<T, N, UP_INIT>, b);
-  allow_lds(k_update_haar<T, N, UP_STEP>, b);
   SizeKernels k{};
   k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;
   k.rowfwd[RF_PCG_HAAR] = L_rowfwd<T, N, RF_PCG_HAAR>;

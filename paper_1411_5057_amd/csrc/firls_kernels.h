@@ -12,14 +12,16 @@
 // so q = S p with S of eq. (15) / eq. (39).  The FP64 partial sums of each
 // inner product are written one per workgroup and summed, in index order,
 // by every workgroup that needs the scalar.
+//
+// Row passes work on bands of band_rows(n) full rows; the Haar parts run in
+// registers on 16-row tile columns (haar_col), the FFT parts through LDS.
 #pragma once
 #include "firls_dev.h"
 
 namespace firls {
 
 template <typename T> struct Geo {
-  static constexpr int ROWS = sizeof(T) == 4 ? 16 : 8;   // band height of row passes
-  static constexpr int COLS = ROWS;                      // strip width of column passes
+  static constexpr int COLS = strip_cols(sizeof(T) == 8);   // strip width of column passes
 };
 
 #define FIRLS_SLICE_PROLOGUE(idx)                 \
@@ -43,9 +45,10 @@ __device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, cons
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
-  constexpr int ROWS = Geo<T>::ROWS;
+  constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
+  using U = Units<N, ROWS>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
@@ -67,23 +70,28 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     const T bt = (T)beta;
     C* p = static_cast<C*>(D.p) + off;
     if constexpr (MODE == RF_PCG_HAAR) {
+      // z = Phi^T ((Phi r) / (rho + lambda d)) in registers, p = z + beta p
       const C* r = static_cast<const C*>(D.r[0]) + off;
       const T* d = static_cast<const T*>(D.d) + off;
       const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = r[i];
-      __syncthreads();
-      haar_tiles<T, N, ROWS, false>(lds, P.L);
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
-        const int a = Lay::at(i / N, i % N);
-        lds[a] = lds[a] * ((T)1 / (rho + lam * d[i]));
-      }
-      __syncthreads();
-      haar_tiles<T, N, ROWS, true>(lds, P.L);
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
-        const int a = Lay::at(i / N, i % N);
-        const C pn = P.k > 0 ? lds[a] + p[i] * bt : lds[a];   // p is not read at k = 0
-        p[i] = pn;
-        lds[a] = pn;
+#pragma unroll
+      for (int k = 0; k < U::PER; ++k) {
+        if (!U::valid(k)) continue;
+        const int col = U::col(k), row = U::row(k);
+        C v[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) v[s] = r[(row + s) * N + col];
+        haar_col<false>(v, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) v[s] = v[s] * ((T)1 / (rho + lam * d[(row + s) * N + col]));
+        haar_col<true>(v, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int g = (row + s) * N + col;
+          const C pn = P.k > 0 ? v[s] + p[g] * bt : v[s];   // p is not read at k = 0
+          p[g] = pn;
+          lds[Lay::at(row + s, col)] = pn;
+        }
       }
     } else {
       const C* z = static_cast<const C*>(D.z) + off;
@@ -111,7 +119,10 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   const int col0 = blockIdx.x * COLS;
   const C* tw = static_cast<const C*>(P.tw);
   C* t = static_cast<C*>(D.t);
-  const uint8_t* m = D.mask;
+  // sampled(c, row): bit of the packed mask word of this strip and row
+  const uint16_t* mw = D.mbits + (size_t)(col0 >> 4) * N;
+  const int sh0 = col0 & 15;
+  auto sampled = [&](int c, int row) { return (mw[row] >> (sh0 + c)) & 1u; };
   auto gsrc = [&](int c, int row) { return t[(size_t)row * N + col0 + c]; };
   auto gdst = [&](int c, int row, C v) { t[(size_t)row * N + col0 + c] = v; };
   LdsIO<T, N> io{lds};
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   if constexpr (MODE == COL_SP) {
     const T sc = sn * sn;
     fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
-      lds[Lay::at(c, row)] = m[(size_t)row * N + col0 + c] ? v * sc : C{(T)0, (T)0};
+      lds[Lay::at(c, row)] = sampled(c, row) ? v * sc : C{(T)0, (T)0};
     });
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else if constexpr (MODE == COL_R0) {
@@ -130,7 +141,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
       const size_t g = (size_t)row * N + col0 + c;
       C u{(T)0, (T)0};
-      if (m[g]) {
+      if (sampled(c, row)) {
         u = b[g] - v * sn;
         acc += cabs2(u);
         u = u * sn;
@@ -144,7 +155,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     const C* b = static_cast<const C*>(D.b);
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, [&](int c, int row) {
       const size_t g = (size_t)row * N + col0 + c;
-      return m[g] ? b[g] * sn : C{(T)0, (T)0};
+      return sampled(c, row) ? b[g] * sn : C{(T)0, (T)0};
     }, gdst);
   }
 }
@@ -152,9 +163,10 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
-  constexpr int ROWS = Geo<T>::ROWS;
+  constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
+  using U = Units<N, ROWS>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
@@ -178,24 +190,27 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
     const T sgn = SP ? (T)1 : (T)-1;
     double acc = 0.0;
     if constexpr (HAAR) {
+      // A^H A part into LDS, then lambda Phi^T (d * Phi v) in registers
+      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, LdsIO<T, N>{lds});
       const T* d = static_cast<const T*>(D.d) + off;
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = v[i];
-      __syncthreads();
-      haar_tiles<T, N, ROWS, false>(lds, P.L);
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
-        const int a = Lay::at(i / N, i % N);
-        lds[a] = lds[a] * (lam * d[i]);
+#pragma unroll
+      for (int k = 0; k < U::PER; ++k) {
+        if (!U::valid(k)) continue;
+        const int col = U::col(k), row = U::row(k);
+        C a[16], w[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) w[s] = a[s] = v[(row + s) * N + col];
+        haar_col<false>(w, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) w[s] = w[s] * (lam * sgn * d[(row + s) * N + col]);
+        haar_col<true>(w, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const C o = lds[Lay::at(row + s, col)] + w[s];
+          out[(row + s) * N + col] = o;
+          if (SP) acc += cdot(a[s], o);
+        }
       }
-      __syncthreads();
-      haar_tiles<T, N, ROWS, true>(lds, P.L);
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) out[i] = lds[Lay::at(i / N, i % N)] * sgn;
-      __syncthreads();
-      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
-        const int i = l * N + q;
-        const C o = out[i] + val;
-        out[i] = o;
-        if (SP) acc += cdot(v[i], o);
-      });
     } else {
       const T* w1 = static_cast<const T*>(D.d);
       const T* w2 = w1 + (size_t)N * N;
@@ -214,59 +229,71 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 }
 
 // ---------------------------------------------------------------------------
-// |Phi x|^2 per coefficient (Haar, tile-major layout).
+// |Phi x|^2 per coefficient (Haar, in-place coefficient layout).
 template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
-  constexpr int ROWS = Geo<T>::ROWS;
+  constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
-  using Lay = LdsLayout<N>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* lds = reinterpret_cast<C*>(smem);
+  using U = Units<N, ROWS>;
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   const C* x = static_cast<const C*>(D.x) + off;
   T* sq = static_cast<T*>(D.sq) + off;
-  for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = x[i];
-  __syncthreads();
-  haar_tiles<T, N, ROWS, false>(lds, P.L);
-  for (int i = threadIdx.x; i < ROWS * N; i += NT) sq[i] = (T)cabs2(lds[Lay::at(i / N, i % N)]);
+#pragma unroll
+  for (int k = 0; k < U::PER; ++k) {
+    if (!U::valid(k)) continue;
+    const int col = U::col(k), row = U::row(k);
+    C v[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = x[(row + s) * N + col];
+    haar_col<false>(v, P.L, col);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) sq[(row + s) * N + col] = (T)cabs2(v[s]);
+  }
 }
 
 // Haar PCG update: alpha step (UP_STEP) and <r, z> = sum |Phi r|^2 / (rho + lambda d).
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(NT) void k_update_haar(Params P) {
-  constexpr int ROWS = Geo<T>::ROWS;
+  constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
-  using Lay = LdsLayout<N>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* lds = reinterpret_cast<C*>(smem);
+  using U = Units<N, ROWS>;
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   C* r = static_cast<C*>(D.r[0]) + off;
   const T* d = static_cast<const T*>(D.d) + off;
+  T al = (T)0;
   if constexpr (MODE == UP_STEP) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
-    const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
-    C* x = static_cast<C*>(D.x) + off;
-    const C* p = static_cast<const C*>(D.p) + off;
-    const C* q = static_cast<const C*>(D.q) + off;
-    for (int i = threadIdx.x; i < ROWS * N; i += NT) {
-      x[i] = x[i] + p[i] * al;
-      const C rn = r[i] - q[i] * al;
-      r[i] = rn;
-      lds[Lay::at(i / N, i % N)] = rn;
-    }
-  } else {
-    for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = r[i];
+    al = (T)(pq > 0.0 ? rz / pq : 0.0);
   }
-  __syncthreads();
-  haar_tiles<T, N, ROWS, false>(lds, P.L);
+  C* x = static_cast<C*>(D.x) + off;
+  const C* p = static_cast<const C*>(D.p) + off;
+  const C* q = static_cast<const C*>(D.q) + off;
   const double rho = P.state[s_].rho, lam = D.lambda;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < ROWS * N; i += NT)
-    acc += cabs2(lds[Lay::at(i / N, i % N)]) / (rho + lam * (double)d[i]);
+#pragma unroll
+  for (int k = 0; k < U::PER; ++k) {
+    if (!U::valid(k)) continue;
+    const int col = U::col(k), row = U::row(k);
+    C v[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int g = (row + s) * N + col;
+      if (MODE == UP_STEP) {
+        x[g] = x[g] + p[g] * al;
+        v[s] = r[g] - q[g] * al;
+        r[g] = v[s];
+      } else {
+        v[s] = r[g];
+      }
+    }
+    haar_col<false>(v, P.L, col);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc += cabs2(v[s]) / (rho + lam * (double)d[(row + s) * N + col]);
+  }
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[blockIdx.x] = tot;
 }

@@ -11,6 +11,14 @@ constexpr int GROUPS_PER_WG = 1024;
 constexpr int TV_TR = 16;        // TV preconditioner tile rows
 constexpr int TV_TC = 32;        // TV preconditioner tile columns
 
+// Rows per workgroup of the row passes for an n x n image: a multiple of 16
+// (one Haar tile row of side 16) chosen so a band holds about 4096 pixels.
+__host__ __device__ constexpr int band_rows(int n) {
+  return n >= 192 ? 16 : ((n == 128 || n == 96) ? 32 : n);
+}
+// Columns per workgroup of the column pass.
+__host__ __device__ constexpr int strip_cols(bool fp64) { return fp64 ? 8 : 16; }
+
 // Slots of the per-slice FP64 partial-sum area.  Every slot holds up to
 // PMAX partials, each written by exactly one workgroup, and every consumer
 // sums them in index order, so all reductions are deterministic.
@@ -49,6 +57,7 @@ struct SliceDesc {
   void* d;
   void* sq;
   void* W;
+  uint16_t* mbits;   // mask bits: word [c16][row] = mask[row][16 c16 .. 16 c16 + 15]
   double* parts;
   double lambda;
   int32_t n;

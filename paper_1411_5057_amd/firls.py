@@ -36,6 +36,9 @@ EXPORTED = (
     "firls_solve_batched", "firls_op_adjoint", "firls_op_weights",
     "firls_op_system", "firls_op_precond", "firls_op_objective",
     "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
+    "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
+    "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
+    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_autotune",
 )
 PROF_CLASSES = 14
 
@@ -99,6 +102,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_profile": ([vp, i32], ctypes.c_int),
         "firls_profile_read": ([vp, i32, ctypes.POINTER(firls_kernel_stat)], ctypes.c_int),
         "firls_last_error": ([], ctypes.c_char_p),
+        "firls_set_graphs": ([vp, i32], ctypes.c_int),
+        "firls_set_chunk": ([vp, i32], ctypes.c_int),
+        "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32)], ctypes.c_int),
+        "firls_cnn_param_count": ([], ctypes.c_int32),
+        "firls_cnn_create": ([i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "firls_cnn_destroy": ([vp], ctypes.c_int),
+        "firls_cnn_set_params": ([vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "firls_cnn_get_params": ([vp, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+        "firls_cnn_forward": ([vp, vp, i32, vp, vp], ctypes.c_int),
+        "firls_cnn_gradients": ([vp, vp, i32, vp, vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(dbl)], ctypes.c_int),
+        "firls_cnn_train_step": ([vp, vp, i32, vp, vp, ctypes.c_float, ctypes.POINTER(dbl)], ctypes.c_int),
+        "firls_solve_batched_learned": ([vp, vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report),
+                                         ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -193,6 +209,114 @@ def firls_profile_read(h) -> dict:
                                    "ms": arr[i].ms} for i in range(m)}
 
 
+def firls_cnn_param_count() -> int:
+    return int(load().firls_cnn_param_count())
+
+
+def firls_cnn_create(n: int, max_batch: int):
+    h = ctypes.c_void_p()
+    _check(load().firls_cnn_create(n, max_batch, ctypes.byref(h)), "firls_cnn_create")
+    return h
+
+
+def firls_cnn_destroy(h) -> int:
+    return load().firls_cnn_destroy(h)
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def firls_cnn_set_params(h, params: np.ndarray) -> int:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == firls_cnn_param_count()
+    return _check(load().firls_cnn_set_params(h, _fptr(p)), "firls_cnn_set_params")
+
+
+def firls_cnn_get_params(h) -> np.ndarray:
+    p = np.empty(firls_cnn_param_count(), dtype=np.float32)
+    _check(load().firls_cnn_get_params(h, _fptr(p)), "firls_cnn_get_params")
+    return p
+
+
+def firls_cnn_forward(h, stream, batch, zf, x0) -> int:
+    return _check(load().firls_cnn_forward(h, stream, batch, zf, x0), "firls_cnn_forward")
+
+
+def firls_cnn_gradients(h, stream, batch, zf, label):
+    g = np.empty(firls_cnn_param_count(), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(load().firls_cnn_gradients(h, stream, batch, zf, label, _fptr(g), ctypes.byref(loss)),
+           "firls_cnn_gradients")
+    return g, loss.value
+
+
+def firls_cnn_train_step(h, stream, batch, zf, label, lr: float) -> float:
+    loss = ctypes.c_double()
+    _check(load().firls_cnn_train_step(h, stream, batch, zf, label, float(lr), ctypes.byref(loss)),
+           "firls_cnn_train_step")
+    return loss.value
+
+
+def firls_solve_batched_learned(h, net, stream, n, slices, reports, used) -> int:
+    return _check(load().firls_solve_batched_learned(h, net, stream, n, slices, reports, used),
+                  "firls_solve_batched_learned")
+
+
+def flatten_params(layers) -> np.ndarray:
+    """[(W [3,3,cin,cout], b [cout]) x 5] -> the ABI's float32 parameter order."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float64).ravel(), np.asarray(b, np.float64).ravel()])
+                           for W, b in layers]).astype(np.float32)
+
+
+def unflatten_params(flat: np.ndarray, channels=(2, 32, 32, 32, 32, 2)):
+    out, o = [], 0
+    for i in range(5):
+        cin, cout = channels[i], channels[i + 1]
+        W = flat[o:o + 9 * cin * cout].reshape(3, 3, cin, cout)
+        o += 9 * cin * cout
+        b = flat[o:o + cout]
+        o += cout
+        out.append((W.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+class Net:
+    """Owns a firls_cnn (warm-start network for n x n images)."""
+
+    def __init__(self, n: int, max_batch: int, params: Optional[np.ndarray] = None):
+        self.n, self.max_batch = n, max_batch
+        self.handle = firls_cnn_create(n, max_batch)
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if self.handle:
+            firls_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        firls_cnn_set_params(self.handle, params)
+
+    def get_params(self) -> np.ndarray:
+        return firls_cnn_get_params(self.handle)
+
+    def forward(self, zf, x0, stream=None):
+        firls_cnn_forward(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(x0))
+
+    def gradients(self, zf, label, stream=None):
+        return firls_cnn_gradients(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(label))
+
+    def train_step(self, zf, label, lr, stream=None) -> float:
+        return firls_cnn_train_step(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(label), lr)
+
+
 # ---------------------------------------------------------------------------
 # Convenience layer over torch tensors
 # ---------------------------------------------------------------------------
@@ -283,6 +407,41 @@ class Solver:
 
     def objective(self, b, mask, lam, x, shape_id=0, stream=None):
         return firls_op_objective(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
+
+    def solve_batched_learned(self, net: "Net", items: List[dict], stream=None):
+        """Like solve_batched, started from the network (returns reports and
+        the per-slice flag of whether the learned start was kept)."""
+        n = len(items)
+        arr = (firls_slice * n)()
+        for i, it in enumerate(items):
+            arr[i] = firls_slice(int(it.get("shape_id", 0)), 1, float(it["lam"]), _ptr(it["b"]),
+                                 _ptr(it["mask"]), _ptr(it["x"]))
+        reps = (firls_report * n)()
+        used = (ctypes.c_int32 * n)()
+        firls_solve_batched_learned(self.handle, net.handle, _stream(stream), n, arr, reps, used)
+        return [r.as_dict() for r in reps], [int(u) for u in used]
+
+    def _slices(self, items, init=None):
+        n = len(items)
+        arr = (firls_slice * n)()
+        for i, it in enumerate(items):
+            x_init = int(bool(it.get("x_is_init", False))) if init is None else init
+            arr[i] = firls_slice(int(it.get("shape_id", 0)), x_init, float(it["lam"]), _ptr(it["b"]),
+                                 _ptr(it["mask"]), _ptr(it["x"]))
+        return arr
+
+    def set_graphs(self, enable: bool):
+        _check(load().firls_set_graphs(self.handle, int(enable)), "firls_set_graphs")
+
+    def set_chunk(self, chunk: int):
+        _check(load().firls_set_chunk(self.handle, int(chunk)), "firls_set_chunk")
+
+    def autotune(self, items: List[dict], stream=None) -> int:
+        arr = self._slices(items)
+        chosen = ctypes.c_int32()
+        _check(load().firls_autotune(self.handle, _stream(stream), len(items), arr, ctypes.byref(chosen)),
+               "firls_autotune")
+        return chosen.value
 
     def profile(self, enable: bool):
         firls_profile(self.handle, enable)

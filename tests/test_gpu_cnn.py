@@ -1,0 +1,128 @@
+"""GPU parity of the warm-start network kernels against the FP64 oracle with
+bfloat16 emulation.
+
+Bars: network output f(zf) to 1e-3 relative L2 (bfloat16 outputs), weight
+gradients to 1e-2 relative L2 per layer (FP32 split-K sums of bfloat16
+products), one Adam step exact to FP32 rounding, and FIRLS finished from the
+learned start reaching the oracle's objective to 1e-5.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn
+from oracle.firls import Operators, firls
+from tests.gpu_util import dev_complex, dev_mask, shape_of, to_np, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def make_params(seed=3):
+    p = cnn.init_params(seed)
+    rs = np.random.default_rng(seed + 100)
+    p[4] = (p[4][0] * 10.0, rs.standard_normal(2) * 0.05)
+    p = [(W, rs.standard_normal(b.shape) * 0.05 if i < 4 else b) for i, (W, b) in enumerate(p)]
+    from paper_1411_5057_amd import firls as F
+    flat = F.flatten_params(p)
+    return flat, F.unflatten_params(flat)
+
+
+def zero_filled(n, batch, seed):
+    rs = np.random.default_rng(seed)
+    return 0.5 * (rs.standard_normal((batch, n, n)) + 1j * rs.standard_normal((batch, n, n)))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("n,batch", [(32, 1), (64, 3), (256, 2)])
+def test_forward(n, batch):
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    flat, params = make_params()
+    zf = zero_filled(n, batch, n + batch)
+    net = F.Net(n, batch, flat)
+    zt = dev_complex(zf, "fp32")
+    x0 = torch.empty_like(zt)
+    net.forward(zt, x0)
+    zfr = to_np(zt)                                   # the FP32 values the GPU saw
+    ref, _ = cnn.forward(params, zfr, bf16_mode=True)
+    assert rel(to_np(x0) - zfr, ref - zfr) < 1e-3
+
+
+@pytest.mark.parametrize("n,batch", [(32, 2), (64, 2)])
+def test_gradients(n, batch):
+    from paper_1411_5057_amd import firls as F
+    flat, params = make_params(5)
+    zf = zero_filled(n, batch, 7)
+    rs = np.random.default_rng(8)
+    label = zf + 0.2 * (rs.standard_normal(zf.shape) + 1j * rs.standard_normal(zf.shape))
+    net = F.Net(n, batch, flat)
+    zt, lt = dev_complex(zf, "fp32"), dev_complex(label, "fp32")
+    g, loss = net.gradients(zt, lt)
+    zfr, lr_ = to_np(zt), to_np(lt)
+    x0, cache = cnn.forward(params, zfr, bf16_mode=True)
+    ref_loss = cnn.loss(x0, lr_)
+    grads = cnn.backward(cache, cnn.loss_grad(x0, lr_))
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    gg = F.unflatten_params(g)
+    for layer in range(5):
+        assert rel(gg[layer][0], grads[layer][0]) < 1e-2, layer
+        assert rel(gg[layer][1], grads[layer][1]) < 1e-2, layer
+
+
+def test_adam_step():
+    from paper_1411_5057_amd import firls as F
+    flat, _ = make_params(9)
+    zf = zero_filled(32, 2, 10)
+    label = 0.9 * zf
+    net = F.Net(32, 2, flat)
+    zt, lt = dev_complex(zf, "fp32"), dev_complex(label, "fp32")
+    g, _ = net.gradients(zt, lt)
+    net.train_step(zt, lt, 1e-3)
+    after = net.get_params()
+    expect, _, _ = cnn.adam(flat.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, lr=1e-3)
+    np.testing.assert_allclose(after, expect, rtol=1e-5, atol=1e-6)
+
+
+def test_learned_solve_reaches_oracle_optimum():
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    flat, params = make_params(11)
+    flat = flat.copy()
+    probs = [synth.make_problem(64, 300 + i, psi="haar", levels=4, groups="quadtree", lam=0.035,
+                                sigma=0.01, frac=0.2) for i in range(3)]
+    T, tau = 80, 1e-8
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=3, max_outer=T, pcg_iters=20, outer_tol=tau)
+    net = F.Net(64, 3, flat)
+    items = []
+    for p in probs:
+        b = dev_complex(p.b, "fp32")
+        items.append(dict(b=b, mask=dev_mask(p.mask), x=torch.zeros_like(b), lam=p.lam))
+    reps, used = s.solve_batched_learned(net, items)
+    for p, it, rep in zip(probs, items, reps):
+        ops = Operators.from_problem(p)
+        zf = ops.AHb()
+        x0, _ = cnn.forward(params, zf[None], bf16_mode=True)
+        start = x0[0] if ops.objective(x0[0])[0] <= ops.objective(zf)[0] else zf
+        ref = firls(ops, T, 20, tau=tau, x1=start)
+        fe = ops.objective(to_np(it["x"]))[0]
+        assert abs(fe - ref.F_eps) <= 1e-5 * ref.F_eps
+
+
+def test_bad_network_falls_back_to_zero_filled():
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    flat, _ = make_params(12)
+    flat = flat * 50.0                                   # a network that makes things worse
+    p = synth.make_problem(64, 400, psi="haar", levels=4, groups="quadtree", lam=0.035, sigma=0.01, frac=0.2)
+    s = F.Solver([shape_of(p)], prec="fp32", max_slices=1, max_outer=5, pcg_iters=20)
+    net = F.Net(64, 1, flat)
+    b = dev_complex(p.b, "fp32")
+    x = torch.zeros_like(b)
+    reps, used = s.solve_batched_learned(net, [dict(b=b, mask=dev_mask(p.mask), x=x, lam=p.lam)])
+    assert used == [0]
+    ops = Operators.from_problem(p)
+    ref = firls(ops, 5, 20)
+    assert abs(ops.objective(to_np(x))[0] - ref.F_eps) <= 1e-5 * ref.F_eps

@@ -137,3 +137,65 @@ def test_full_size_tree_config():
     iterations, compared over the whole image."""
     p = synth.cfg1(0)
     check(p, "fp32", 5, 20)
+
+
+def _batch(torch, probs):
+    from paper_1411_5057_amd import firls as F
+    items = []
+    for p in probs:
+        b = dev_complex(p.b, "fp32")
+        items.append(dict(b=b, mask=dev_mask(p.mask), x=torch.zeros_like(b), lam=p.lam))
+    return items
+
+
+def test_graph_replay_matches_direct_launches():
+    """The captured per-iteration graphs, replayed across iterations and
+    across calls, on the caller's stream and on the library's own stream,
+    give bitwise the same results as direct launches."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(96, 50 + i, psi="tv" if i % 2 else "haar", levels=4,
+                                groups="tv_iso" if i % 2 else "quadtree", lam=0.02, sigma=0.01, frac=0.25)
+             for i in range(4)]
+    shapes = [shape_of(probs[0]), shape_of(probs[1])]
+    s = F.Solver(shapes, prec="fp32", max_slices=4, max_outer=6, pcg_iters=10, outer_tol=1e-6)
+    runs = []
+    side = torch.cuda.Stream()
+    for mode in ("direct", "graph_null", "graph_null", "graph_side"):
+        s.set_graphs(mode != "direct")
+        items = _batch(torch, probs)
+        for i, it in enumerate(items):
+            it["shape_id"] = i % 2
+        if mode == "graph_side":
+            with torch.cuda.stream(side):
+                reps = s.solve_batched(items, stream=side)
+            side.synchronize()
+        else:
+            reps = s.solve_batched(items)
+        torch.cuda.synchronize()
+        runs.append(([to_np(it["x"]) for it in items], [r["F_eps"] for r in reps]))
+    for xs, fe in runs[1:]:
+        assert fe == runs[0][1]
+        for a, b in zip(xs, runs[0][0]):
+            assert np.array_equal(a, b)
+
+
+def test_chunked_batches_and_autotune():
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 60 + i, psi="haar", levels=4, groups="quadtree", lam=0.035,
+                                sigma=0.01, frac=0.2) for i in range(40)]
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=40, max_outer=5, pcg_iters=10)
+    whole = _batch(torch, probs)
+    r0 = s.solve_batched(whole)
+    s.set_chunk(7)
+    parts = _batch(torch, probs)
+    r1 = s.solve_batched(parts)
+    assert [r["F_eps"] for r in r0] == [r["F_eps"] for r in r1]
+    for a, b in zip(whole, parts):
+        assert torch.equal(a["x"], b["x"])
+    before = [it["x"].clone() for it in parts]
+    chosen = s.autotune(parts)
+    assert chosen in (0, 32)
+    for a, b in zip(before, parts):
+        assert torch.equal(a, b["x"])
