@@ -1,18 +1,22 @@
 """Benchmark: batched FIRLS_OG solves at 256^2 on one MI355X.
 
-One step = one call of firls_solve_batched on B slices of the tree-group
-CS-MRI workload (256 x 256 ellipse phantoms, 20% variable-density k-space
-mask, sigma 0.01, 4-level Haar, each coefficient grouped with its quadtree
-parent, lambda 0.035, eps 1e-10, FP32 vectors with FP64 scalars, 20 PCG
-iterations per outer iteration), every slice started from A^H b and run
-until its relative objective decrease falls below tau (calibrated so that
-the final objective is within 1e-4 of the optimum) or 50 outer iterations.
-Inputs are generated and uploaded before the timed region.
+One step = one batched solve of B slices of the tree-group CS-MRI workload
+(256 x 256 ellipse phantoms, 20% variable-density k-space mask, sigma 0.01,
+4-level Haar, each coefficient grouped with its quadtree parent, lambda
+0.035, eps 1e-10, FP32 vectors with FP64 scalars, 20 PCG iterations per
+outer iteration) through the whole hot path: the learned warm start (network
+on A^H b, measured samples put back, A^H b kept where it has the lower
+objective), then FIRLS on every slice until its relative objective decrease
+falls below tau (calibrated so that the final objective is within 1e-4 of
+the optimum) or 50 outer iterations.  Inputs are generated and uploaded
+before the timed region; the sub-batch size is autotuned before it.
 
-Prints one JSON line with solves/s, the roofline of the dominant kernel
-(HIP-event durations measured during the timed steps), the achieved
+Prints one JSON line: solves/s, the roofline of the dominant kernel
+(HIP-event durations of every launch, measured on one more step of the same
+call right after the timed steps), the achieved
 algorithmic HBM rate of the whole path, the gap to the optimum of every
-slice, and the FP64 CPU oracle timed on a bounded sample on the host.
+slice, the same solves from the zero-filled start (the ablation), and the
+FP64 CPU oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -72,6 +76,7 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1411_5057_amd", "weights", "warmstart_256.f32"),
                     help="warm-start network parameters (float32, ABI order); skipped if missing")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the sub-batch autotuner")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -104,6 +109,47 @@ def cpu_baseline(n, tau, max_outer, K):
                       f"numpy FP64, single process; {dt:.1f} s per solve"}
 
 
+def timed(solver, run, steps, warmup, profile, torch):
+    """Warm up, then time ``steps`` calls of run() (HIP events per launch
+    when ``profile``).  Returns (seconds, last reports, profile dict)."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    if profile:
+        solver.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = solver.profile_read() if profile else {}
+    solver.profile(False)
+    return dt, out, prof
+
+
+def roofline_of(prof, n, K, dt):
+    """Dominant PCG kernel by measured time: algorithmic bytes per launch
+    over its average HIP-event duration; plus the whole path's rate."""
+    npx = n * n
+    tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
+    pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update")}
+    dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
+    v = prof[dom]
+    per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]
+    avg_s = v["ms"] / v["launches"] / 1e3
+    ach = per_launch_bytes / avg_s / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
+            "bytes_per_launch": per_launch_bytes}
+    return roof, tot_bytes / dt / 1e9, {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]}
+
+
+def gap_stats(fe, fstar):
+    g = (fe - fstar) / fstar
+    return {"max": float(g.max()), "p99": float(np.quantile(g, 0.99)), "median": float(np.median(g)),
+            "frac_le_1e-4": float(np.mean(g <= 1e-4))}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -128,42 +174,24 @@ def main():
     solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
                       outer_tol=a.tau, eps=1e-10)
     x = torch.zeros_like(b)
-    stream = torch.cuda.current_stream()
     items = [dict(b=b[i], mask=m[i], x=x[i], lam=lams[i]) for i in range(B)]
+    chunk = solver.autotune(items) if not a.no_tune else 0
+    use_learned = not a.no_learned and os.path.exists(a.weights) and n == 256
+    net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4")) if use_learned else None
 
-    for _ in range(a.warmup):
-        solver.solve_batched(items)
-    torch.cuda.synchronize()
+    def run_plain():
+        return solver.solve_batched(items), None
+
+    def run_learned():
+        return solver.solve_batched_learned(net, items)
+
+    main_run = run_learned if use_learned else run_plain
+    dt, (reps, used), _ = timed(solver, main_run, a.steps, a.warmup, False, torch)
+    # kernel durations: one more step of the same call with HIP events around
+    # every launch (events turn graph replay off, so this step is not timed)
+    prof = {}
     if not a.no_profile:
-        solver.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        reps = solver.solve_batched(items)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = solver.profile_read() if not a.no_profile else {}
-    solver.profile(False)
-
-    learned = None
-    if not a.no_learned and os.path.exists(a.weights) and n == 256:
-        net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4"))
-        xl = torch.zeros_like(b)
-        items_l = [dict(b=b[i], mask=m[i], x=xl[i], lam=lams[i]) for i in range(B)]
-        for _ in range(a.warmup):
-            solver.solve_batched_learned(net, items_l)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(a.steps):
-            reps_l, used = solver.solve_batched_learned(net, items_l)
-        torch.cuda.synchronize()
-        dtl = time.perf_counter() - t1
-        outer_l = np.array([r["outer_iters"] for r in reps_l])
-        learned = {"value": B * a.steps / dtl, "unit": "solves/s", "ms_per_step": 1e3 * dtl / a.steps,
-                   "outer_iters_mean": float(outer_l.mean()), "outer_iters_max": int(outer_l.max()),
-                   "learned_start_kept_frac": float(np.mean(used)),
-                   "fe": np.array([r["F_eps"] for r in reps_l]), "weights": os.path.relpath(a.weights, ROOT)}
-        net.close()
-
+        _, _, prof = timed(solver, main_run, 1, 0, True, torch)
     value = B * a.steps / dt
     outer = np.array([r["outer_iters"] for r in reps])
     pcg = np.array([r["pcg_iters"] for r in reps])
@@ -175,28 +203,28 @@ def main():
         "data": "synthetic (seeded ellipse phantoms, VD masks, complex Gaussian noise)",
         "config": {"workload": f"tree-group FIRLS_OG, {n}x{n}, 20% VD mask, sigma 0.01, 4-level Haar, "
                                f"quadtree-pair groups, lambda 0.035, eps 1e-10, {B} slices per step, "
-                               f"{K} PCG per outer, stop at rel. F_eps decrease {a.tau:g} (max {a.max_outer})",
-                   "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer},
+                               f"{K} PCG per outer, stop at rel. F_eps decrease {a.tau:g} (max {a.max_outer}), "
+                               f"start: {'learned warm start (network + data consistency, A^H b fallback)' if use_learned else 'A^H b'}",
+                   "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer,
+                   "start": "learned" if use_learned else "zero-filled", "sub_batch": chunk},
         "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
         "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
         "converged_frac": float(np.mean([r["converged"] for r in reps])),
     }
+    if used is not None:
+        out["learned_start_kept_frac"] = float(np.mean(used))
+        out["weights"] = os.path.relpath(a.weights, ROOT)
     if prof:
-        npx = n * n
-        tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
-        out["hbm_gbs_algorithmic"] = tot_bytes / dt / 1e9
-        pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update")}
-        dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
-        v = prof[dom]
-        per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]
-        avg_s = v["ms"] / v["launches"] / 1e3
-        ach = per_launch_bytes / avg_s / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                           "avg_launch_us": avg_s * 1e6, "bytes_per_launch": per_launch_bytes}
-        out["kernel_ms"] = {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]}
-        gpu_ms = sum(v["ms"] for v in prof.values())
-        out["kernel_time_frac_of_wall"] = gpu_ms / 1e3 / dt
+        # the instrumented step does 1/steps of the timed work
+        out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps)
+        out["kernel_time_frac_of_wall"] = sum(v["ms"] for v in prof.values()) / 1e3 / (dt / a.steps)
+    plain = None
+    if use_learned:
+        dtp, (reps_p, _), _ = timed(solver, run_plain, a.steps, a.warmup, False, torch)
+        op = np.array([r["outer_iters"] for r in reps_p])
+        plain = {"value": B * a.steps / dtp, "unit": "solves/s", "ms_per_step": 1e3 * dtp / a.steps,
+                 "outer_iters_mean": float(op.mean()), "outer_iters_max": int(op.max()),
+                 "fe": np.array([r["F_eps"] for r in reps_p])}
     if not a.no_gap:
         # optimum estimate: the same slices, tau = 0, ref_outer outer iterations
         ref = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.ref_outer, pcg_iters=K,
@@ -204,24 +232,20 @@ def main():
         xr = torch.zeros_like(b)
         rr = ref.solve_batched([dict(b=b[i], mask=m[i], x=xr[i], lam=lams[i]) for i in range(B)])
         fstar = np.array([r["F_eps"] for r in rr])
-        gap = (fe - fstar) / fstar
-        out["gap_to_optimum"] = {"max": float(gap.max()), "p99": float(np.quantile(gap, 0.99)),
-                                 "median": float(np.median(gap)), "frac_le_1e-4": float(np.mean(gap <= 1e-4)),
-                                 "reference": f"same slices, {a.ref_outer} outer iterations, tau = 0"}
-        if learned is not None:
-            gl = (learned["fe"] - fstar) / fstar
-            learned["gap_to_optimum"] = {"max": float(gl.max()), "p99": float(np.quantile(gl, 0.99)),
-                                         "frac_le_1e-4": float(np.mean(gl <= 1e-4))}
+        out["gap_to_optimum"] = gap_stats(fe, fstar)
+        out["gap_to_optimum"]["reference"] = f"same slices, {a.ref_outer} outer iterations, tau = 0"
+        if plain is not None:
+            plain["gap_to_optimum"] = gap_stats(plain["fe"], fstar)
         ref.close()
-    if learned is not None:
-        learned.pop("fe")
-        learned["speedup_vs_plain"] = learned["value"] / value
-        out["learned"] = learned
+    if plain is not None:
+        plain.pop("fe")
+        out["plain"] = plain
+        out["learned_speedup_vs_plain"] = value / plain["value"]
     if not a.no_cpu:
-        cb = cpu_baseline(n, a.tau, a.max_outer, K)
-        cb["cores"] = 1
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(n, a.tau, a.max_outer, K)
     print(json.dumps(out))
+    if net is not None:
+        net.close()
     solver.close()
 
 

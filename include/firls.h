@@ -235,9 +235,10 @@ int firls_cnn_train_step(firls_cnn* net, void* stream, int32_t batch, const void
                          float lr, double* loss);
 
 /* firls_solve_batched started from the network: every slice (FP32 handle,
- * image side = the network's) gets x = A^H b and x0 = x + f(x); x0 is kept
- * where F_eps(x0) <= F_eps(A^H b), else A^H b (used_learned[i] = 1 / 0, may
- * be NULL); then FIRLS runs from there with the handle's tolerance. */
+ * image side = the network's) gets z = A^H b and x0 = z + f(z), then the
+ * measured samples are put back into x0 (x0 <- F^H (m b + (1 - m) F x0));
+ * x0 is kept where F_eps(x0) <= F_eps(z), else z (used_learned[i] = 1 / 0,
+ * may be NULL); FIRLS then runs from there with the handle's tolerance. */
 int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, int32_t n_slices,
                                 const firls_slice* slices, firls_report* reports, int32_t* used_learned);
 

@@ -993,6 +993,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     for (int i : by_shape[s]) h->h_list[pos++] = i;
   }
   auto upload = [&](char* xbuf) -> int {
+    HIPCHK(hipStreamSynchronize(st));   // an earlier upload may still read the pinned staging
     for (int i = 0; i < ns; ++i) {
       tmp[i].x = xbuf + (size_t)i * np * 8;
       fill_desc(h, h->h_desc[i], h->shapes[slices[i].shape_id], off[i], &tmp[i]);
@@ -1037,7 +1038,20 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     const int bn = std::min(mb, ns - b0);
     if ((rc = cnn_forward(net, st, bn, zf + (size_t)b0 * np * 8, x0 + (size_t)b0 * np * 8))) return rc;
   }
-  // 3. objectives of both candidates, 4. keep the better one in each x
+  // 3. data consistency on the network starts: x0 <- F^H (m b + (1 - m) F x0)
+  if ((rc = upload(x0))) return rc;
+  for (int s = 0; s < nsh; ++s) {
+    const int c = (int)by_shape[s].size();
+    if (!c) continue;
+    const Shape& S = h->shapes[s];
+    Params P = base_params(h, S, s, h->d_list + lo[s]);
+    LAUNCH(S.sk->rowfwd[RF_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+    LAUNCH(S.sk->col[COL_DC], P, dim3(S.n / strip_cols(false), c), st);
+    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+  }
+  HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
+  if ((rc = upload(zf))) return rc;
+  // 4. objectives of both candidates, 5. keep the better one in each x
   if ((rc = evaluate())) return rc;
   HIPCHK(hipMemcpyAsync(st_zero, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
@@ -1055,7 +1069,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
   if (used_learned)
     for (int i = 0; i < ns; ++i) used_learned[i] = s1[i].Fe <= s0[i].Fe ? 1 : 0;
   h->profiling = prof;
-  // 5. FIRLS from the chosen starts
+  // 6. FIRLS from the chosen starts
   for (int i = 0; i < ns; ++i) tmp[i] = slices[i], tmp[i].x_is_init = 1;
   return run_batch(h, st, ns, tmp.data(), reports, h->cfg.max_outer, h->cfg.outer_tol);
 }

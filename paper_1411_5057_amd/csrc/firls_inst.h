@@ -59,6 +59,7 @@ SizeKernels make_size_kernels() {
   allow_lds(k_col<T, N, COL_SP>, bc);
   allow_lds(k_col<T, N, COL_R0>, bc);
   allow_lds(k_col<T, N, COL_AHB>, bc);
+  allow_lds(k_col<T, N, COL_DC>, bc);
   allow_lds(k_rowinv<T, N, RI_PLAIN>, b);
   allow_lds(k_rowinv<T, N, RI_SP_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
@@ -71,6 +72,7 @@ SizeKernels make_size_kernels() {
   k.col[COL_SP] = L_col<T, N, COL_SP>;
   k.col[COL_R0] = L_col<T, N, COL_R0>;
   k.col[COL_AHB] = L_col<T, N, COL_AHB>;
+  k.col[COL_DC] = L_col<T, N, COL_DC>;
   k.rowinv[RI_PLAIN] = L_rowinv<T, N, RI_PLAIN>;
   k.rowinv[RI_SP_HAAR] = L_rowinv<T, N, RI_SP_HAAR>;
   k.rowinv[RI_SP_TV] = L_rowinv<T, N, RI_SP_TV>;

@@ -151,6 +151,15 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) slot_wptr(D, SLOT_DATA)[blockIdx.x] = 0.5 * tot;
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+  } else if constexpr (MODE == COL_DC) {
+    // data consistency: keep F x where unsampled, put b where sampled
+    // (k = m b + (1 - m) F x), then the column inverse with 1/n
+    const C* b = static_cast<const C*>(D.b);
+    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+      const size_t g = (size_t)row * N + col0 + c;
+      lds[Lay::at(c, row)] = (sampled(c, row) ? b[g] : v * sn) * sn;
+    });
+    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else {
     const C* b = static_cast<const C*>(D.b);
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, [&](int c, int row) {

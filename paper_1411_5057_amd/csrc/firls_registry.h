@@ -10,7 +10,7 @@ using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
 // Kernels that depend on the image side (FFT length).
 struct SizeKernels {
   Launcher rowfwd[3];
-  Launcher col[3];
+  Launcher col[4];
   Launcher rowinv[5];
   Launcher psi_sq_haar;
   Launcher update_haar[2];

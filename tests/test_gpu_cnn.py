@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import cnn
+from oracle import cnn, fourier
 from oracle.firls import Operators, firls
 from tests.gpu_util import dev_complex, dev_mask, shape_of, to_np, torch_cuda
 
@@ -105,7 +105,9 @@ def test_learned_solve_reaches_oracle_optimum():
         ops = Operators.from_problem(p)
         zf = ops.AHb()
         x0, _ = cnn.forward(params, zf[None], bf16_mode=True)
-        start = x0[0] if ops.objective(x0[0])[0] <= ops.objective(zf)[0] else zf
+        # measured samples put back: F^H (m b + (1 - m) F x0)
+        x0 = fourier.ifft2u(ops.b + (1.0 - ops.mask) * fourier.fft2u(x0[0]))
+        start = x0 if ops.objective(x0)[0] <= ops.objective(zf)[0] else zf
         ref = firls(ops, T, 20, tau=tau, x1=start)
         fe = ops.objective(to_np(it["x"]))[0]
         assert abs(fe - ref.F_eps) <= 1e-5 * ref.F_eps
