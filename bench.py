@@ -38,13 +38,13 @@ HBM_PEAK_GBS = 8000.0
 # Haar slice in FP32 (c64 = 8 B, r32 = 4 B, u8 mask = 1 B), the minimum each
 # kernel must stream:
 #   rowfwd : read r, d, p; write p, t         (p not read at k = 0)
-#   col    : read t, mask; write t
+#   col    : read t, mask bits; write t
 #   rowinv : read t, p, d; write q
 #   update : read x, p, q, r, d; write x, r
 def bytes_per_px(cls: str, K: int) -> float:
     return {
         "rowfwd": (28.0 + 36.0 * (K - 1)) / K,
-        "col": 17.0,
+        "col": 16.125,        # mask as one bit per pixel
         "rowinv": 28.0,
         "update": 52.0,
         "psi_sq": 12.0,        # read x; write |Phi x|^2
@@ -138,10 +138,35 @@ def roofline_of(prof, n, K, dt):
     per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]
     avg_s = v["ms"] / v["launches"] / 1e3
     ach = per_launch_bytes / avg_s / 1e9
+    tr = traffic_record()
+    traffic = None
+    if tr is not None and tr.get("n") == n and dom in tr["traffic_bytes_per_px"]:
+        traffic = tr["traffic_bytes_per_px"][dom] * npx * v["slice_launches"] / v["launches"]
     roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
             "bytes_per_launch": per_launch_bytes}
     return roof, tot_bytes / dt / 1e9, {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]}
+
+
+def traffic_record():
+    """Measured HBM bytes per pixel of each PCG kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel
+    sources (else None)."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "firls_pcg_256_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic_record:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1411_5057_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return rec if h.hexdigest()[:16] == rec["kernel_source_sha"] else None
 
 
 def gap_stats(fe, fstar):
@@ -189,9 +214,9 @@ def main():
     dt, (reps, used), _ = timed(solver, main_run, a.steps, a.warmup, False, torch)
     # kernel durations: one more step of the same call with HIP events around
     # every launch (events turn graph replay off, so this step is not timed)
-    prof = {}
+    prof, dt_prof = {}, None
     if not a.no_profile:
-        _, _, prof = timed(solver, main_run, 1, 0, True, torch)
+        dt_prof, _, prof = timed(solver, main_run, 1, 0, True, torch)
     value = B * a.steps / dt
     outer = np.array([r["outer_iters"] for r in reps])
     pcg = np.array([r["pcg_iters"] for r in reps])
@@ -217,7 +242,7 @@ def main():
     if prof:
         # the instrumented step does 1/steps of the timed work
         out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps)
-        out["kernel_time_frac_of_wall"] = sum(v["ms"] for v in prof.values()) / 1e3 / (dt / a.steps)
+        out["kernel_time_frac_of_instrumented_step"] = sum(v["ms"] for v in prof.values()) / 1e3 / dt_prof
     plain = None
     if use_learned:
         dtp, (reps_p, _), _ = timed(solver, run_plain, a.steps, a.warmup, False, torch)
