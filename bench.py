@@ -3,7 +3,7 @@
 One step = one batched solve of B slices of the tree-group CS-MRI workload
 (256 x 256 ellipse phantoms, 20% variable-density k-space mask, sigma 0.01,
 4-level Haar, each coefficient grouped with its quadtree parent, lambda
-0.035, eps 1e-10, FP32 vectors with FP64 scalars, 20 PCG iterations per
+0.035, eps 1e-10, FP32 vectors with FP64 scalars, 4 PCG iterations per
 outer iteration) through the whole hot path: the learned warm start (network
 on A^H b, measured samples put back, A^H b kept where it has the lower
 objective), then FIRLS on every slice until its relative objective decrease
@@ -43,17 +43,18 @@ HBM_PEAK_GBS = 8000.0
 #   update : read x, p, q, r, d; write x, r
 def bytes_per_px(cls: str, K: int) -> float:
     return {
-        "rowfwd": (28.0 + 36.0 * (K - 1)) / K,
-        "col": 16.125,        # mask as one bit per pixel
-        "rowinv": 28.0,
-        "update": 52.0,
-        "psi_sq": 12.0,        # read x; write |Phi x|^2
+        "rowfwd": 28.0,        # first iteration: read r, d; write p, t
+        "col": 16.125,         # read t, mask bits; write t
+        "rowinv": 28.0,        # read t, p, d; write q
+        "update": 68.0,        # read x, p, q, r, d; write x, r, p, t
+        "last_x": 24.0,        # read x, p; write x
+        "psi_sq": 12.0,        # read x; write |Phi x|^2 (TV only)
         "group_w": 10.0,       # read |z|^2 of members (~2 per group), write W
         "group_d": 12.0,       # read W of the groups of each coefficient (~2), write d
-        "r0_rowfwd": 16.0,     # read x; write t
+        "r0_rowfwd": 20.0,     # read x; write t and |Phi x|^2
         "r0_col": 25.0,        # read t, mask, b; write t
         "r0_rowinv": 28.0,     # read t, x, d; write r
-        "r0_update": 12.0,     # read r, d
+        "r0_update": 12.0,     # read r, d (TV only)
         "adjoint": 33.0,       # read b, mask; write t; read t; write x
     }.get(cls, 0.0)
 
@@ -65,9 +66,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--slices", type=int, default=256)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--pcg", type=int, default=20)
+    ap.add_argument("--pcg", type=int, default=4)
     ap.add_argument("--max-outer", type=int, default=50)
-    ap.add_argument("--tau", type=float, default=1e-5)
+    ap.add_argument("--tau", type=float, default=8e-6)
     ap.add_argument("--ref-outer", type=int, default=300,
                     help="outer iterations of the reference solve that estimates the optimum")
     ap.add_argument("--no-profile", action="store_true")
@@ -132,7 +133,7 @@ def roofline_of(prof, n, K, dt):
     over its average HIP-event duration; plus the whole path's rate."""
     npx = n * n
     tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
-    pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update")}
+    pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update", "last_x")}
     dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
     v = prof[dom]
     per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]

@@ -273,16 +273,17 @@ enum {
   FIRLS_PROF_PSI_SQ = 2,    /* |Psi x|^2 */
   FIRLS_PROF_GROUP_W = 3,   /* group weights W and penalty partials */
   FIRLS_PROF_GROUP_D = 4,   /* d = diag(G^T W G) */
-  FIRLS_PROF_R0_ROWFWD = 5, /* residual A^H b - S x: row FFT */
+  FIRLS_PROF_R0_ROWFWD = 5, /* residual A^H b - S x: row FFT (Haar: and |Psi x|^2) */
   FIRLS_PROF_R0_COL = 6,    /*   column pass with the data term */
-  FIRLS_PROF_R0_ROWINV = 7, /*   row inverse FFT + regulariser */
-  FIRLS_PROF_R0_UPDATE = 8, /*   z0 and <r0, z0> */
+  FIRLS_PROF_R0_ROWINV = 7, /*   row inverse FFT + regulariser (Haar: and <r0, z0>) */
+  FIRLS_PROF_R0_UPDATE = 8, /*   TV: z0 and <r0, z0> */
   FIRLS_PROF_CHECK = 9,     /* objective and stop rule */
-  FIRLS_PROF_ROWFWD = 10,   /* PCG: z = P^{-1} r, p = z + beta p, row FFT */
+  FIRLS_PROF_ROWFWD = 10,   /* PCG: first p and row FFT (Haar), or p = z + beta p and row FFT (TV) */
   FIRLS_PROF_COL = 11,      /* PCG: column FFT, mask, column inverse FFT */
-  FIRLS_PROF_ROWINV = 12,   /* PCG: row inverse FFT + regulariser, <p, q> */
-  FIRLS_PROF_UPDATE = 13,   /* PCG: x, r update and <r, z> */
-  FIRLS_PROF_CLASSES = 14
+  FIRLS_PROF_ROWINV = 12,   /* PCG: row inverse FFT + regulariser, <p, q> (Haar: and <q, P^{-1} q>) */
+  FIRLS_PROF_UPDATE = 13,   /* PCG: x, r update, z and <r, z> (Haar: and the next p and row FFT) */
+  FIRLS_PROF_LAST_X = 14,   /* PCG, Haar: x += alpha p after the last iteration */
+  FIRLS_PROF_CLASSES = 15
 };
 
 typedef struct {

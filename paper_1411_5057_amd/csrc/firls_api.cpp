@@ -100,6 +100,7 @@ struct firls_handle {
   SliceState* h_state = nullptr;
   int32_t* h_list = nullptr;
   hipEvent_t ev = nullptr;
+  hipEvent_t ev2 = nullptr;
 
   // graph replay of the per-outer-iteration launch blocks
   bool use_graphs = true;
@@ -206,7 +207,7 @@ int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
     HIPCHK(hipMalloc(&h->d_state, sizeof(SliceState) * want));
     HIPCHK(hipMalloc(&h->d_list, sizeof(int32_t) * 2 * want));
     HIPCHK(hipHostMalloc(&h->h_desc, sizeof(SliceDesc) * want, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc(&h->h_state, sizeof(SliceState) * want, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h->h_state, sizeof(SliceState) * 3 * want, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&h->h_list, sizeof(int32_t) * 2 * want, hipHostMallocDefault));
     h->cap_slices = want;
   }
@@ -270,7 +271,7 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.eps = h->cfg.eps;
   P.tau = h->cfg.outer_tol;
   const int R = band_rows(s.n);
-  P.npq = s.n / R;
+  P.npq = s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0);
   P.ndata = s.n / strip_cols(h->fp64);
   P.nrz = s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC);
   P.nreg = (s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG;
@@ -320,30 +321,56 @@ int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipS
   return FIRLS_OK;
 }
 
-// r0 = A^H b - S x (data term fused), then z0 and <r0, z0>.
-int launch_residual(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+// Weights and residual of the current x, then the objective check (one
+// outer iteration's preparation).  Haar: the row FFT of x also writes
+// |Phi x|^2, and the row-inverse pass of r0 = A^H b - S x also sums
+// <r0, z0>; TV: |D x|^2, weights, the residual passes and z0 = M^{-1} r0.
+int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
-  const bool haar = s.psi == PSI_HAAR;
-  KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / band_rows(s.n), c), st);
-  KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
-  KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[haar ? RI_R0_HAAR : RI_R0_TV], P, dim3(s.n / band_rows(s.n), c), st);
-  if (haar) KLAUNCH(h, FIRLS_PROF_R0_UPDATE, s.sk->update_haar[UP_INIT], P, dim3(s.n / band_rows(s.n), c), st);
-  else KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
+  const dim3 rows(s.n / band_rows(s.n), c);
+  if (s.psi == PSI_HAAR) {
+    KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQ_HAAR], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
+    KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
+  } else {
+    int rc = launch_weights(h, s, P, c, st);
+    if (rc) return rc;
+    KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
+  }
+  KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
   return FIRLS_OK;
 }
 
+// K PCG iterations.  Haar: 3 launches per iteration (the update of one
+// iteration rides in the row pass of the next) and x += alpha p at the end;
+// TV: 4 launches per iteration.
 int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
-  for (int k = 0; k < h->cfg.pcg_iters; ++k) {
+  const dim3 rows(s.n / band_rows(s.n), c);
+  const int K = h->cfg.pcg_iters;
+  for (int k = 0; k < K; ++k) {
     P.k = k;
-    KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[haar ? RF_PCG_HAAR : RF_PCG_Z], P, dim3(s.n / band_rows(s.n), c), st);
-    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[COL_SP], P, dim3(s.n / C, c), st);
-    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, dim3(s.n / band_rows(s.n), c), st);
-    if (haar) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar[UP_STEP], P, dim3(s.n / band_rows(s.n), c), st);
-    else KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
+    if (haar) {
+      if (k == 0) KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
+      else KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
+    } else {
+      KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_Z], P, rows, st);
+    }
+    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
+    if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
+  }
+  if (haar) {
+    P.k = K - 1;
+    KLAUNCH(h, FIRLS_PROF_LAST_X, s.sk->last_x, P, rows, st);
   }
   return FIRLS_OK;
 }
@@ -446,9 +473,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       h->ctx_group = s;
       h->ctx_count = c;
       int r2;
-      if ((r2 = launch_weights(h, S, P, c, st))) return r2;
-      if ((r2 = launch_residual(h, S, P, c, st))) return r2;
-      KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
+      if ((r2 = launch_prep(h, S, P, c, st))) return r2;
     }
     return FIRLS_OK;
   };
@@ -496,24 +521,46 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       h->gkey = key;
     }
   }
+  // The host learns which slices are still active one iteration late:
+  // iteration it + 1 is enqueued before the stop-test record of iteration it
+  // is read, so the GPU never waits for the host.  Kernels of slices that
+  // have stopped exit at their first instruction, so the iteration enqueued
+  // after the last slice stopped costs only its launches.
+  hipEvent_t evs[2] = {h->ev, h->ev2};
+  auto ring = [&](int j) { return h->h_state + (size_t)(1 + (j & 1)) * h->cap_slices; };
+  auto read_active = [&](int j) {
+    const SliceState* hs = ring(j);
+    int active = 0;
+    act_pcg.emplace_back(nsh, 0);
+    for (int i = 0; i < ns; ++i) {
+      active += hs[i].active;
+      act_pcg.back()[sl[i].shape_id] += hs[i].active;
+    }
+    return active;
+  };
+  bool stopped = false;
   for (int it = 0; it <= Tmax; ++it) {
     h->ctx_it = it;
     h->ctx_phase = 1;
     if (graphs) HIPCHK(hipGraphLaunch(h->g_prep, st));
     else if ((rc = enqueue_prep())) return rc;
-    HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(h->ev, st));
+    HIPCHK(hipMemcpyAsync(ring(it), h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(evs[it & 1], st));
     h->ctx_phase = 2;
     if (graphs) HIPCHK(hipGraphLaunch(h->g_pcg, st));
     else if ((rc = enqueue_pcg())) return rc;
-    HIPCHK(hipEventSynchronize(h->ev));
-    int active = 0;
-    act_pcg.emplace_back(nsh, 0);
-    for (int i = 0; i < ns; ++i) {
-      active += h->h_state[i].active;
-      act_pcg.back()[sl[i].shape_id] += h->h_state[i].active;
+    if (it >= 1) {
+      HIPCHK(hipEventSynchronize(evs[(it - 1) & 1]));
+      if (!read_active(it - 1)) {
+        act_pcg.emplace_back(nsh, 0);   // iteration it ran with no active slice
+        stopped = true;
+        break;
+      }
     }
-    if (!active) break;
+  }
+  if (!stopped) {
+    HIPCHK(hipEventSynchronize(evs[Tmax & 1]));
+    (void)read_active(Tmax);
   }
   HIPCHK(hipStreamSynchronize(st));
   if (h->profiling && (rc = prof_collect(h, act_pcg))) return rc;
@@ -731,7 +778,8 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
       return fail(rc, msg);
     }
   }
-  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev2, hipEventDisableTiming) != hipSuccess) {
     destroy_shapes(h);
     delete h;
     return fail(FIRLS_E_HIP, "event creation failed");
@@ -746,6 +794,7 @@ int firls_destroy(firls_handle* h) {
   free_batch(h);
   destroy_shapes(h);
   if (h->ev) (void)hipEventDestroy(h->ev);
+  if (h->ev2) (void)hipEventDestroy(h->ev2);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->own) (void)hipStreamDestroy(h->own);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -788,7 +837,7 @@ int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out)
   if (!h || !out || n < 0) return fail(FIRLS_E_INVALID, "null argument");
   static const char* names[FIRLS_PROF_CLASSES] = {
       "init", "adjoint", "psi_sq", "group_w", "group_d", "r0_rowfwd", "r0_col", "r0_rowinv",
-      "r0_update", "check", "rowfwd", "col", "rowinv", "update"};
+      "r0_update", "check", "rowfwd", "col", "rowinv", "update", "last_x"};
   const int m = std::min<int>(n, FIRLS_PROF_CLASSES);
   for (int c = 0; c < m; ++c) {
     std::memset(&out[c], 0, sizeof(out[c]));
@@ -1010,11 +1059,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
       Params P = base_params(h, S, s, h->d_list + lo[s]);
       P.Tmax = 0;
       P.tau = 0.0;
+      // Both candidates reproduce the measurements exactly (A A^H b = b, and
+      // the data-consistency step sets m F x0 = b), so F_eps is lambda times
+      // the penalty: no Fourier pass is needed.
+      P.no_data = 1;
       LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
       int r2 = launch_weights(h, S, P, c, st);
       if (r2) return r2;
-      LAUNCH(S.sk->rowfwd[RF_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
-      LAUNCH(S.sk->col[COL_R0], P, dim3(S.n / strip_cols(false), c), st);
       LAUNCH(prec_kernels(false)->outer_check, P, dim3(c), st);
     }
     return FIRLS_OK;

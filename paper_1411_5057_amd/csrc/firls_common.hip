@@ -46,7 +46,7 @@ __global__ __launch_bounds__(NT) void k_outer_check(Params P) {
   SliceState& S = P.state[s];
   if (!S.active) return;
   const SliceDesc& D = P.desc[s];
-  const double data = slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
+  const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
   const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg, red);
   const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg, red);
   if (threadIdx.x != 0) return;

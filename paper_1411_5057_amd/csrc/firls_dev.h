@@ -28,6 +28,15 @@ template <typename T> __device__ __forceinline__ double cabs2(cplx<T> a) {
 template <typename T> __device__ __forceinline__ double cdot(cplx<T> a, cplx<T> b) {  // Re(conj(a) b)
   return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
 }
+template <typename T> __device__ __forceinline__ T cabs2t(cplx<T> a) { return a.x * a.x + a.y * a.y; }
+
+// 1 / (rho + lambda d) of the pseudo-diagonal preconditioner (eq. 17).  Every
+// kernel that applies P^{-1} or sums <v, P^{-1} v> takes it from here, so
+// all of them use the same operator (single precision: the hardware
+// reciprocal, within 1 ulp; the preconditioner need not be exact, only
+// symmetric positive definite and the same everywhere).
+__device__ __forceinline__ float pc_inv(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double pc_inv(double v) { return 1.0 / v; }
 
 // cos(2 pi e / 16) and sin(2 pi e / 16), e = 0..15.
 __device__ constexpr double kC16[16] = {

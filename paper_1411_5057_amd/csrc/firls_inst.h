@@ -35,9 +35,9 @@ template <typename T, int N, int M>
 hipError_t L_col(const Params& P, dim3 g, hipStream_t st) {
   return launch_dyn(k_col<T, N, M>, lds_col_bytes<T, N>(), P, g, st);
 }
-template <typename T, int N, int M>
-hipError_t L_update_haar(const Params& P, dim3 g, hipStream_t st) {
-  return launch_dyn(k_update_haar<T, N, M>, 0, P, g, st);
+template <typename T, int N>
+hipError_t L_last_x(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_last_x<T, N>, 0, P, g, st);
 }
 template <typename T, int N>
 hipError_t L_psi_sq_haar(const Params& P, dim3 g, hipStream_t st) {
@@ -55,11 +55,14 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowfwd<T, N, RF_PLAIN>, b);
   allow_lds(k_rowfwd<T, N, RF_PCG_HAAR>, b);
   allow_lds(k_rowfwd<T, N, RF_PCG_Z>, b);
+  allow_lds(k_rowfwd<T, N, RF_STEP_HAAR>, b);
+  allow_lds(k_rowfwd<T, N, RF_SQ_HAAR>, b);
   const size_t bc = lds_col_bytes<T, N>();
   allow_lds(k_col<T, N, COL_SP>, bc);
   allow_lds(k_col<T, N, COL_R0>, bc);
   allow_lds(k_col<T, N, COL_AHB>, bc);
   allow_lds(k_col<T, N, COL_DC>, bc);
+  allow_lds(k_col<T, N, COL_SP_PQ>, bc);
   allow_lds(k_rowinv<T, N, RI_PLAIN>, b);
   allow_lds(k_rowinv<T, N, RI_SP_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
@@ -69,18 +72,20 @@ SizeKernels make_size_kernels() {
   k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;
   k.rowfwd[RF_PCG_HAAR] = L_rowfwd<T, N, RF_PCG_HAAR>;
   k.rowfwd[RF_PCG_Z] = L_rowfwd<T, N, RF_PCG_Z>;
+  k.rowfwd[RF_STEP_HAAR] = L_rowfwd<T, N, RF_STEP_HAAR>;
+  k.rowfwd[RF_SQ_HAAR] = L_rowfwd<T, N, RF_SQ_HAAR>;
   k.col[COL_SP] = L_col<T, N, COL_SP>;
   k.col[COL_R0] = L_col<T, N, COL_R0>;
   k.col[COL_AHB] = L_col<T, N, COL_AHB>;
   k.col[COL_DC] = L_col<T, N, COL_DC>;
+  k.col[COL_SP_PQ] = L_col<T, N, COL_SP_PQ>;
   k.rowinv[RI_PLAIN] = L_rowinv<T, N, RI_PLAIN>;
   k.rowinv[RI_SP_HAAR] = L_rowinv<T, N, RI_SP_HAAR>;
   k.rowinv[RI_SP_TV] = L_rowinv<T, N, RI_SP_TV>;
   k.rowinv[RI_R0_HAAR] = L_rowinv<T, N, RI_R0_HAAR>;
   k.rowinv[RI_R0_TV] = L_rowinv<T, N, RI_R0_TV>;
   k.psi_sq_haar = L_psi_sq_haar<T, N>;
-  k.update_haar[UP_INIT] = L_update_haar<T, N, UP_INIT>;
-  k.update_haar[UP_STEP] = L_update_haar<T, N, UP_STEP>;
+  k.last_x = L_last_x<T, N>;
   return k;
 }
 

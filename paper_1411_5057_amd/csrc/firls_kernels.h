@@ -1,16 +1,26 @@
 // FIRLS kernels (templated; instantiated per precision and image size).
 //
-// One PCG iteration on a batch of slices of one shape is four launches:
-//   k_rowfwd  : z = P^{-1} r (Haar: Phi^T((Phi r)/(rho + lambda d)), eq. 17;
-//               TV: read z), p = z + beta p, then row FFTs of p -> t
+// One PCG iteration on a batch of slices of one shape (TV) is four launches:
+//   k_rowfwd  : read z, p = z + beta p, then row FFTs of p -> t
 //   k_col     : column FFT, times mask / n^2, column inverse FFT (t in place)
 //   k_rowinv  : row inverse FFTs of t plus lambda Psi^T diag(d) Psi p -> q,
 //               and the partials of <p, q>
-//   k_update  : alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, and the
-//               partials of the next <r, z> (TV: z = M^{-1} r in red-black
-//               order, the factors of eqs. 40-43)
-// so q = S p with S of eq. (15) / eq. (39).  The FP64 partial sums of each
-// inner product are written one per workgroup and summed, in index order,
+//   k_update  : alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, and
+//               z = M^{-1} r in red-black order (eqs. 40-43) with <r, z>
+// so q = S p with S of eq. (15) / eq. (39).  With Haar (pseudo-diagonal
+// preconditioner Phi^T (rho + lambda d)^{-1} Phi, eq. 17) the update of one
+// iteration and the row pass of the next are one launch (RF_STEP_HAAR):
+// it needs beta_k = <r_{k+1}, z_{k+1}> / <r_k, z_k> before the global sum of
+// <r_{k+1}, z_{k+1}> exists, and takes it from the recurrence
+//   <r_{k+1}, z_{k+1}> = alpha_k^2 <q_k, P^{-1} q_k> - <r_k, z_k>,
+// which follows from r_{k+1} = r_k - alpha_k q_k and <q_k, z_k> = <p_k, q_k>
+// (S-conjugacy of p_k and p_{k-1}); the row-inverse pass sums
+// <q_k, P^{-1} q_k> alongside <p_k, q_k>.  alpha_{k+1} uses the directly
+// summed <r_{k+1}, z_{k+1}>, so the recurrence only enters beta and never
+// accumulates.  After the last iteration only x += alpha p is needed (r is
+// recomputed from x at the next outer iteration).
+// The FP64 partial sums of each inner product are written one per workgroup
+// and summed, in index order,
 // by every workgroup that needs the scalar.
 //
 // Row passes work on bands of band_rows(n) full rows; the Haar parts run in
@@ -60,16 +70,85 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   if constexpr (MODE == RF_PLAIN) {
     const C* x = static_cast<const C*>(D.x) + off;
     fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
+  } else if constexpr (MODE == RF_SQ_HAAR) {
+    // row FFTs of x and, from the same read, |Phi x|^2 per coefficient
+    const C* x = static_cast<const C*>(D.x) + off;
+    T* sq = static_cast<T*>(D.sq) + off;
+#pragma unroll
+    for (int k = 0; k < U::PER; ++k) {
+      if (!U::valid(k)) continue;
+      const int col = U::col(k), row = U::row(k);
+      C v[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        v[s] = x[(row + s) * N + col];
+        lds[Lay::at(row + s, col)] = v[s];
+      }
+      haar_col<false>(v, P.L, col);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) sq[(row + s) * N + col] = (T)cabs2(v[s]);
+    }
+    __syncthreads();
+    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
   } else {
     double beta = 0.0;
-    if (P.k > 0) {
+    if (MODE != RF_STEP_HAAR && P.k > 0) {
       const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
       const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz, red);
       beta = rzo > 0.0 ? rz / rzo : 0.0;
     }
     const T bt = (T)beta;
     C* p = static_cast<C*>(D.p) + off;
-    if constexpr (MODE == RF_PCG_HAAR) {
+    if constexpr (MODE == RF_STEP_HAAR) {
+      // end of iteration k - 1 (alpha, x, r, <r_k, z_k>) and start of
+      // iteration k (z_k, p_k = z_k + beta p_{k-1}) in one pass
+      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz, red);
+      const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq, red);
+      const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz, red);
+      const double ald = pqo > 0.0 ? rzo / pqo : 0.0;
+      const double rzn = ald * ald * qqo - rzo;
+      const T al = (T)ald;
+      const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
+      C* x = static_cast<C*>(D.x) + off;
+      C* r = static_cast<C*>(D.r[0]) + off;
+      const C* q = static_cast<const C*>(D.q) + off;
+      const T* d = static_cast<const T*>(D.d) + off;
+      const T rhot = (T)P.state[s_].rho, lam = (T)D.lambda;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < U::PER; ++k) {
+        if (!U::valid(k)) continue;
+        const int col = U::col(k), row = U::row(k);
+        C v[16];
+        // p_{k-1} waits in this thread's own LDS cells until beta p is added
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int g = (row + s) * N + col;
+          const C po = p[g];
+          lds[Lay::at(row + s, col)] = po;
+          x[g] = x[g] + po * al;
+          v[s] = r[g] - q[g] * al;
+          r[g] = v[s];
+        }
+        haar_col<false>(v, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const T iv = pc_inv(rhot + lam * d[(row + s) * N + col]);
+          acc += (double)(cabs2t(v[s]) * iv);
+          v[s] = v[s] * iv;
+        }
+        haar_col<true>(v, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int a = Lay::at(row + s, col);
+          const C pn = v[s] + lds[a] * bs;
+          p[(row + s) * N + col] = pn;
+          lds[a] = pn;
+        }
+      }
+      const double tot = block_sum(acc, red);
+      if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k)[blockIdx.x] = tot;
+    } else if constexpr (MODE == RF_PCG_HAAR) {
       // z = Phi^T ((Phi r) / (rho + lambda d)) in registers, p = z + beta p
       const C* r = static_cast<const C*>(D.r[0]) + off;
       const T* d = static_cast<const T*>(D.d) + off;
@@ -83,7 +162,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         for (int s = 0; s < 16; ++s) v[s] = r[(row + s) * N + col];
         haar_col<false>(v, P.L, col);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) v[s] = v[s] * ((T)1 / (rho + lam * d[(row + s) * N + col]));
+        for (int s = 0; s < 16; ++s) v[s] = v[s] * pc_inv(rho + lam * d[(row + s) * N + col]);
         haar_col<true>(v, P.L, col);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -132,6 +211,22 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
       lds[Lay::at(c, row)] = sampled(c, row) ? v * sc : C{(T)0, (T)0};
     });
+    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+  } else if constexpr (MODE == COL_SP_PQ) {
+    // as COL_SP, and the partials of <p, A^H A p> = ||m F p||^2 / n^2 go to
+    // the <p, S p> slot after the row pass's partials
+    const T sc = sn * sn;
+    double acc = 0.0;
+    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+      C u{(T)0, (T)0};
+      if (sampled(c, row)) {
+        acc += (double)(cabs2t(v) * sc);
+        u = v * sc;
+      }
+      lds[Lay::at(c, row)] = u;
+    });
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[N / band_rows(N) + blockIdx.x] = tot;
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else if constexpr (MODE == COL_R0) {
     // k = (F x) at the sampled entries; keep m (b - k) / n for the inverse
@@ -202,24 +297,40 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       // A^H A part into LDS, then lambda Phi^T (d * Phi v) in registers
       fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, LdsIO<T, N>{lds});
       const T* d = static_cast<const T*>(D.d) + off;
+      const T rho = (T)P.state[s_].rho;
+      double acc2 = 0.0;
 #pragma unroll
       for (int k = 0; k < U::PER; ++k) {
         if (!U::valid(k)) continue;
         const int col = U::col(k), row = U::row(k);
-        C a[16], w[16];
+        C w[16];
+        // <p, S p> = ||A p||^2 + lambda sum d |Phi p|^2: the first part
+        // comes from the column pass, the second is summed here
 #pragma unroll
-        for (int s = 0; s < 16; ++s) w[s] = a[s] = v[(row + s) * N + col];
+        for (int s = 0; s < 16; ++s) w[s] = v[(row + s) * N + col];
         haar_col<false>(w, P.L, col);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) w[s] = w[s] * (lam * sgn * d[(row + s) * N + col]);
+        for (int s = 0; s < 16; ++s) {
+          const T ld = lam * d[(row + s) * N + col];
+          if (SP) acc += (double)(ld * cabs2t(w[s]));
+          w[s] = w[s] * (ld * sgn);
+        }
         haar_col<true>(w, P.L, col);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const C o = lds[Lay::at(row + s, col)] + w[s];
           out[(row + s) * N + col] = o;
-          if (SP) acc += cdot(a[s], o);
+          w[s] = o;
         }
+        // <o, P^{-1} o> = sum |Phi o|^2 / (rho + lambda d): <q, P^{-1} q>
+        // for the beta recurrence, or <r0, z0>
+        haar_col<false>(w, P.L, col);
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+          acc2 += (double)(cabs2t(w[s]) * pc_inv(rho + lam * d[(row + s) * N + col]));
       }
+      const double t2 = block_sum(acc2, red);
+      if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
     } else {
       const T* w1 = static_cast<const T*>(D.d);
       const T* w2 = w1 + (size_t)N * N;
@@ -261,50 +372,20 @@ __global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
   }
 }
 
-// Haar PCG update: alpha step (UP_STEP) and <r, z> = sum |Phi r|^2 / (rho + lambda d).
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_update_haar(Params P) {
+// After the last PCG iteration (Haar): alpha = <r, z> / <p, q>, x += alpha p.
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_last_x(Params P) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
-  using U = Units<N, ROWS>;
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
-  C* r = static_cast<C*>(D.r[0]) + off;
-  const T* d = static_cast<const T*>(D.d) + off;
-  T al = (T)0;
-  if constexpr (MODE == UP_STEP) {
-    const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-    const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
-    al = (T)(pq > 0.0 ? rz / pq : 0.0);
-  }
+  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+  const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
-  const C* q = static_cast<const C*>(D.q) + off;
-  const double rho = P.state[s_].rho, lam = D.lambda;
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < U::PER; ++k) {
-    if (!U::valid(k)) continue;
-    const int col = U::col(k), row = U::row(k);
-    C v[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int g = (row + s) * N + col;
-      if (MODE == UP_STEP) {
-        x[g] = x[g] + p[g] * al;
-        v[s] = r[g] - q[g] * al;
-        r[g] = v[s];
-      } else {
-        v[s] = r[g];
-      }
-    }
-    haar_col<false>(v, P.L, col);
-#pragma unroll
-    for (int s = 0; s < 16; ++s) acc += cabs2(v[s]) / (rho + lam * (double)d[(row + s) * N + col]);
-  }
-  const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[blockIdx.x] = tot;
+  for (int i = threadIdx.x; i < ROWS * N; i += NT) x[i] = x[i] + p[i] * al;
 }
 
 // ---------------------------------------------------------------------------
@@ -406,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   const T* d1 = static_cast<const T*>(D.d);
   const T* d2 = d1 + (size_t)n * n;
   T al = (T)0;
-  if constexpr (MODE == UP_STEP) {
+  if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
     al = (T)(pq > 0.0 ? rz / pq : 0.0);

@@ -9,11 +9,11 @@ using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
 
 // Kernels that depend on the image side (FFT length).
 struct SizeKernels {
-  Launcher rowfwd[3];
-  Launcher col[4];
+  Launcher rowfwd[5];
+  Launcher col[5];
   Launcher rowinv[5];
   Launcher psi_sq_haar;
-  Launcher update_haar[2];
+  Launcher last_x;
 };
 
 // Kernels that depend on the precision only.

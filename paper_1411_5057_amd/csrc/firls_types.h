@@ -26,17 +26,19 @@ enum Slot : int {
   SLOT_DATA = 0,      // 1/2 ||m F x - b||^2 partials (column pass)
   SLOT_REG_EPS = 1,   // sum sqrt(s_g + eps)        (group pass)
   SLOT_REG0 = 2,      // sum sqrt(s_g)              (group pass)
-  SLOT_PQ0 = 3,       // <p_k, S p_k>, k = 0..KMAX-1
+  SLOT_PQ0 = 3,       // <p_k, S p_k>, k = 0..KMAX-1 (Haar: row-pass partials,
+                      // then ||A p_k||^2 partials of the column pass)
   SLOT_RZ0 = 3 + KMAX,  // <r_k, z_k>, k = 0..KMAX
-  SLOT_COUNT = 3 + KMAX + KMAX + 1
+  SLOT_QQ0 = 4 + 2 * KMAX,  // <q_k, P^{-1} q_k>, k = 0..KMAX-1 (Haar)
+  SLOT_COUNT = 4 + 3 * KMAX
 };
 
 enum Psi : int { PSI_HAAR = 0, PSI_TV = 1 };
 enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
 
 // Kernel variants (template modes).
-enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2 };
-enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3 };
+enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAAR = 3, RF_SQ_HAAR = 4 };
+enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3, COL_SP_PQ = 4 };
 enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
 enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
 
@@ -108,6 +110,7 @@ struct Params {
   int32_t npq;
   int32_t ndata;
   int32_t nreg;
+  int32_t no_data;       // objective check: take the data term as 0
   double eps;
   double tau;
   void* out;             // op entry points: extra output

@@ -40,7 +40,7 @@ EXPORTED = (
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
     "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_autotune",
 )
-PROF_CLASSES = 14
+PROF_CLASSES = 15
 
 
 class firls_shape(ctypes.Structure):
