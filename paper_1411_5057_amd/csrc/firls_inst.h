@@ -6,14 +6,14 @@
 namespace firls {
 
 // Dynamic LDS of the row passes (band_rows(N) lines) and of the column
-// pass (strip_cols lines).
+// pass (strip_cols lines), each followed by the N twiddles.
 template <typename T, int N>
 constexpr size_t lds_bytes() {
-  return (size_t)band_rows(N) * LdsLayout<N>::LS * sizeof(cplx<T>);
+  return ((size_t)band_rows(N) * LdsLayout<N>::LS + N) * sizeof(cplx<T>);
 }
 template <typename T, int N>
 constexpr size_t lds_col_bytes() {
-  return (size_t)Geo<T>::COLS * LdsLayout<N>::LS * sizeof(cplx<T>);
+  return ((size_t)Geo<T>::COLS * LdsLayout<N>::LS + N) * sizeof(cplx<T>);
 }
 
 template <class K>

@@ -34,6 +34,27 @@ template <typename T> struct Geo {
   static constexpr int COLS = strip_cols(sizeof(T) == 8);   // strip width of column passes
 };
 
+// The twiddle table exp(-2 pi i k / N), k < N, copied into LDS behind the
+// LINES lines of the FFT buffer.  The first stage of an FFT uses no
+// twiddles and ends with a barrier, so the copy is visible before any use.
+template <typename T, int N, int LINES>
+__device__ __forceinline__ const cplx<T>* lds_twiddles(cplx<T>* lds, const void* tw) {
+  cplx<T>* t = lds + LINES * LdsLayout<N>::LS;
+  const cplx<T>* g = static_cast<const cplx<T>*>(tw);
+  for (int i = threadIdx.x; i < N; i += NT) t[i] = g[i];
+  return t;
+}
+
+// The spectrum scratch t between the three FFT passes is stored strip-major:
+// column strip j (COLS columns) is one contiguous block of n rows x COLS
+// values.  The column pass then streams whole blocks, and a row band still
+// meets it as runs of COLS values per row.
+template <typename T, int N>
+__device__ __forceinline__ size_t t_index(int row, int col) {
+  constexpr int TS = Geo<T>::COLS;
+  return (size_t)(col / TS) * (N * TS) + (size_t)row * TS + (col % TS);
+}
+
 #define FIRLS_SLICE_PROLOGUE(idx)                 \
   const int s_ = P.list[idx];                    \
   if (!P.state[s_].active) return;               \
@@ -64,9 +85,10 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
-  const C* tw = static_cast<const C*>(P.tw);
-  C* t = static_cast<C*>(D.t) + off;
-  auto gdst = [&](int l, int q, C v) { t[l * N + q] = v; };
+  const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
+  C* t = static_cast<C*>(D.t);
+  const int row0 = blockIdx.x * ROWS;
+  auto gdst = [&](int l, int q, C v) { t[t_index<T, N>(row0 + l, q)] = v; };
   if constexpr (MODE == RF_PLAIN) {
     const C* x = static_cast<const C*>(D.x) + off;
     fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
@@ -196,14 +218,14 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const int col0 = blockIdx.x * COLS;
-  const C* tw = static_cast<const C*>(P.tw);
-  C* t = static_cast<C*>(D.t);
+  const C* tw = lds_twiddles<T, N, COLS>(lds, P.tw);
+  C* t = static_cast<C*>(D.t) + (size_t)blockIdx.x * N * COLS;   // this strip's block
   // sampled(c, row): bit of the packed mask word of this strip and row
   const uint16_t* mw = D.mbits + (size_t)(col0 >> 4) * N;
   const int sh0 = col0 & 15;
   auto sampled = [&](int c, int row) { return (mw[row] >> (sh0 + c)) & 1u; };
-  auto gsrc = [&](int c, int row) { return t[(size_t)row * N + col0 + c]; };
-  auto gdst = [&](int c, int row, C v) { t[(size_t)row * N + col0 + c] = v; };
+  auto gsrc = [&](int c, int row) { return t[row * COLS + c]; };
+  auto gdst = [&](int c, int row, C v) { t[row * COLS + c] = v; };
   LdsIO<T, N> io{lds};
   const T sn = (T)1 / (T)N;
   if constexpr (MODE == COL_SP) {
@@ -277,9 +299,9 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const int row0 = blockIdx.x * ROWS;
   const size_t off = (size_t)row0 * N;
-  const C* tw = static_cast<const C*>(P.tw);
-  const C* tin = static_cast<const C*>(D.t) + off;
-  auto gsrc = [&](int l, int q) { return tin[l * N + q]; };
+  const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
+  const C* tin = static_cast<const C*>(D.t);
+  auto gsrc = [&](int l, int q) { return tin[t_index<T, N>(row0 + l, q)]; };
   if constexpr (MODE == RI_PLAIN) {
     C* x = static_cast<C*>(D.x) + off;
     fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C v) { x[l * N + q] = v; });
