@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1411_5057_amd", "weights", "warmstart_256.f32"),
                     help="warm-start network parameters (float32, ABI order); skipped if missing")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--precond", choices=("paper", "jacobi", "none"), default="paper",
+                    help="inner preconditioner: the paper's (eq. 17), Jacobi (diag S) or none (plain CG)")
     ap.add_argument("--no-tune", action="store_true", help="skip the sub-batch autotuner")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
@@ -197,8 +199,9 @@ def main():
         del src, dst
     p0, b, m, lams = make_inputs(B, n, torch)
     shape = F.Shape(n, "haar", 4, p0.group_ptr, p0.group_idx)
+    pc = {"paper": F.FIRLS_PC_PAPER, "jacobi": F.FIRLS_PC_JACOBI, "none": F.FIRLS_PC_NONE}[a.precond]
     solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
-                      outer_tol=a.tau, eps=1e-10)
+                      outer_tol=a.tau, eps=1e-10, precond=pc)
     x = torch.zeros_like(b)
     items = [dict(b=b[i], mask=m[i], x=x[i], lam=lams[i]) for i in range(B)]
     chunk = solver.autotune(items) if not a.no_tune else 0
@@ -232,7 +235,8 @@ def main():
                                f"{K} PCG per outer, stop at rel. F_eps decrease {a.tau:g} (max {a.max_outer}), "
                                f"start: {'learned warm start (network + data consistency, A^H b fallback)' if use_learned else 'A^H b'}",
                    "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer,
-                   "start": "learned" if use_learned else "zero-filled", "sub_batch": chunk},
+                   "start": "learned" if use_learned else "zero-filled", "sub_batch": chunk,
+                   "precond": a.precond},
         "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
         "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
         "converged_frac": float(np.mean([r["converged"] for r in reps])),

@@ -184,7 +184,8 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id,
                     const void* p, void* q);
 
 /* z = P^{-1} r for the configured preconditioner at the weights of x_w
- * (eq. 17 exactly for Haar; SGS factors of eq. 40 for TV). */
+ * (FIRLS_PC_PAPER: eq. 17 exactly for Haar, SGS factors of eq. 40 for TV;
+ * FIRLS_PC_JACOBI: r / diag(S); FIRLS_PC_NONE: z = r). */
 int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id,
                      const uint8_t* mask, double lambda, const void* x_w,
                      const void* r, void* z);

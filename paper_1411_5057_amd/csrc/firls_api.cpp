@@ -347,28 +347,33 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStre
   return FIRLS_OK;
 }
 
-// K PCG iterations.  Haar: 3 launches per iteration (the update of one
-// iteration rides in the row pass of the next) and x += alpha p at the end;
-// TV: 4 launches per iteration.
+// K PCG iterations.  Haar with the paper's preconditioner: 3 launches per
+// iteration (the update of one iteration rides in the row pass of the
+// next) and x += alpha p at the end; Haar with the Jacobi or identity
+// preconditioner, and TV: 4 launches per iteration in the textbook order.
 int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
+  const bool fused = haar && h->cfg.precond == FIRLS_PC_PAPER;
   const dim3 rows(s.n / band_rows(s.n), c);
   const int K = h->cfg.pcg_iters;
   for (int k = 0; k < K; ++k) {
     P.k = k;
-    if (haar) {
+    if (fused) {
       if (k == 0) KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
       else KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
+    } else if (haar) {
+      KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
     } else {
       KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_Z], P, rows, st);
     }
     KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.n / C, c), st);
     KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
+    if (haar && !fused) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar, P, rows, st);
     if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
   }
-  if (haar) {
+  if (fused) {
     P.k = K - 1;
     KLAUNCH(h, FIRLS_PROF_LAST_X, s.sk->last_x, P, rows, st);
   }
@@ -757,7 +762,8 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
   if (cfg->max_outer < 0) return fail(FIRLS_E_INVALID, "max_outer must be >= 0");
   if (cfg->pcg_iters < 1 || cfg->pcg_iters > KMAX) return fail(FIRLS_E_INVALID, "pcg_iters must be in 1..64");
   if (!(cfg->outer_tol >= 0.0)) return fail(FIRLS_E_INVALID, "outer_tol must be >= 0");
-  if (cfg->precond != FIRLS_PC_PAPER) return fail(FIRLS_E_UNSUPPORTED, "only the paper's preconditioner is built");
+  if (cfg->precond != FIRLS_PC_PAPER && cfg->precond != FIRLS_PC_JACOBI && cfg->precond != FIRLS_PC_NONE)
+    return fail(FIRLS_E_INVALID, "precond must be FIRLS_PC_PAPER, FIRLS_PC_JACOBI or FIRLS_PC_NONE");
   firls_handle* h = new firls_handle();
   h->cfg = *cfg;
   h->cfg.shapes = nullptr;

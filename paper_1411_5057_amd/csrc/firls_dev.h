@@ -314,6 +314,30 @@ __device__ __forceinline__ void haar_col(cplx<T> (&v)[16], int L, int col) {
   }
 }
 
+// diag(Phi^T diag(d) Phi) from d (both in the in-place layout), in
+// registers: every coefficient reaches a pixel through one chain of level
+// steps with entries +-1/2, so the squared entries form the same tree with
+// every entry 1/4.  The transpose therefore replaces each 2x2 block by the
+// mean of its four values, levels from the coarsest down.
+template <int ST, typename T>
+__device__ __forceinline__ void haar_diag_level(T (&v)[16], int col) {
+  const bool active = (col & (ST - 1)) == 0;
+#pragma unroll
+  for (int s = 0; s < 16; s += 2 * ST) {
+    const T S = v[s] + v[s + ST];
+    const T So = __shfl_xor(S, ST, 64);
+    if (active) v[s] = v[s + ST] = (S + So) * (T)0.25;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void haar_diag_col(T (&v)[16], int L, int col) {
+  if (L >= 4) haar_diag_level<8>(v, col);
+  if (L >= 3) haar_diag_level<4>(v, col);
+  if (L >= 2) haar_diag_level<2>(v, col);
+  if (L >= 1) haar_diag_level<1>(v, col);
+}
+
 // Work units of a band of ROWS rows and N columns: unit u covers column
 // u % N of the 16-row group u / N.  Thread t owns units t, t + NT, ...
 template <int N, int ROWS>

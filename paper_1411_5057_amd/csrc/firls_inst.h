@@ -36,6 +36,10 @@ hipError_t L_col(const Params& P, dim3 g, hipStream_t st) {
   return launch_dyn(k_col<T, N, M>, lds_col_bytes<T, N>(), P, g, st);
 }
 template <typename T, int N>
+hipError_t L_update_haar(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_update_haar<T, N>, 0, P, g, st);
+}
+template <typename T, int N>
 hipError_t L_last_x(const Params& P, dim3 g, hipStream_t st) {
   return launch_dyn(k_last_x<T, N>, 0, P, g, st);
 }
@@ -86,6 +90,7 @@ SizeKernels make_size_kernels() {
   k.rowinv[RI_R0_TV] = L_rowinv<T, N, RI_R0_TV>;
   k.psi_sq_haar = L_psi_sq_haar<T, N>;
   k.last_x = L_last_x<T, N>;
+  k.update_haar = L_update_haar<T, N>;
   return k;
 }
 

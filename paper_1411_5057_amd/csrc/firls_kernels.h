@@ -60,6 +60,41 @@ __device__ __forceinline__ size_t t_index(int row, int col) {
   if (!P.state[s_].active) return;               \
   const SliceDesc& D = P.desc[s_];
 
+// The preconditioner on one tile column (16 rows of column ``col``; v in the
+// pixel domain, dg points at the weight d of the first row, row stride N):
+// acc += <v, P^{-1} v>, and with NEED_Z v becomes P^{-1} v.
+//   PC_PAPER : Phi^T ((Phi v) / (rho + lambda d))                 (eq. 17)
+//   PC_JACOBI: v / (rho + lambda diag(Phi^T diag(d) Phi))         (diag of S)
+//   PC_NONE  : v                                                  (plain CG)
+template <bool NEED_Z, int N, typename T>
+__device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int L, int col, T rho, T lam,
+                                             int pc, double& acc) {
+  if (pc == PC_PAPER) {
+    haar_col<false>(v, L, col);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const T iv = pc_inv(rho + lam * dg[s * N]);
+      acc += (double)(cabs2t(v[s]) * iv);
+      if (NEED_Z) v[s] = v[s] * iv;
+    }
+    if (NEED_Z) haar_col<true>(v, L, col);
+  } else if (pc == PC_JACOBI) {
+    T e[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) e[s] = dg[s * N];
+    haar_diag_col(e, L, col);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const T iv = pc_inv(rho + lam * e[s]);
+      acc += (double)(cabs2t(v[s]) * iv);
+      if (NEED_Z) v[s] = v[s] * iv;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc += (double)cabs2t(v[s]);
+  }
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // lambda (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c), periodic forward
@@ -152,14 +187,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
           v[s] = r[g] - q[g] * al;
           r[g] = v[s];
         }
-        haar_col<false>(v, P.L, col);
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const T iv = pc_inv(rhot + lam * d[(row + s) * N + col]);
-          acc += (double)(cabs2t(v[s]) * iv);
-          v[s] = v[s] * iv;
-        }
-        haar_col<true>(v, P.L, col);
+        precond_tile<true, N>(v, d + row * N + col, P.L, col, rhot, lam, P.precond, acc);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const int a = Lay::at(row + s, col);
@@ -171,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       const double tot = block_sum(acc, red);
       if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k)[blockIdx.x] = tot;
     } else if constexpr (MODE == RF_PCG_HAAR) {
-      // z = Phi^T ((Phi r) / (rho + lambda d)) in registers, p = z + beta p
+      // z = P^{-1} r in registers (precond_tile), p = z + beta p
       const C* r = static_cast<const C*>(D.r[0]) + off;
       const T* d = static_cast<const T*>(D.d) + off;
       const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
@@ -182,10 +210,8 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         C v[16];
 #pragma unroll
         for (int s = 0; s < 16; ++s) v[s] = r[(row + s) * N + col];
-        haar_col<false>(v, P.L, col);
-#pragma unroll
-        for (int s = 0; s < 16; ++s) v[s] = v[s] * pc_inv(rho + lam * d[(row + s) * N + col]);
-        haar_col<true>(v, P.L, col);
+        double unused = 0.0;
+        precond_tile<true, N>(v, d + row * N + col, P.L, col, rho, lam, P.precond, unused);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const int g = (row + s) * N + col;
@@ -344,12 +370,8 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
           out[(row + s) * N + col] = o;
           w[s] = o;
         }
-        // <o, P^{-1} o> = sum |Phi o|^2 / (rho + lambda d): <q, P^{-1} q>
-        // for the beta recurrence, or <r0, z0>
-        haar_col<false>(w, P.L, col);
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-          acc2 += (double)(cabs2t(w[s]) * pc_inv(rho + lam * d[(row + s) * N + col]));
+        // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
+        precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
       }
       const double t2 = block_sum(acc2, red);
       if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
@@ -392,6 +414,47 @@ __global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) sq[(row + s) * N + col] = (T)cabs2(v[s]);
   }
+}
+
+// Haar PCG update in the textbook order, for the Jacobi and identity
+// preconditioners (whose slower inner convergence makes the beta
+// recurrence of the fused step less accurate in single precision):
+// alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, and the partials of the
+// new <r, P^{-1} r>.  The next k_rowfwd (mode 1) forms z, beta and p.
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_update_haar(Params P) {
+  constexpr int ROWS = band_rows(N);
+  using C = cplx<T>;
+  using U = Units<N, ROWS>;
+  __shared__ double red[NT / 64];
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+  const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
+  C* x = static_cast<C*>(D.x) + off;
+  C* r = static_cast<C*>(D.r[0]) + off;
+  const C* p = static_cast<const C*>(D.p) + off;
+  const C* q = static_cast<const C*>(D.q) + off;
+  const T* d = static_cast<const T*>(D.d) + off;
+  const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < U::PER; ++k) {
+    if (!U::valid(k)) continue;
+    const int col = U::col(k), row = U::row(k);
+    C v[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int g = (row + s) * N + col;
+      x[g] = x[g] + p[g] * al;
+      v[s] = r[g] - q[g] * al;
+      r[g] = v[s];
+    }
+    precond_tile<false, N>(v, d + row * N + col, P.L, col, rho, lam, P.precond, acc);
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k + 1)[blockIdx.x] = tot;
 }
 
 // After the last PCG iteration (Haar): alpha = <r, z> / <p, q>, x += alpha p.
@@ -485,6 +548,7 @@ __global__ __launch_bounds__(NT) void k_group_d(Params P) {
 // D2^T W2 D2) (eq. 40; the L and U of eqs. 42-43) in red-black order:
 //   y_red = r / a;  y_black = (r - sum P_pq y_q) / a;
 //   z_black = y_black;  z_red = y_red - (sum P_pq z_q) / a.
+// With PC_JACOBI z = r / a (a = diag P = diag S) and with PC_NONE z = r.
 // Each workgroup owns a TV_TR x TV_TC tile and recomputes a two-pixel halo
 // of r (and a three-pixel halo of the weights) in LDS.  In UP_STEP mode
 // the residual is read from r[k & 1] and written to r[(k + 1) & 1], so a
@@ -544,7 +608,8 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
     if (red_cell) y[i] = rn[i] * ((T)1 / a);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < (RR - 2) * (RC - 2); i += NT) {
+  const int pc = P.precond;
+  for (int i = threadIdx.x; pc == PC_PAPER && i < (RR - 2) * (RC - 2); i += NT) {
     const int lr = 1 + i / (RC - 2), lc = 1 + i % (RC - 2);
     const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
     if (!red_cell) {
@@ -563,8 +628,8 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
     const int lr = H + i / TV_TC, lc = H + i % TV_TC;
     const int o = lr * RC + lc;
     const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
-    C zz = y[o];
-    if (red_cell) {
+    C zz = pc == PC_PAPER ? y[o] : (pc == PC_JACOBI ? rn[o] * ((T)1 / av[o]) : rn[o]);
+    if (pc == PC_PAPER && red_cell) {
       const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
       zz = zz + s * (lam / av[o]);
     }

@@ -14,6 +14,7 @@ struct SizeKernels {
   Launcher rowinv[5];
   Launcher psi_sq_haar;
   Launcher last_x;
+  Launcher update_haar;
 };
 
 // Kernels that depend on the precision only.

@@ -102,6 +102,25 @@ def test_precond(n, psi, prec):
     assert rel(to_np(z), ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("kind", ["jacobi", "none"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("n", [32, 256])
+def test_precond_ablation_variants(n, psi, prec, kind):
+    """Jacobi (diag S) and identity preconditioners against the oracle's."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    p = problem(n, psi, L=3 if psi == "haar" else None)
+    s = solver(p, prec, precond={"jacobi": F.FIRLS_PC_JACOBI, "none": F.FIRLS_PC_NONE}[kind])
+    ops = Operators.from_problem(p)
+    xw, r = crandn(16, n), crandn(17, n)
+    _, d = ops.weights(xw)
+    ref = ops.precond(d, kind)(r)
+    z = torch.empty((n, n), dtype=torch.complex64 if prec == "fp32" else torch.complex128, device="cuda")
+    s.precond(dev_mask(p.mask), p.lam, dev_complex(xw, prec), dev_complex(r, prec), z)
+    assert rel(to_np(z), ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("psi", ["haar", "tv"])
 @pytest.mark.parametrize("n", [32, 128, 256])
