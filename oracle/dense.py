@@ -65,9 +65,26 @@ def D2(n):
     return shift(n, 0, 1) - np.eye(n * n)
 
 
+def bidiag(n):
+    """n x n: ones on the diagonal, minus ones just below (the paper's
+    difference matrix of Section 4.1 on one image column or row)."""
+    return np.eye(n) - np.eye(n, k=-1)
+
+
+def D1p(n):
+    """The paper's vertical differences on the row-major vector: B on the row index."""
+    return np.kron(bidiag(n), np.eye(n))
+
+
+def D2p(n):
+    return np.kron(np.eye(n), bidiag(n))
+
+
 def Psi(n, psi, L=0):
     if psi == "haar":
         return Phi(n, L)
+    if psi == "tvp":
+        return np.vstack([D1p(n), D2p(n)])
     return np.vstack([D1(n), D2(n)])
 
 

@@ -69,11 +69,15 @@ class Operators:
     def psi_fwd(self, x):
         if self.psi == "haar":
             return haar.fwd(x, self.levels).ravel()
+        if self.psi == "tvp":
+            return tv.fwd_p(x)
         return tv.fwd(x)
 
     def psi_adj(self, z):
         if self.psi == "haar":
             return haar.adj(z.reshape(self.n, self.n), self.levels)
+        if self.psi == "tvp":
+            return tv.adj_p(z, self.n)
         return tv.adj(z, self.n)
 
     @property
@@ -118,16 +122,25 @@ class Operators:
         return fourier.AHA(x, self.mask) + self.lam * self.psi_adj(d * self.psi_fwd(x))
 
     def _tv_bands(self, d):
+        """(diagonal a of P = rho I + lambda (D1^T W1 D1 + D2^T W2 D2), W1, W2)."""
         n = self.n
         d1 = d[: n * n].reshape(n, n)
         d2 = d[n * n:].reshape(n, n)
-        a = self.rho + self.lam * (d1 + np.roll(d1, 1, axis=0) + d2 + np.roll(d2, 1, axis=1))
-        return a, d1, d2
+        return self.rho + self.lam * self.psi_diag(d), d1, d2
 
     def _tv_offdiag(self, v, d1, d2):
-        """sum_{q != p} P[p, q] v[q] for P of eq. (40) with periodic D1, D2:
-        P[p, p+e1] = -lam d1[p], P[p, p-e1] = -lam d1[p-e1], same for e2."""
+        """sum_{q != p} P[p, q] v[q] for P of eq. (40).
+        Periodic: P[p, p+e1] = -lam d1[p], P[p, p-e1] = -lam d1[p-e1].
+        Paper's D: P[p, p-e1] = -lam d1[p] (r >= 1), P[p, p+e1] = -lam d1[p+e1]
+        (r <= n-2), the same along columns with d2."""
         lam = self.lam
+        if self.psi == "tvp":
+            out = np.zeros_like(v)
+            out[1:, :] += d1[1:, :] * v[:-1, :]
+            out[:-1, :] += d1[1:, :] * v[1:, :]
+            out[:, 1:] += d2[:, 1:] * v[:, :-1]
+            out[:, :-1] += d2[:, 1:] * v[:, 1:]
+            return -lam * out
         return -lam * (d1 * np.roll(v, -1, axis=0) + np.roll(d1 * v, 1, axis=0)
                        + d2 * np.roll(v, -1, axis=1) + np.roll(d2 * v, 1, axis=1))
 
@@ -151,7 +164,7 @@ class Operators:
         if kind == "jacobi":
             dg = rho + lam * self.psi_diag(d)
             return lambda r: r / dg
-        assert self.psi == "tv"
+        assert self.psi in ("tv", "tvp")
         a, d1, d2 = self._tv_bands(d)
         if kind == "sgs_rb":
             ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
@@ -169,9 +182,21 @@ class Operators:
         raise ValueError(kind)
 
     def tv_neighbours(self, p, d1, d2):
-        """[(q, P[p, q])] for the four periodic neighbours of pixel p."""
+        """[(q, P[p, q])] for the neighbours of pixel p (four periodic ones,
+        or those inside the image for the paper's D)."""
         n, lam = self.n, self.lam
         r, c = divmod(p, n)
+        if self.psi == "tvp":
+            out = []
+            if r >= 1:
+                out.append(((r - 1) * n + c, -lam * d1[r, c]))
+            if r <= n - 2:
+                out.append(((r + 1) * n + c, -lam * d1[r + 1, c]))
+            if c >= 1:
+                out.append((r * n + c - 1, -lam * d2[r, c]))
+            if c <= n - 2:
+                out.append((r * n + c + 1, -lam * d2[r, c + 1]))
+            return out
         return [(((r + 1) % n) * n + c, -lam * d1[r, c]),
                 (((r - 1) % n) * n + c, -lam * d1[(r - 1) % n, c]),
                 (r * n + (c + 1) % n, -lam * d2[r, c]),
@@ -202,10 +227,16 @@ class Operators:
     def psi_diag(self, d):
         """diag(Psi^T diag(d) Psi) as an n x n array."""
         n = self.n
-        if self.psi == "tv":
+        if self.psi in ("tv", "tvp"):
             d1 = d[: n * n].reshape(n, n)
             d2 = d[n * n:].reshape(n, n)
-            return d1 + np.roll(d1, 1, axis=0) + d2 + np.roll(d2, 1, axis=1)
+            if self.psi == "tv":
+                return d1 + np.roll(d1, 1, axis=0) + d2 + np.roll(d2, 1, axis=1)
+            # column j of D1 has +1 at row j and -1 at row j + e1 (if inside)
+            out = d1 + d2
+            out[:-1, :] += d1[1:, :]
+            out[:, :-1] += d2[:, 1:]
+            return out
         # Haar: every coefficient reaches a pixel through one chain of 1D
         # steps whose entries are +-1/sqrt(2), so Phi[j, p]^2 is a product of
         # 1/2 factors: apply the inverse transform with (a + d) / 2 to both

@@ -206,7 +206,7 @@ def groups_tv_aniso(n: int):
 @dataclasses.dataclass
 class Problem:
     n: int
-    psi: str                     # "haar" or "tv"
+    psi: str                     # "haar", "tv" (periodic) or "tvp" (the paper's D)
     levels: int                  # Haar levels (0 for TV)
     lam: float
     eps: float

@@ -111,6 +111,33 @@ def test_tv_hand_values():
     assert tv.d2(x)[1, 2] == x[1, 0] - x[1, 2]
 
 
+def test_paper_tv_matches_printed_matrices_and_adjoint():
+    """The paper's D1, D2 (Section 4.1): ones on the diagonal, minus ones one
+    pixel above (D1) or one pixel to the left (D2), no wrap; built here as
+    Kronecker products of the printed bidiagonal with the identity."""
+    n = 6
+    rs = np.random.default_rng(8)
+    x = crandn(rs, n, n)
+    np.testing.assert_allclose(tv.d1p(x).ravel(), dense.D1p(n) @ x.ravel(), atol=1e-13)
+    np.testing.assert_allclose(tv.d2p(x).ravel(), dense.D2p(n) @ x.ravel(), atol=1e-13)
+    y = crandn(rs, 2 * n * n)
+    assert abs(np.vdot(tv.fwd_p(x), y) - np.vdot(x.ravel(), tv.adj_p(y, n).ravel())) < 1e-11
+    # injective: the first row of each difference keeps the pixel itself
+    P = dense.Psi(n, "tvp")
+    assert np.linalg.matrix_rank(P) == n * n
+
+
+def test_paper_tv_hand_values():
+    x = np.arange(9, dtype=np.float64).reshape(3, 3) + 1.0
+    assert tv.d1p(x)[0, 2] == x[0, 2]                # first row: identity
+    assert tv.d1p(x)[2, 1] == x[2, 1] - x[1, 1]
+    assert tv.d2p(x)[1, 0] == x[1, 0]                # first column: identity
+    assert tv.d2p(x)[1, 2] == x[1, 2] - x[1, 1]
+    # a constant image leaves only the boundary identity rows
+    z = tv.fwd_p(np.full((3, 3), 2.0))
+    assert np.count_nonzero(z) == 3 + 3 and np.all(z[z != 0] == 2.0)
+
+
 # -- Group replication G (Section 3.1, Fig. 1) ----------------------------------
 
 def dense_G(ptr, idx, count):
@@ -166,7 +193,7 @@ def test_quadtree_groups_membership():
 
 # -- System S (eq. 15, eq. 39) and its dense form ------------------------------------
 
-@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("psi", ["haar", "tv", "tvp"])
 def test_S_matches_dense(psi):
     n = 8
     p = synth.make_problem(n, 4, psi=psi, levels=2 if psi == "haar" else 0,
@@ -184,7 +211,7 @@ def test_S_matches_dense(psi):
 
 def test_psi_diag_matches_dense():
     rs = np.random.default_rng(14)
-    for psi, L in (("haar", 2), ("haar", 3), ("tv", 0)):
+    for psi, L in (("haar", 2), ("haar", 3), ("tv", 0), ("tvp", 0)):
         p = synth.make_problem(8, 1, psi=psi, levels=L,
                                groups="singletons" if psi == "haar" else "tv_iso",
                                lam=0.05, sigma=0.01)

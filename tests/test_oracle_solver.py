@@ -26,9 +26,9 @@ def haar_problem(n=8, L=2, groups="quadtree", frac=0.3, seed=3, lam=0.05, mask="
         frac=frac, mask_kind=mask))
 
 
-def tv_problem(n=8, frac=0.3, seed=3, lam=0.05):
+def tv_problem(n=8, frac=0.3, seed=3, lam=0.05, psi="tv"):
     return Operators.from_problem(synth.make_problem(
-        n, seed, psi="tv", levels=0, groups="tv_iso", lam=lam, sigma=0.01, frac=frac))
+        n, seed, psi=psi, levels=0, groups="tv_iso", lam=lam, sigma=0.01, frac=frac))
 
 
 def dense_P(ops, d):
@@ -71,9 +71,10 @@ def sgs_dense(Pm, order):
     return M[np.ix_(inv, inv)]
 
 
+@pytest.mark.parametrize("psi", ["tv", "tvp"])
 @pytest.mark.parametrize("n", [4, 8])
-def test_tv_sgs_matches_dense_factors(n):
-    ops = tv_problem(n=n)
+def test_tv_sgs_matches_dense_factors(n, psi):
+    ops = tv_problem(n=n, psi=psi)
     rs = np.random.default_rng(n)
     d = np.repeat(rs.uniform(0.2, 4.0, n * n), 1)
     d = np.concatenate([d, d])                      # isotropic: same W for D1, D2 rows
@@ -109,12 +110,12 @@ def test_tv_sgs_general_weights_and_small_lambda():
 
 # -- PCG (Section 3.2) -------------------------------------------------------------------
 
-@pytest.mark.parametrize("kind", ["haar", "tv"])
+@pytest.mark.parametrize("kind", ["haar", "tv", "tvp"])
 def test_pcg_converges_to_cholesky_solution(kind):
-    ops = haar_problem() if kind == "haar" else tv_problem()
+    ops = haar_problem() if kind == "haar" else tv_problem(psi=kind)
     rs = np.random.default_rng(4)
     d = rs.uniform(0.5, 20.0, ops.n_coef)
-    if kind == "tv":
+    if kind != "haar":
         d[ops.n ** 2:] = d[:ops.n ** 2]
     xs = dense.solve_S(ops, d)
     x, _ = pcg(ops, d, ops.AHb(), 200)
@@ -179,23 +180,23 @@ def test_Q_majorises_and_decreases_along_pcg():
 
 # -- outer loop (Algorithms 2, 3; Theorems 2, 3) ----------------------------------
 
-@pytest.mark.parametrize("kind,K", [("haar", 3), ("haar", 20), ("tv", 3), ("tv", 20)])
+@pytest.mark.parametrize("kind,K", [("haar", 3), ("haar", 20), ("tv", 3), ("tv", 20), ("tvp", 3), ("tvp", 20)])
 def test_objective_monotone_any_pcg_count(kind, K):
     """Theorem 2 holds whatever the number of inner iterations."""
-    ops = haar_problem(n=16, L=3, lam=0.035) if kind == "haar" else tv_problem(n=16, lam=0.02)
+    ops = haar_problem(n=16, L=3, lam=0.035) if kind == "haar" else tv_problem(n=16, lam=0.02, psi=kind)
     rep = firls(ops, 15, K)
     h = np.asarray(rep.history)
     assert np.all(np.diff(h) <= 1e-12 * h[:-1])
 
 
-@pytest.mark.parametrize("kind,bound", [("haar", 2e-4), ("tv", 1e-5)])
+@pytest.mark.parametrize("kind,bound", [("haar", 2e-4), ("tv", 1e-5), ("tvp", 1e-5)])
 def test_stationarity_at_convergence(kind, bound):
     """Theorem 3: the iterates approach a point where S(W(x)) x = A^H b,
     the gradient of F_eps (eps = 1e-6 keeps the run short)."""
     if kind == "haar":
         ops = haar_problem(n=16, L=3, lam=0.035)
     else:
-        ops = tv_problem(n=16, lam=0.02)
+        ops = tv_problem(n=16, lam=0.02, psi=kind)
     ops.eps = 1e-6
     s = [stationarity(ops, firls(ops, T, 30).x) for T in (20, 50, 100)]
     assert s[0] > s[1] > s[2] and s[2] < bound
