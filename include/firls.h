@@ -56,7 +56,14 @@ enum {
   FIRLS_W_MAXITER = 1        /* stopped at max_outer before the tolerance */
 };
 
-enum { FIRLS_PSI_HAAR = 0, FIRLS_PSI_TV = 1 };
+/* Sparsifying transform Psi.  HAAR: orthonormal L-level 2D Haar (Section
+ * 3, eq. 17).  TV: first-order differences with a periodic boundary,
+ * (D1 x)[r,c] = x[r+1,c] - x[r,c], (D2 x)[r,c] = x[r,c+1] - x[r,c] mod n.
+ * TV_PAPER: the difference matrices printed in Section 4.1 (ones on the
+ * diagonal, minus ones one pixel above for D1 / to the left for D2, no
+ * wrap), so (D1 x)[r,c] = x[r,c] - x[r-1,c] with (D1 x)[0,c] = x[0,c], and
+ * likewise along rows. */
+enum { FIRLS_PSI_HAAR = 0, FIRLS_PSI_TV = 1, FIRLS_PSI_TV_PAPER = 2 };
 enum { FIRLS_FP64 = 0, FIRLS_FP32 = 1 };
 
 /* Preconditioner of the inner PCG.  PAPER is the paper's choice: eq. (17)
@@ -66,7 +73,7 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
 
 /* One image geometry and regulariser.
  *   n           image side; n in {16, 32, 48, 64, 96, 128, 192, 256, 384, 512}.
- *   psi         FIRLS_PSI_HAAR or FIRLS_PSI_TV.
+ *   psi         FIRLS_PSI_HAAR, FIRLS_PSI_TV or FIRLS_PSI_TV_PAPER.
  *   levels      Haar levels, 1 <= L <= 4, n % 2^L == 0.  Ignored for TV.
  *   n_groups    number of groups s; 0 with NULL pointers selects the
  *               default map: singletons for Haar (standard sparsity), pixel
@@ -76,8 +83,8 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
  *               rows of the transform output.  Haar: Mallat index r * n + c
  *               of the coefficient (top-left block = coarsest approximation,
  *               level-l details in [0,h)x[h,2h), [h,2h)x[0,h), [h,2h)^2
- *               with h = n / 2^l).  TV: p for (D1 x)[p], N + p for
- *               (D2 x)[p], N = n^2.  A coefficient may sit in several groups
+ *               with h = n / 2^l).  TV, TV_PAPER: p for (D1 x)[p],
+ *               N + p for (D2 x)[p], N = n^2, p = r * n + c.  A coefficient may sit in several groups
  *               (overlap through G, Section 3.1, Fig. 1); a coefficient in
  *               no group is not penalised.
  * The arrays are copied at create; the caller keeps ownership. */

@@ -39,6 +39,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Shape {
   int n = 0, psi = 0, L = 0, n_groups = 0, n_coef = 0;
+  int tvb = 0;   // TV boundary: 0 periodic, 1 the paper's non-periodic D
   int64_t n_members = 0;
   int32_t* d_gptr = nullptr;
   int32_t* d_gidx = nullptr;
@@ -261,6 +262,7 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.shape.tptr = s.d_tptr;
   P.shape.tidx = s.d_tidx;
   P.shape.perm = s.d_perm;
+  P.tvb = s.tvb;
   P.shape.n_groups = s.n_groups;
   P.shape.n_coef = s.n_coef;
   P.n = s.n;
@@ -628,8 +630,10 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
     if (n % (1 << in.levels)) return fail(FIRLS_E_INVALID, "n must be a multiple of 2^levels");
     s.L = in.levels;
     s.n_coef = n * n;
-  } else if (in.psi == FIRLS_PSI_TV) {
+  } else if (in.psi == FIRLS_PSI_TV || in.psi == FIRLS_PSI_TV_PAPER) {
     if (n % TV_TC || n % TV_TR) return fail(FIRLS_E_UNSUPPORTED, "TV needs n to be a multiple of 32");
+    s.psi = PSI_TV;
+    s.tvb = in.psi == FIRLS_PSI_TV_PAPER ? 1 : 0;
     s.L = 0;
     s.n_coef = 2 * n * n;
   } else {
@@ -670,6 +674,15 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   if (s.psi == FIRLS_PSI_HAAR) {
     for (int r = 0; r < n; ++r)
       for (int c = 0; c < n; ++c) perm[r * n + c] = haar_internal_index(n, s.L, r, c);
+  } else if (s.tvb) {
+    // the paper's coefficient of pixel (r, c) lives in forward slot (r-1, c)
+    // of D1 and (r, c-1) of D2 (indices mod n)
+    const int N = n * n;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        perm[r * n + c] = ((r + n - 1) % n) * n + c;
+        perm[N + r * n + c] = N + r * n + (c + n - 1) % n;
+      }
   } else {
     for (int i = 0; i < s.n_coef; ++i) perm[i] = i;
   }

@@ -66,10 +66,10 @@ __device__ __forceinline__ size_t t_index(int row, int col) {
 //   PC_PAPER : Phi^T ((Phi v) / (rho + lambda d))                 (eq. 17)
 //   PC_JACOBI: v / (rho + lambda diag(Phi^T diag(d) Phi))         (diag of S)
 //   PC_NONE  : v                                                  (plain CG)
-template <bool NEED_Z, int N, typename T>
-__device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int L, int col, T rho, T lam,
-                                             int pc, double& acc) {
-  if (pc == PC_PAPER) {
+template <bool NEED_Z, int N, int PC, typename T>
+__device__ __forceinline__ void precond_tile_k(cplx<T> (&v)[16], const T* dg, int L, int col, T rho, T lam,
+                                               double& acc) {
+  if constexpr (PC == PC_PAPER) {
     haar_col<false>(v, L, col);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -78,7 +78,7 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
       if (NEED_Z) v[s] = v[s] * iv;
     }
     if (NEED_Z) haar_col<true>(v, L, col);
-  } else if (pc == PC_JACOBI) {
+  } else if constexpr (PC == PC_JACOBI) {
     T e[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) e[s] = dg[s * N];
@@ -95,17 +95,40 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
   }
 }
 
+// The same with the kind chosen at run time (uniform per launch).
+template <bool NEED_Z, int N, typename T>
+__device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int L, int col, T rho, T lam,
+                                             int pc, double& acc) {
+  if (pc == PC_PAPER) precond_tile_k<NEED_Z, N, PC_PAPER>(v, dg, L, col, rho, lam, acc);
+  else if (pc == PC_JACOBI) precond_tile_k<NEED_Z, N, PC_JACOBI>(v, dg, L, col, rho, lam, acc);
+  else precond_tile_k<NEED_Z, N, PC_NONE>(v, dg, L, col, rho, lam, acc);
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// lambda (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c), periodic forward
-// differences (D1 v)[r,c] = v[r+1,c] - v[r,c], (D2 v)[r,c] = v[r,c+1] - v[r,c].
+// TV coefficients are stored in forward slots: slot (r, c) of D1 holds
+// v[r+1, c] - s1(r) v[r, c] and slot (r, c) of D2 holds v[r, c+1] - s2(c) v[r, c]
+// (indices mod n).  Periodic differences have s = 1 everywhere.  The paper's
+// non-periodic D (backward differences whose first row is the pixel itself,
+// Section 4.1) is the same with s1(n-1) = s2(n-1) = 0: its coefficient for
+// pixel (r, c) sits in slot (r-1, c) of D1 / (r, c-1) of D2, and the slots
+// that wrap hold the identity rows.  The host maps the caller's coefficient
+// order to these slots.
+__device__ __forceinline__ bool tv_cut(int tvb, int i, int n) { return tvb && i == n - 1; }
+
+// lambda (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c) without lambda:
+//   s1(r) W1[r] (v[r] - v[r+1]) + W1[r-1] (v[r] - s1(r-1) v[r-1]) + (same along c)
 template <typename T>
-__device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, const T* w2, int n, int r, int c) {
+__device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, const T* w2, int n, int r, int c,
+                                             int tvb) {
   const int rp = r + 1 == n ? 0 : r + 1, rm = r == 0 ? n - 1 : r - 1;
   const int cp = c + 1 == n ? 0 : c + 1, cm = c == 0 ? n - 1 : c - 1;
   const cplx<T> v0 = v[r * n + c];
-  const T a = w1[r * n + c], b = w1[rm * n + c], e = w2[r * n + c], f = w2[r * n + cm];
-  return (v0 - v[rp * n + c]) * a + (v0 - v[rm * n + c]) * b + (v0 - v[r * n + cp]) * e + (v0 - v[r * n + cm]) * f;
+  const T a = tv_cut(tvb, r, n) ? (T)0 : w1[r * n + c], b = w1[rm * n + c];
+  const T e = tv_cut(tvb, c, n) ? (T)0 : w2[r * n + c], f = w2[r * n + cm];
+  const cplx<T> vrm = tv_cut(tvb, rm, n) ? cplx<T>{(T)0, (T)0} : v[rm * n + c];
+  const cplx<T> vcm = tv_cut(tvb, cm, n) ? cplx<T>{(T)0, (T)0} : v[r * n + cm];
+  return (v0 - v[rp * n + c]) * a + (v0 - vrm) * b + (v0 - v[r * n + cp]) * e + (v0 - vcm) * f;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
           v[s] = r[g] - q[g] * al;
           r[g] = v[s];
         }
-        precond_tile<true, N>(v, d + row * N + col, P.L, col, rhot, lam, P.precond, acc);
+        precond_tile_k<true, N, PC_PAPER>(v, d + row * N + col, P.L, col, rhot, lam, acc);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const int a = Lay::at(row + s, col);
@@ -371,7 +394,12 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
           w[s] = o;
         }
         // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
-        precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
+        if constexpr (SP) {
+          // only the fused step (paper's preconditioner) uses <q, P^{-1} q>
+          if (P.precond == PC_PAPER) precond_tile_k<false, N, PC_PAPER>(w, d + row * N + col, P.L, col, rho, lam, acc2);
+        } else {
+          precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
+        }
       }
       const double t2 = block_sum(acc2, red);
       if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
@@ -380,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       const T* w2 = w1 + (size_t)N * N;
       fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
         const int i = l * N + q;
-        const C o = val + tv_normal<T>(vfull, w1, w2, N, row0 + l, q) * (lam * sgn);
+        const C o = val + tv_normal<T>(vfull, w1, w2, N, row0 + l, q, P.tvb) * (lam * sgn);
         out[i] = o;
         if (SP) acc += cdot(v[i], o);
       });
@@ -489,9 +517,9 @@ __global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
   for (int i = blockIdx.x * NT * 4 + threadIdx.x, e = 0; e < 4 && i < total; ++e, i += NT) {
     const int r = i / n, c = i - r * n;
     const int rp = r + 1 == n ? 0 : r + 1, cp = c + 1 == n ? 0 : c + 1;
-    const C v = x[i];
-    sq[i] = (T)cabs2(x[rp * n + c] - v);
-    sq[total + i] = (T)cabs2(x[r * n + cp] - v);
+    const C v = x[i], z{(T)0, (T)0};
+    sq[i] = (T)cabs2(x[rp * n + c] - (tv_cut(P.tvb, r, n) ? z : v));
+    sq[total + i] = (T)cabs2(x[r * n + cp] - (tv_cut(P.tvb, c, n) ? z : v));
   }
 }
 
@@ -579,11 +607,13 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
     al = (T)(pq > 0.0 ? rz / pq : 0.0);
   }
   const C* q = static_cast<const C*>(D.q);
+  // coupling weights: slots that hold identity rows (tvb) couple nothing
   for (int i = threadIdx.x; i < WR * WC; i += NT) {
     const int lr = i / WC, lc = i - lr * WC;
-    const size_t g = (size_t)wrapi(r0 - H - 1 + lr, n) * n + wrapi(c0 - H - 1 + lc, n);
-    w1[i] = d1[g];
-    w2[i] = d2[g];
+    const int gr = wrapi(r0 - H - 1 + lr, n), gc = wrapi(c0 - H - 1 + lc, n);
+    const size_t g = (size_t)gr * n + gc;
+    w1[i] = tv_cut(P.tvb, gr, n) ? (T)0 : d1[g];
+    w2[i] = tv_cut(P.tvb, gc, n) ? (T)0 : d2[g];
   }
   for (int i = threadIdx.x; i < RR * RC; i += NT) {
     const int lr = i / RC, lc = i - lr * RC;
@@ -602,7 +632,14 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
 #define W2M(lr, lc) w2[((lr) + 1) * WC + (lc)]
   for (int i = threadIdx.x; i < RR * RC; i += NT) {
     const int lr = i / RC, lc = i - lr * RC;
-    const T a = rho + lam * (W1P(lr, lc) + W1M(lr, lc) + W2P(lr, lc) + W2M(lr, lc));
+    T a = rho + lam * (W1P(lr, lc) + W1M(lr, lc) + W2P(lr, lc) + W2M(lr, lc));
+    if (P.tvb) {
+      // the identity-row slot of pixel row 0 / column 0 adds its weight to
+      // the diagonal only
+      const int gr = wrapi(r0 - H + lr, n), gc = wrapi(c0 - H + lc, n);
+      if (gr == 0) a += lam * d1[(size_t)(n - 1) * n + gc];
+      if (gc == 0) a += lam * d2[(size_t)gr * n + n - 1];
+    }
     av[i] = a;
     const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
     if (red_cell) y[i] = rn[i] * ((T)1 / a);

@@ -111,6 +111,7 @@ struct Params {
   int32_t ndata;
   int32_t nreg;
   int32_t no_data;       // objective check: take the data term as 0
+  int32_t tvb;           // TV boundary: 0 periodic, 1 the paper's non-periodic D
   double eps;
   double tau;
   void* out;             // op entry points: extra output

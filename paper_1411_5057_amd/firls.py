@@ -25,6 +25,7 @@ FIRLS_E_NONFINITE = -5
 FIRLS_W_MAXITER = 1
 FIRLS_PSI_HAAR = 0
 FIRLS_PSI_TV = 1
+FIRLS_PSI_TV_PAPER = 2
 FIRLS_FP64 = 0
 FIRLS_FP32 = 1
 FIRLS_PC_PAPER = 0
@@ -332,7 +333,7 @@ class Shape:
     def c(self) -> firls_shape:
         s = firls_shape()
         s.n = self.n
-        s.psi = FIRLS_PSI_HAAR if self.psi == "haar" else FIRLS_PSI_TV
+        s.psi = {"haar": FIRLS_PSI_HAAR, "tv": FIRLS_PSI_TV, "tvp": FIRLS_PSI_TV_PAPER}[self.psi]
         s.levels = self.levels
         if self.group_ptr is not None:
             s.n_groups = len(self.group_ptr) - 1

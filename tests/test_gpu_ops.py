@@ -26,7 +26,7 @@ def problem(n, psi, seed=1, groups=None, L=None):
         L = L if L is not None else (4 if n % 16 == 0 else 3)
         return synth.make_problem(n, seed, psi="haar", levels=L, groups=groups or "quadtree",
                                   lam=0.035, sigma=0.01, frac=0.25)
-    return synth.make_problem(n, seed, psi="tv", levels=0, groups=groups or "tv_iso",
+    return synth.make_problem(n, seed, psi=psi, levels=0, groups=groups or "tv_iso",
                               lam=0.02, sigma=0.01, frac=0.25)
 
 
@@ -56,7 +56,8 @@ def test_adjoint(n, prec):
 @pytest.mark.parametrize("prec,psi,L,groups", [
     ("fp32", "haar", 4, "quadtree"), ("fp32", "haar", 3, "singletons"), ("fp32", "haar", 2, "quadtree"),
     ("fp64", "haar", 3, "quadtree"), ("fp64", "haar", 1, "singletons"),
-    ("fp32", "tv", 0, "tv_iso"), ("fp32", "tv", 0, "tv_aniso"), ("fp64", "tv", 0, "tv_iso")])
+    ("fp32", "tv", 0, "tv_iso"), ("fp32", "tv", 0, "tv_aniso"), ("fp64", "tv", 0, "tv_iso"),
+    ("fp32", "tvp", 0, "tv_iso"), ("fp32", "tvp", 0, "tv_aniso"), ("fp64", "tvp", 0, "tv_iso")])
 @pytest.mark.parametrize("n", [32, 96, 256])
 def test_weights(n, prec, psi, L, groups):
     torch = torch_cuda()
@@ -71,7 +72,7 @@ def test_weights(n, prec, psi, L, groups):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("psi", ["haar", "tv", "tvp"])
 @pytest.mark.parametrize("n", [32, 64, 96, 192, 256, 512])
 def test_system(n, psi, prec):
     torch = torch_cuda()
@@ -87,7 +88,7 @@ def test_system(n, psi, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("psi", ["haar", "tv", "tvp"])
 @pytest.mark.parametrize("n", [32, 64, 192, 256])
 def test_precond(n, psi, prec):
     torch = torch_cuda()
@@ -104,7 +105,7 @@ def test_precond(n, psi, prec):
 
 @pytest.mark.parametrize("kind", ["jacobi", "none"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("psi", ["haar", "tv", "tvp"])
 @pytest.mark.parametrize("n", [32, 256])
 def test_precond_ablation_variants(n, psi, prec, kind):
     """Jacobi (diag S) and identity preconditioners against the oracle's."""
@@ -122,7 +123,7 @@ def test_precond_ablation_variants(n, psi, prec, kind):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("psi", ["haar", "tv"])
+@pytest.mark.parametrize("psi", ["haar", "tv", "tvp"])
 @pytest.mark.parametrize("n", [32, 128, 256])
 def test_objective(n, psi, prec):
     p = problem(n, psi, L=3)

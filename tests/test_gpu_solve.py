@@ -109,6 +109,18 @@ def test_preconditioner_ablation_solves(psi, kind, prec):
     assert rel(x, ref.x) <= max(1e-8 if prec == "fp64" else 1e-4, 20 * dx), (rel(x, ref.x), dx)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("groups", ["tv_iso", "tv_aniso"])
+def test_tv_paper_boundary(groups, prec):
+    """The paper's non-periodic difference matrices (Section 4.1), isotropic
+    and anisotropic (l1) TV, red-black SGS preconditioner."""
+    p = synth.make_problem(64, 13, psi="tvp", levels=0, groups=groups, lam=0.01, sigma=0.005,
+                           n_ellipses=12, mask_kind="radial", frac=0.15, ramp=True)
+    x, rep, ref = check(p, prec, 8, 20)
+    if prec == "fp64":
+        assert rel(x, ref.x) < 1e-8
+
+
 def test_tv_anisotropic_groups():
     p = synth.make_problem(64, 6, psi="tv", levels=0, groups="tv_aniso", lam=0.01, sigma=0.005)
     check(p, "fp32", 6, 15)
