@@ -10,10 +10,13 @@ Modules
 -------
 fourier  undersampled Fourier operator A = R F and its adjoint (Section 5.4)
 haar     orthonormal 2D Haar transform Phi, Mallat layout (Section 3.1)
-tv       periodic forward differences D1, D2 (Section 4.1)
+tv       first-order differences D1, D2: periodic, and the paper's
+         non-periodic matrices (Section 4.1)
 groups   group weights W and replicated weights d = diag(G^T W G) (eqs. 12-13)
 firls    system S, preconditioners, PCG, the FIRLS_OG / FIRLS_TV outer loops
-         (Algorithms 2 and 3; eqs. 15, 17, 39-43)
+         (Algorithms 2 and 3; eqs. 15, 17, 39-43); C contrasts are one
+         stacked problem with block-diagonal A and Psi and groups across
+         contrasts (FIRLS_MT, FIRLS_JTV; Section 5.6)
 dense    dense matrices of every operator for tiny images, Cholesky solves,
          closed-form group shrinkage
 cnn      conv3x3 network for the learned warm start: forward, backward,

@@ -56,6 +56,7 @@ class Operators:
     b: np.ndarray
     group_ptr: np.ndarray
     group_idx: np.ndarray
+    C: int = 1          # contrasts (Section 5.6); x, mask, b are (C, n, n) when C > 1
 
     @classmethod
     def from_problem(cls, p, eps: Optional[float] = None, lam: Optional[float] = None):
@@ -63,26 +64,55 @@ class Operators:
                    lam=p.lam if lam is None else lam,
                    eps=p.eps if eps is None else eps,
                    mask=p.mask.astype(np.float64), b=p.mask * p.b,
-                   group_ptr=p.group_ptr, group_idx=p.group_idx)
+                   group_ptr=p.group_ptr, group_idx=p.group_idx, C=getattr(p, "C", 1))
 
     # -- Psi and its adjoint ------------------------------------------------
-    def psi_fwd(self, x):
+    # With C contrasts Psi is block diagonal: Psi x = [Psi x_0; ...; Psi x_{C-1}]
+    # for Haar; for TV the D1 rows of all contrasts come first, then the D2
+    # rows (so a joint TV group lists 2C rows).
+    def _psi_fwd1(self, x):
         if self.psi == "haar":
             return haar.fwd(x, self.levels).ravel()
         if self.psi == "tvp":
             return tv.fwd_p(x)
         return tv.fwd(x)
 
-    def psi_adj(self, z):
+    def _psi_adj1(self, z):
         if self.psi == "haar":
             return haar.adj(z.reshape(self.n, self.n), self.levels)
         if self.psi == "tvp":
             return tv.adj_p(z, self.n)
         return tv.adj(z, self.n)
 
+    def psi_fwd(self, x):
+        if self.C == 1:
+            return self._psi_fwd1(x)
+        zs = [self._psi_fwd1(x[c]) for c in range(self.C)]
+        if self.psi == "haar":
+            return np.concatenate(zs)
+        N = self.n * self.n
+        return np.concatenate([z[:N] for z in zs] + [z[N:] for z in zs])
+
+    def psi_adj(self, z):
+        if self.C == 1:
+            return self._psi_adj1(z)
+        N, C = self.n * self.n, self.C
+        if self.psi == "haar":
+            return np.stack([self._psi_adj1(z[c * N:(c + 1) * N]) for c in range(C)])
+        return np.stack([self._psi_adj1(np.concatenate([z[c * N:(c + 1) * N], z[(C + c) * N:(C + c + 1) * N]]))
+                         for c in range(C)])
+
+    def _coef_blocks(self, d):
+        """Per-contrast views of a coefficient vector in the single-contrast
+        order (the inverse of the block layout above)."""
+        N, C = self.n * self.n, self.C
+        if self.psi == "haar":
+            return [d[c * N:(c + 1) * N] for c in range(C)]
+        return [np.concatenate([d[c * N:(c + 1) * N], d[(C + c) * N:(C + c + 1) * N]]) for c in range(C)]
+
     @property
     def n_coef(self) -> int:
-        return self.n * self.n * (1 if self.psi == "haar" else 2)
+        return self.C * self.n * self.n * (1 if self.psi == "haar" else 2)
 
     @property
     def rho(self) -> float:
@@ -122,10 +152,12 @@ class Operators:
         return fourier.AHA(x, self.mask) + self.lam * self.psi_adj(d * self.psi_fwd(x))
 
     def _tv_bands(self, d):
-        """(diagonal a of P = rho I + lambda (D1^T W1 D1 + D2^T W2 D2), W1, W2)."""
-        n = self.n
-        d1 = d[: n * n].reshape(n, n)
-        d2 = d[n * n:].reshape(n, n)
+        """(diagonal a of P = rho I + lambda (D1^T W1 D1 + D2^T W2 D2), W1, W2);
+        (C, n, n) arrays for C contrasts."""
+        n, C = self.n, self.C
+        shp = (n, n) if C == 1 else (C, n, n)
+        d1 = d[: C * n * n].reshape(shp)
+        d2 = d[C * n * n:].reshape(shp)
         return self.rho + self.lam * self.psi_diag(d), d1, d2
 
     def _tv_offdiag(self, v, d1, d2):
@@ -136,13 +168,13 @@ class Operators:
         lam = self.lam
         if self.psi == "tvp":
             out = np.zeros_like(v)
-            out[1:, :] += d1[1:, :] * v[:-1, :]
-            out[:-1, :] += d1[1:, :] * v[1:, :]
-            out[:, 1:] += d2[:, 1:] * v[:, :-1]
-            out[:, :-1] += d2[:, 1:] * v[:, 1:]
+            out[..., 1:, :] += d1[..., 1:, :] * v[..., :-1, :]
+            out[..., :-1, :] += d1[..., 1:, :] * v[..., 1:, :]
+            out[..., :, 1:] += d2[..., :, 1:] * v[..., :, :-1]
+            out[..., :, :-1] += d2[..., :, 1:] * v[..., :, 1:]
             return -lam * out
-        return -lam * (d1 * np.roll(v, -1, axis=0) + np.roll(d1 * v, 1, axis=0)
-                       + d2 * np.roll(v, -1, axis=1) + np.roll(d2 * v, 1, axis=1))
+        return -lam * (d1 * np.roll(v, -1, axis=-2) + np.roll(d1 * v, 1, axis=-2)
+                       + d2 * np.roll(v, -1, axis=-1) + np.roll(d2 * v, 1, axis=-1))
 
     def precond(self, d, kind: str = "auto") -> Callable:
         """Return r -> P^{-1} r.
@@ -159,6 +191,10 @@ class Operators:
             return lambda r: r.copy()
         if kind == "pseudo":
             assert self.psi == "haar"
+            if self.C > 1:
+                invs = [1.0 / (rho + lam * dc.reshape(n, n)) for dc in self._coef_blocks(d)]
+                return lambda r: np.stack([haar.adj(invs[c] * haar.fwd(r[c], self.levels), self.levels)
+                                           for c in range(self.C)])
             inv = 1.0 / (rho + lam * d.reshape(n, n))
             return lambda r: haar.adj(inv * haar.fwd(r, self.levels), self.levels)
         if kind == "jacobi":
@@ -178,6 +214,8 @@ class Operators:
                 return np.where(red, y - self._tv_offdiag(zb, d1, d2) / a, zb)
             return apply
         if kind == "sgs_lex":
+            if self.C > 1:     # P is block diagonal over contrasts
+                return lambda r: np.stack([self._sgs_lex(r[c], a[c], d1[c], d2[c]) for c in range(self.C)])
             return lambda r: self._sgs_lex(r, a, d1, d2)
         raise ValueError(kind)
 
@@ -227,6 +265,9 @@ class Operators:
     def psi_diag(self, d):
         """diag(Psi^T diag(d) Psi) as an n x n array."""
         n = self.n
+        if self.C > 1:
+            one = dataclasses.replace(self, C=1)
+            return np.stack([one.psi_diag(dc) for dc in self._coef_blocks(d)])
         if self.psi in ("tv", "tvp"):
             d1 = d[: n * n].reshape(n, n)
             d2 = d[n * n:].reshape(n, n)

@@ -30,28 +30,37 @@ import numpy as np
 __all__ = [
     "rng", "phantom", "vd_mask", "radial_mask", "noise", "measure",
     "mallat_level_band", "groups_singletons", "groups_quadtree_pairs",
-    "groups_tv_iso", "groups_tv_aniso", "Problem", "make_problem", "cfg0",
-    "cfg1", "cfg2", "cfg3_set", "CFG3_SIZES",
+    "groups_tv_iso", "groups_tv_aniso", "groups_joint", "groups_jtv",
+    "Problem", "make_problem", "make_mc_problem", "cfg0", "cfg1", "cfg2",
+    "cfg3_set", "CFG3_SIZES",
 ]
 
-PHANTOM, MASK, NOISE, PARAMS = 0, 1, 2, 3
+PHANTOM, MASK, NOISE, PARAMS, CONTRAST = 0, 1, 2, 3, 4
 
 
-def rng(seed: int, stream: int) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream)]))
+def rng(seed: int, stream: int, sub: int = 0) -> np.random.Generator:
+    """Stream ``stream`` of ``seed``; ``sub`` > 0 selects one of several
+    independent sub-streams (the channels of a multi-contrast problem)."""
+    key = [int(seed), int(stream)] if sub == 0 else [int(seed), int(stream), int(sub)]
+    return np.random.default_rng(np.random.SeedSequence(key))
 
 
-def phantom(n: int, n_ellipses: int, seed: int, ramp: bool = False) -> np.ndarray:
+def phantom(n: int, n_ellipses: int, seed: int, ramp: bool = False, contrasts: int = 0) -> np.ndarray:
     """Sum of random filled ellipses on an n x n grid (float64, real).
 
     Pixel centres lie in (-1, 1)^2; ellipse centres U[-0.7, 0.7]^2, semi-axes
     U[0.05, 0.45], rotation U[0, pi), intensity U[0, 1].  With ``ramp`` a
     seeded linear ramp alpha*u + beta*v, alpha, beta ~ U[-0.25, 0.25], is added.
+    With ``contrasts`` = C > 0 the result is C images of the same anatomy
+    (the same ellipses) in C contrasts: ellipse e has intensity U[0, 1] drawn
+    per contrast from that contrast's own stream (shape (C, n, n)).
     """
     g = rng(seed, PHANTOM)
     c = -1.0 + (2.0 * np.arange(n) + 1.0) / n
     v, u = np.meshgrid(c, c, indexing="ij")      # v: row coordinate, u: column
-    img = np.zeros((n, n), dtype=np.float64)
+    C = max(contrasts, 1)
+    img = np.zeros((C, n, n), dtype=np.float64)
+    amps = [rng(seed, CONTRAST, ch + 1) for ch in range(C)] if contrasts else None
     for _ in range(n_ellipses):
         cx, cy = g.uniform(-0.7, 0.7, size=2)
         a, b = g.uniform(0.05, 0.45, size=2)
@@ -60,11 +69,13 @@ def phantom(n: int, n_ellipses: int, seed: int, ramp: bool = False) -> np.ndarra
         du, dv = u - cx, v - cy
         up = du * math.cos(th) + dv * math.sin(th)
         vp = -du * math.sin(th) + dv * math.cos(th)
-        img += amp * ((up / a) ** 2 + (vp / b) ** 2 <= 1.0)
+        inside = (up / a) ** 2 + (vp / b) ** 2 <= 1.0
+        for ch in range(C):
+            img[ch] += (amps[ch].uniform(0.0, 1.0) if contrasts else amp) * inside
     if ramp:
         al, be = g.uniform(-0.25, 0.25, size=2)
         img += al * u + be * v
-    return img
+    return img if contrasts else img[0]
 
 
 def _centred_k(n: int) -> Tuple[np.ndarray, np.ndarray]:
@@ -72,14 +83,15 @@ def _centred_k(n: int) -> Tuple[np.ndarray, np.ndarray]:
     return np.meshgrid(k, k, indexing="ij")
 
 
-def vd_mask(n: int, frac: float, seed: int) -> np.ndarray:
+def vd_mask(n: int, frac: float, seed: int, sub: int = 0) -> np.ndarray:
     """Variable-density random k-space mask (uint8, unshifted: DC at [0, 0]).
 
     Exactly M = round(frac * n^2) entries are drawn without replacement with
     probability proportional to (1 - |k| / kmax)^2, kmax = n / sqrt(2), on
     centred integer frequencies k in [-n/2, n/2)^2.  DC is always kept.
+    ``sub`` > 0 draws an independent mask (one per contrast).
     """
-    g = rng(seed, MASK)
+    g = rng(seed, MASK, sub)
     ky, kx = _centred_k(n)
     rad = np.sqrt(kx.astype(np.float64) ** 2 + ky.astype(np.float64) ** 2)
     w = (1.0 - rad / (n / math.sqrt(2.0))) ** 2
@@ -116,9 +128,9 @@ def radial_mask(n: int, coverage: float, seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.fft.ifftshift(m))
 
 
-def noise(n: int, sigma: float, seed: int) -> np.ndarray:
+def noise(n: int, sigma: float, seed: int, sub: int = 0) -> np.ndarray:
     """Complex Gaussian noise sigma * (g1 + i g2), g ~ N(0, 1) (complex128)."""
-    g = rng(seed, NOISE)
+    g = rng(seed, NOISE, sub)
     return sigma * (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n)))
 
 
@@ -199,12 +211,35 @@ def groups_tv_aniso(n: int):
     return groups_singletons(2 * n * n)
 
 
+def groups_joint(n: int, C: int):
+    """Joint sparsity across C contrasts (non-overlapping, FIRLS_MT): group j
+    holds coefficient j of every contrast, indices c * N + j."""
+    N = n * n
+    ptr = np.arange(0, C * N + 1, C, dtype=np.int64)
+    idx = (np.arange(C)[None, :] * N + np.arange(N)[:, None]).ravel()
+    return ptr.astype(np.int32), idx.astype(np.int32)
+
+
+def groups_jtv(n: int, C: int):
+    """Joint TV across C contrasts (FIRLS_JTV): group p holds row p of D1 and
+    of D2 of every contrast; rows are numbered D1 of contrast c at c*N + p,
+    D2 of contrast c at C*N + c*N + p."""
+    N = n * n
+    ptr = np.arange(0, 2 * C * N + 1, 2 * C, dtype=np.int64)
+    ch = np.arange(C)[None, :] * N + np.arange(N)[:, None]
+    idx = np.concatenate([ch, C * N + ch], axis=1).ravel()
+    return ptr.astype(np.int32), idx.astype(np.int32)
+
+
 # ---------------------------------------------------------------------------
 # Problem bundles for the workloads
 # ---------------------------------------------------------------------------
 
 @dataclasses.dataclass
 class Problem:
+    """One reconstruction problem.  With C > 1 contrasts, mask, b and truth
+    are (C, n, n) and the transform rows of contrast c come in blocks (Haar:
+    c*N + j; TV: D1 rows of all contrasts, then D2 rows)."""
     n: int
     psi: str                     # "haar", "tv" (periodic) or "tvp" (the paper's D)
     levels: int                  # Haar levels (0 for TV)
@@ -217,6 +252,7 @@ class Problem:
     group_idx: np.ndarray        # int32 [N']
     seed: int
     name: str = ""
+    C: int = 1
 
     @property
     def rho(self) -> float:
@@ -259,6 +295,46 @@ def make_problem(n: int, seed: int, *, psi: str, levels: int, groups: str,
     ptr, idx = _groups(groups, n, levels)
     return Problem(n=n, psi=psi, levels=levels, lam=lam, eps=eps, mask=m, b=b,
                    truth=img, group_ptr=ptr, group_idx=idx, seed=seed, name=name)
+
+
+def make_mc_problem(n: int, seed: int, *, C: int, psi: str, levels: int, groups: str,
+                    lam: float, sigma: float, n_ellipses: int = 8, frac: float = 0.25,
+                    mask_kind: str = "vd", eps: float = 1e-10, name: str = "") -> Problem:
+    """Multi-contrast problem (Section 5.6): C images of one anatomy, each
+    with its own variable-density mask (same sampling ratio) and noise.
+    groups: "joint" (Haar, FIRLS_MT), "jtv" (TV, FIRLS_JTV), or a
+    single-contrast map kind applied to every contrast separately."""
+    img = phantom(n, n_ellipses, seed, contrasts=C)
+    masks, bs = [], []
+    for ch in range(C):
+        if mask_kind == "vd":
+            m = vd_mask(n, frac, seed, sub=ch + 1)
+        elif mask_kind == "full":
+            m = np.ones((n, n), dtype=np.uint8)
+        else:
+            raise ValueError(mask_kind)
+        masks.append(m)
+        bs.append(measure(img[ch], m, noise(n, sigma, seed, sub=ch + 1)))
+    if groups == "joint":
+        ptr, idx = groups_joint(n, C)
+    elif groups == "jtv":
+        ptr, idx = groups_jtv(n, C)
+    else:
+        p1, i1 = _groups(groups, n, levels)
+        N, cnt = n * n, (1 if psi == "haar" else 2) * n * n
+        ptrs, idxs = [], []
+        for ch in range(C):
+            ptrs.append(p1[:-1] + ch * len(i1))
+            # a contrast's rows: Haar block ch; TV D1 block ch and D2 block ch
+            m_idx = i1.astype(np.int64) + ch * N if psi == "haar" else \
+                np.where(i1 < N, i1 + ch * N, i1 - N + C * N + ch * N)
+            idxs.append(m_idx)
+        ptr = np.concatenate(ptrs + [[C * len(i1)]]).astype(np.int32)
+        idx = np.concatenate(idxs).astype(np.int32)
+        assert cnt * C >= idx.max() + 1
+    return Problem(n=n, psi=psi, levels=levels, lam=lam, eps=eps, mask=np.stack(masks),
+                   b=np.stack(bs), truth=img, group_ptr=ptr, group_idx=idx, seed=seed,
+                   name=name, C=C)
 
 
 def cfg0(seed: int, n: int = 64) -> Problem:
