@@ -87,6 +87,18 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
  *               N + p for (D2 x)[p], N = n^2, p = r * n + c.  A coefficient may sit in several groups
  *               (overlap through G, Section 3.1, Fig. 1); a coefficient in
  *               no group is not penalised.
+ *   channels    C contrasts reconstructed jointly (Section 5.6: FIRLS_MT
+ *               with groups across contrasts, FIRLS_JTV); 0 or 1 for a single
+ *               image.  The C images are one problem: b, mask and x of a
+ *               slice are C contiguous n x n images, A and Psi act on each,
+ *               one PCG solves each reweighted system and rho is the sampled
+ *               fraction over all C masks.  Transform rows are numbered
+ *               contrast by contrast: Haar c * N + j; TV D1 rows of every
+ *               contrast (c * N + p), then D2 rows (C * N + c * N + p).  The
+ *               default map (n_groups = 0) groups row j (Haar) or the D1 and
+ *               D2 rows of pixel p (TV) across all contrasts.  Requires
+ *               C * (n / 16 + n / 16) <= 512 (and C * n^2 / 512 <= 512 for
+ *               TV); the learned start needs C = 1.
  * The arrays are copied at create; the caller keeps ownership. */
 typedef struct {
   int32_t n;
@@ -95,6 +107,7 @@ typedef struct {
   int32_t n_groups;
   const int32_t* group_ptr;
   const int32_t* group_idx;
+  int32_t channels;
 } firls_shape;
 
 /* Solver configuration.

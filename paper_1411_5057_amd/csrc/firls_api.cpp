@@ -40,6 +40,10 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 struct Shape {
   int n = 0, psi = 0, L = 0, n_groups = 0, n_coef = 0;
   int tvb = 0;   // TV boundary: 0 periodic, 1 the paper's non-periodic D
+  int C = 1;     // contrasts, stacked as C blocks of n rows
+  size_t pixels() const { return (size_t)C * n * n; }
+  int row_wgs() const { return C * n / band_rows(n); }                  // row-pass workgroups
+  int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64)); }  // column-pass workgroups
   int64_t n_members = 0;
   int32_t* d_gptr = nullptr;
   int32_t* d_gidx = nullptr;
@@ -142,10 +146,10 @@ struct firls_handle {
   int64_t prof_units[FIRLS_PROF_CLASSES] = {};
 
   size_t slice_bytes(const Shape& s) const {
-    const size_t vec = align256((size_t)s.n * s.n * elt);
+    const size_t vec = align256(s.pixels() * elt);
     const size_t nvec = s.psi == PSI_TV ? 6 : 4;
     return nvec * vec + 2 * align256((size_t)s.n_coef * relt) + align256((size_t)s.n_groups * relt) +
-           align256((size_t)s.n * s.n / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
+           align256(s.pixels() / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
   }
 };
 
@@ -218,7 +222,7 @@ int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
 // Carve slice i's workspace at byte offset ``off``.
 void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const firls_slice* sl) {
   char* base = static_cast<char*>(h->ws) + off;
-  const size_t vec = align256((size_t)s.n * s.n * h->elt);
+  const size_t vec = align256(s.pixels() * h->elt);
   std::memset(&D, 0, sizeof(D));
   D.r[0] = base;
   D.p = base + vec;
@@ -239,9 +243,10 @@ void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const 
   D.W = base + o;
   o += align256((size_t)s.n_groups * h->relt);
   D.mbits = reinterpret_cast<uint16_t*>(base + o);
-  o += align256((size_t)s.n * s.n / 8);
+  o += align256(s.pixels() / 8);
   D.parts = reinterpret_cast<double*>(base + o);
   D.n = s.n;
+  D.C = s.C;
   D.shape = 0;
   if (sl) {
     D.b = sl->b;
@@ -266,6 +271,7 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.shape.n_groups = s.n_groups;
   P.shape.n_coef = s.n_coef;
   P.n = s.n;
+  P.C = s.C;
   P.L = s.L;
   P.K = h->cfg.pcg_iters;
   P.Tmax = h->cfg.max_outer;
@@ -273,9 +279,10 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.eps = h->cfg.eps;
   P.tau = h->cfg.outer_tol;
   const int R = band_rows(s.n);
-  P.npq = s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0);
-  P.ndata = s.n / strip_cols(h->fp64);
-  P.nrz = s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC);
+  // partials per slot: one per workgroup, over the rows of every contrast
+  P.npq = s.C * (s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0));
+  P.ndata = s.C * (s.n / strip_cols(h->fp64));
+  P.nrz = s.C * (s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC));
   P.nreg = (s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG;
   (void)shape_id;
   return P;
@@ -316,8 +323,8 @@ hipEvent_t prof_event(firls_handle* h) {
 int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
-  if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.n / band_rows(s.n), c), st);
-  else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3((s.n * s.n + 4 * NT - 1) / (4 * NT), c), st);
+  if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.row_wgs(), c), st);
+  else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3(((int)s.pixels() + 4 * NT - 1) / (4 * NT), c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
   return FIRLS_OK;
@@ -330,18 +337,18 @@ int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipS
 int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
-  const dim3 rows(s.n / band_rows(s.n), c);
+  const dim3 rows(s.row_wgs(), c);
   if (s.psi == PSI_HAAR) {
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQ_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
     KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
-    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
     KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
   } else {
     int rc = launch_weights(h, s, P, c, st);
     if (rc) return rc;
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_PLAIN], P, rows, st);
-    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
     KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
   }
@@ -358,7 +365,7 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
   const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
   const bool fused = haar && h->cfg.precond == FIRLS_PC_PAPER;
-  const dim3 rows(s.n / band_rows(s.n), c);
+  const dim3 rows(s.row_wgs(), c);
   const int K = h->cfg.pcg_iters;
   for (int k = 0; k < K; ++k) {
     P.k = k;
@@ -370,7 +377,7 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     } else {
       KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_Z], P, rows, st);
     }
-    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.n / C, c), st);
+    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.col_wgs(h->fp64), c), st);
     KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
     if (haar && !fused) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar, P, rows, st);
     if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
@@ -466,8 +473,8 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     Params P = base_params(h, S, s, h->d_list + zlo[s]);
     h->ctx_group = s;
     h->ctx_count = c;
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.n / C, c), st);
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
   }
   auto enqueue_prep = [&]() -> int {
     for (int s = 0; s < nsh; ++s) {
@@ -623,40 +630,39 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   if (!size_supported(n)) return fail(FIRLS_E_UNSUPPORTED, "image side " + std::to_string(n) + " is not built");
   s.n = n;
   s.psi = in.psi;
+  s.C = in.channels <= 0 ? 1 : in.channels;
+  if (s.C > 64) return fail(FIRLS_E_UNSUPPORTED, "at most 64 contrasts");
   if (in.psi == FIRLS_PSI_HAAR) {
     const int maxL = 4;
     if (in.levels < 1) return fail(FIRLS_E_INVALID, "Haar levels must be >= 1");
     if (in.levels > maxL) return fail(FIRLS_E_UNSUPPORTED, "Haar levels above " + std::to_string(maxL) + " are not built for this precision");
     if (n % (1 << in.levels)) return fail(FIRLS_E_INVALID, "n must be a multiple of 2^levels");
     s.L = in.levels;
-    s.n_coef = n * n;
+    s.n_coef = s.C * n * n;
   } else if (in.psi == FIRLS_PSI_TV || in.psi == FIRLS_PSI_TV_PAPER) {
     if (n % TV_TC || n % TV_TR) return fail(FIRLS_E_UNSUPPORTED, "TV needs n to be a multiple of 32");
     s.psi = PSI_TV;
     s.tvb = in.psi == FIRLS_PSI_TV_PAPER ? 1 : 0;
     s.L = 0;
-    s.n_coef = 2 * n * n;
+    s.n_coef = 2 * s.C * n * n;
   } else {
     return fail(FIRLS_E_INVALID, "unknown psi");
   }
   // group map (caller order) -> internal order
   std::vector<int32_t> ptr, idx;
   if (in.n_groups == 0 && !in.group_ptr && !in.group_idx) {
-    const int N = n * n;
-    if (in.psi == FIRLS_PSI_HAAR) {
-      ptr.resize(N + 1);
-      idx.resize(N);
-      for (int i = 0; i <= N; ++i) ptr[i] = i;
-      for (int i = 0; i < N; ++i) idx[i] = i;
-    } else {
-      ptr.resize(N + 1);
-      idx.resize(2 * N);
-      for (int i = 0; i <= N; ++i) ptr[i] = 2 * i;
-      for (int i = 0; i < N; ++i) {
-        idx[2 * i] = i;
-        idx[2 * i + 1] = N + i;
+    // default: coefficient j of every contrast (Haar: standard / joint
+    // sparsity), or rows p of D1 and D2 of every contrast (isotropic / joint TV)
+    const int N = n * n, C = s.C;
+    const int per = (s.psi == PSI_HAAR ? 1 : 2) * C;
+    ptr.resize(N + 1);
+    idx.resize((size_t)N * per);
+    for (int i = 0; i <= N; ++i) ptr[i] = i * per;
+    for (int i = 0; i < N; ++i)
+      for (int c = 0; c < C; ++c) {
+        idx[(size_t)i * per + c] = c * N + i;
+        if (s.psi != PSI_HAAR) idx[(size_t)i * per + C + c] = (C + c) * N + i;
       }
-    }
   } else {
     if (in.n_groups <= 0 || !in.group_ptr || !in.group_idx) return fail(FIRLS_E_INVALID, "group map needs n_groups > 0 and both arrays");
     if (in.group_ptr[0] != 0) return fail(FIRLS_E_INVALID, "group_ptr[0] must be 0");
@@ -670,19 +676,28 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   s.n_groups = (int)ptr.size() - 1;
   s.n_members = (int64_t)idx.size();
   if ((s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many groups");
+  {
+    // every partial-sum slot holds one value per workgroup of a pass
+    const int R = band_rows(n), sc = strip_cols(h->fp64);
+    const int most = std::max({s.C * (n / R + n / sc), s.C * (n / TV_TR) * (n / TV_TC) * (s.psi == PSI_TV)});
+    if (most > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many contrasts for this image size");
+  }
   std::vector<int32_t> perm(s.n_coef);
+  const int N = n * n, C = s.C;
   if (s.psi == FIRLS_PSI_HAAR) {
-    for (int r = 0; r < n; ++r)
-      for (int c = 0; c < n; ++c) perm[r * n + c] = haar_internal_index(n, s.L, r, c);
+    // contrast c's coefficients: block c, in-place layout within it
+    for (int ch = 0; ch < C; ++ch)
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) perm[ch * N + r * n + c] = ch * N + haar_internal_index(n, s.L, r, c);
   } else if (s.tvb) {
     // the paper's coefficient of pixel (r, c) lives in forward slot (r-1, c)
-    // of D1 and (r, c-1) of D2 (indices mod n)
-    const int N = n * n;
-    for (int r = 0; r < n; ++r)
-      for (int c = 0; c < n; ++c) {
-        perm[r * n + c] = ((r + n - 1) % n) * n + c;
-        perm[N + r * n + c] = N + r * n + (c + n - 1) % n;
-      }
+    // of D1 and (r, c-1) of D2 (indices mod n), contrast by contrast
+    for (int ch = 0; ch < C; ++ch)
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+          perm[ch * N + r * n + c] = ch * N + ((r + n - 1) % n) * n + c;
+          perm[(C + ch) * N + r * n + c] = (C + ch) * N + r * n + (c + n - 1) % n;
+        }
   } else {
     for (int i = 0; i < s.n_coef; ++i) perm[i] = i;
   }
@@ -882,8 +897,8 @@ int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void
   Params P = base_params(h, s, shape_id, h->d_list);
   const int C = strip_cols(h->fp64);
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
-  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.n / C, 1), st);
-  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.n / band_rows(s.n), 1), st);
+  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.col_wgs(h->fp64), 1), st);
+  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.row_wgs(), 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
 }
@@ -933,9 +948,9 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
   if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
   PB.k = 0;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.n / band_rows(s.n), 1), st);
-  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.n / C, 1), st);
-  LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.n / band_rows(s.n), 1), st);
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.row_wgs(), 1), st);
+  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.col_wgs(h->fp64), 1), st);
+  LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.row_wgs(), 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
 }
@@ -967,7 +982,7 @@ int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
   if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
   PB.k = 0;
-  if (s.psi == PSI_HAAR) LAUNCH(s.sk->rowfwd[RF_PCG_HAAR], PB, dim3(s.n / band_rows(s.n), 1), st);
+  if (s.psi == PSI_HAAR) LAUNCH(s.sk->rowfwd[RF_PCG_HAAR], PB, dim3(s.row_wgs(), 1), st);
   else LAUNCH(prec_kernels(h->fp64)->update_tv[UP_INIT], PB, dim3(PB.nrz, 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
@@ -993,8 +1008,8 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const vo
   P.tau = 0.0;
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
   if ((rc = launch_weights(h, s, P, 1, st))) return rc;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.n / band_rows(s.n), 1), st);
-  LAUNCH(s.sk->col[COL_R0], P, dim3(s.n / C, 1), st);
+  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.row_wgs(), 1), st);
+  LAUNCH(s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), 1), st);
   LAUNCH(prec_kernels(h->fp64)->outer_check, P, dim3(1), st);
   HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1017,6 +1032,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     int rc = check_slice(h, slices[i]);
     if (rc) return rc;
     if (h->shapes[slices[i].shape_id].n != n) return fail(FIRLS_E_INVALID, "every slice must have the network's image size");
+    if (h->shapes[slices[i].shape_id].C != 1) return fail(FIRLS_E_UNSUPPORTED, "the learned start is built for single-contrast shapes");
   }
   hipStream_t st = (hipStream_t)stream;
   const int ns = n_slices;
@@ -1099,8 +1115,8 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     const Shape& S = h->shapes[s];
     Params P = base_params(h, S, s, h->d_list + lo[s]);
     LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
-    LAUNCH(S.sk->col[COL_AHB], P, dim3(S.n / strip_cols(false), c), st);
-    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+    LAUNCH(S.sk->col[COL_AHB], P, dim3(S.col_wgs(false), c), st);
+    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
   }
   // 2. network starts x0 = zf + f(zf), in network batches
   const int mb = cnn_max_batch(net);
@@ -1115,9 +1131,9 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     if (!c) continue;
     const Shape& S = h->shapes[s];
     Params P = base_params(h, S, s, h->d_list + lo[s]);
-    LAUNCH(S.sk->rowfwd[RF_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
-    LAUNCH(S.sk->col[COL_DC], P, dim3(S.n / strip_cols(false), c), st);
-    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.n / band_rows(S.n), c), st);
+    LAUNCH(S.sk->rowfwd[RF_PLAIN], P, dim3(S.row_wgs(), c), st);
+    LAUNCH(S.sk->col[COL_DC], P, dim3(S.col_wgs(false), c), st);
+    LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
   }
   HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
   if ((rc = upload(zf))) return rc;
@@ -1195,8 +1211,7 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
   size_t bytes = 0;
   std::vector<size_t> xb(n_slices);
   for (int i = 0; i < n_slices; ++i) {
-    const int n = h->shapes[slices[i].shape_id].n;
-    xb[i] = (size_t)n * n * h->elt;
+    xb[i] = h->shapes[slices[i].shape_id].pixels() * h->elt;
     bytes += xb[i];
   }
   void* snap = nullptr;

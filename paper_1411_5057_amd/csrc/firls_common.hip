@@ -12,13 +12,14 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
   const SliceDesc& D = P.desc[s];
-  const int n = D.n, total = n * n;
+  const int n = D.n, rows = D.C * n, total = rows * n;
   // count the samples and pack the mask: word [c16][row] holds columns
-  // 16 c16 .. 16 c16 + 15 of the row, bit c = column 16 c16 + c
+  // 16 c16 .. 16 c16 + 15 of the row, bit c = column 16 c16 + c; rows run
+  // over all contrasts
   double cnt = 0.0;
   const int words = total / 16;
   for (int w = threadIdx.x; w < words; w += NT) {
-    const int c16 = w / n, row = w - c16 * n;
+    const int c16 = w / rows, row = w - c16 * rows;
     const uint8_t* src = D.mask + (size_t)row * n + c16 * 16;
     unsigned int bits = 0;
 #pragma unroll

@@ -46,13 +46,15 @@ __device__ __forceinline__ const cplx<T>* lds_twiddles(cplx<T>* lds, const void*
 }
 
 // The spectrum scratch t between the three FFT passes is stored strip-major:
-// column strip j (COLS columns) is one contiguous block of n rows x COLS
-// values.  The column pass then streams whole blocks, and a row band still
-// meets it as runs of COLS values per row.
+// column strip j (COLS columns) of contrast c is one contiguous block of n
+// rows x COLS values.  The column pass then streams whole blocks, and a row
+// band still meets it as runs of COLS values per row.  ``row`` counts the
+// rows of all contrasts (row = c n + local row).
 template <typename T, int N>
 __device__ __forceinline__ size_t t_index(int row, int col) {
   constexpr int TS = Geo<T>::COLS;
-  return (size_t)(col / TS) * (N * TS) + (size_t)row * TS + (col % TS);
+  const int ch = row / N, lr = row - ch * N;
+  return (size_t)ch * N * N + (size_t)(col / TS) * (N * TS) + (size_t)lr * TS + (col % TS);
 }
 
 #define FIRLS_SLICE_PROLOGUE(idx)                 \
@@ -266,11 +268,14 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const int col0 = blockIdx.x * COLS;
+  // workgroup = (contrast ch, strip): strips of all contrasts in turn
+  constexpr int STRIPS = N / COLS;
+  const int ch = blockIdx.x / STRIPS, strip = blockIdx.x - ch * STRIPS;
+  const int col0 = strip * COLS;
   const C* tw = lds_twiddles<T, N, COLS>(lds, P.tw);
-  C* t = static_cast<C*>(D.t) + (size_t)blockIdx.x * N * COLS;   // this strip's block
+  C* t = static_cast<C*>(D.t) + (size_t)ch * N * N + (size_t)strip * N * COLS;   // this strip's block
   // sampled(c, row): bit of the packed mask word of this strip and row
-  const uint16_t* mw = D.mbits + (size_t)(col0 >> 4) * N;
+  const uint16_t* mw = D.mbits + (size_t)(col0 >> 4) * N * P.C + (size_t)ch * N;
   const int sh0 = col0 & 15;
   auto sampled = [&](int c, int row) { return (mw[row] >> (sh0 + c)) & 1u; };
   auto gsrc = [&](int c, int row) { return t[row * COLS + c]; };
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
       lds[Lay::at(c, row)] = u;
     });
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[N / band_rows(N) + blockIdx.x] = tot;
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[P.C * (N / band_rows(N)) + blockIdx.x] = tot;
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else if constexpr (MODE == COL_R0) {
     // k = (F x) at the sampled entries; keep m (b - k) / n for the inverse
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     const C* b = static_cast<const C*>(D.b);
     double acc = 0.0;
     fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
-      const size_t g = (size_t)row * N + col0 + c;
+      const size_t g = (size_t)(ch * N + row) * N + col0 + c;
       C u{(T)0, (T)0};
       if (sampled(c, row)) {
         u = b[g] - v * sn;
@@ -322,14 +327,14 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     // (k = m b + (1 - m) F x), then the column inverse with 1/n
     const C* b = static_cast<const C*>(D.b);
     fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
-      const size_t g = (size_t)row * N + col0 + c;
+      const size_t g = (size_t)(ch * N + row) * N + col0 + c;
       lds[Lay::at(c, row)] = (sampled(c, row) ? b[g] : v * sn) * sn;
     });
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else {
     const C* b = static_cast<const C*>(D.b);
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, [&](int c, int row) {
-      const size_t g = (size_t)row * N + col0 + c;
+      const size_t g = (size_t)(ch * N + row) * N + col0 + c;
       return sampled(c, row) ? b[g] * sn : C{(T)0, (T)0};
     }, gdst);
   }
@@ -404,11 +409,15 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       const double t2 = block_sum(acc2, red);
       if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
     } else {
-      const T* w1 = static_cast<const T*>(D.d);
-      const T* w2 = w1 + (size_t)N * N;
+      // this band's contrast: its image, its D1 weights and its D2 weights
+      const int ch = row0 / N, lrow0 = row0 - ch * N;
+      const size_t NN = (size_t)N * N;
+      const C* vch = vfull + ch * NN;
+      const T* w1 = static_cast<const T*>(D.d) + ch * NN;
+      const T* w2 = static_cast<const T*>(D.d) + (P.C + ch) * NN;
       fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
         const int i = l * N + q;
-        const C o = val + tv_normal<T>(vfull, w1, w2, N, row0 + l, q, P.tvb) * (lam * sgn);
+        const C o = val + tv_normal<T>(vch, w1, w2, N, lrow0 + l, q, P.tvb) * (lam * sgn);
         out[i] = o;
         if (SP) acc += cdot(v[i], o);
       });
@@ -513,12 +522,13 @@ __global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
   const int n = P.n;
   const C* x = static_cast<const C*>(D.x);
   T* sq = static_cast<T*>(D.sq);
-  const int total = n * n;
+  const int total = P.C * n * n;        // D1 rows of every contrast, then D2 rows
   for (int i = blockIdx.x * NT * 4 + threadIdx.x, e = 0; e < 4 && i < total; ++e, i += NT) {
-    const int r = i / n, c = i - r * n;
-    const int rp = r + 1 == n ? 0 : r + 1, cp = c + 1 == n ? 0 : c + 1;
+    const int r = i / n, c = i - r * n;          // r counts rows of all contrasts
+    const int lr = r % n;                         // row within the contrast
+    const int rp = lr + 1 == n ? r - lr : r + 1, cp = c + 1 == n ? 0 : c + 1;
     const C v = x[i], z{(T)0, (T)0};
-    sq[i] = (T)cabs2(x[rp * n + c] - (tv_cut(P.tvb, r, n) ? z : v));
+    sq[i] = (T)cabs2(x[rp * n + c] - (tv_cut(P.tvb, lr, n) ? z : v));
     sq[total + i] = (T)cabs2(x[r * n + cp] - (tv_cut(P.tvb, c, n) ? z : v));
   }
 }
@@ -595,18 +605,22 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   const int n = P.n;
   const int tiles_x = n / TV_TC;
   const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
-  const int r0 = ty * TV_TR, c0 = tx * TV_TC;
+  // tiles run over the rows of all contrasts; a tile lies in one contrast,
+  // whose image (and D1, D2 weights) the pointers below select
+  const int ch = (ty * TV_TR) / n;
+  const int r0 = ty * TV_TR - ch * n, c0 = tx * TV_TC;
+  const size_t cb = (size_t)ch * n * n;
   const int par = (MODE == UP_STEP) ? (P.k & 1) : 0;
-  const C* rin = static_cast<const C*>(D.r[par]);
-  const T* d1 = static_cast<const T*>(D.d);
-  const T* d2 = d1 + (size_t)n * n;
+  const C* rin = static_cast<const C*>(D.r[par]) + cb;
+  const T* d1 = static_cast<const T*>(D.d) + cb;
+  const T* d2 = static_cast<const T*>(D.d) + (size_t)P.C * n * n + cb;
   T al = (T)0;
   if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
     al = (T)(pq > 0.0 ? rz / pq : 0.0);
   }
-  const C* q = static_cast<const C*>(D.q);
+  const C* q = static_cast<const C*>(D.q) + cb;
   // coupling weights: slots that hold identity rows (tvb) couple nothing
   for (int i = threadIdx.x; i < WR * WC; i += NT) {
     const int lr = i / WC, lc = i - lr * WC;
@@ -656,10 +670,10 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
     }
   }
   __syncthreads();
-  C* z = static_cast<C*>(D.z);
-  C* rout = static_cast<C*>(D.r[par ^ 1]);
-  C* x = static_cast<C*>(D.x);
-  const C* p = static_cast<const C*>(D.p);
+  C* z = static_cast<C*>(D.z) + cb;
+  C* rout = static_cast<C*>(D.r[par ^ 1]) + cb;
+  C* x = static_cast<C*>(D.x) + cb;
+  const C* p = static_cast<const C*>(D.p) + cb;
   double acc = 0.0;
   for (int i = threadIdx.x; i < TV_TR * TV_TC; i += NT) {
     const int lr = H + i / TV_TC, lc = H + i % TV_TC;

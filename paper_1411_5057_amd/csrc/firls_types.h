@@ -64,6 +64,7 @@ struct SliceDesc {
   double lambda;
   int32_t n;
   int32_t shape;
+  int32_t C;         // contrasts stacked as C blocks of n rows
 };
 
 // Per-slice device state of the outer loop (FP64 scalars on the device).
@@ -112,6 +113,7 @@ struct Params {
   int32_t nreg;
   int32_t no_data;       // objective check: take the data term as 0
   int32_t tvb;           // TV boundary: 0 periodic, 1 the paper's non-periodic D
+  int32_t C;             // contrasts: the image is C blocks of n rows (one per contrast)
   double eps;
   double tau;
   void* out;             // op entry points: extra output

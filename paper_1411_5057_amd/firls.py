@@ -47,7 +47,7 @@ PROF_CLASSES = 15
 class firls_shape(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("psi", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_groups", ctypes.c_int32), ("group_ptr", ctypes.POINTER(ctypes.c_int32)),
-                ("group_idx", ctypes.POINTER(ctypes.c_int32))]
+                ("group_idx", ctypes.POINTER(ctypes.c_int32)), ("channels", ctypes.c_int32)]
 
 
 class firls_config(ctypes.Structure):
@@ -325,8 +325,8 @@ class Net:
 class Shape:
     """Python description of a firls_shape (group map as int32 numpy CSR)."""
 
-    def __init__(self, n: int, psi: str, levels: int = 0, group_ptr=None, group_idx=None):
-        self.n, self.psi, self.levels = int(n), psi, int(levels)
+    def __init__(self, n: int, psi: str, levels: int = 0, group_ptr=None, group_idx=None, channels: int = 1):
+        self.n, self.psi, self.levels, self.channels = int(n), psi, int(levels), int(channels)
         self.group_ptr = None if group_ptr is None else np.ascontiguousarray(group_ptr, dtype=np.int32)
         self.group_idx = None if group_idx is None else np.ascontiguousarray(group_idx, dtype=np.int32)
 
@@ -335,6 +335,7 @@ class Shape:
         s.n = self.n
         s.psi = {"haar": FIRLS_PSI_HAAR, "tv": FIRLS_PSI_TV, "tvp": FIRLS_PSI_TV_PAPER}[self.psi]
         s.levels = self.levels
+        s.channels = self.channels
         if self.group_ptr is not None:
             s.n_groups = len(self.group_ptr) - 1
             s.group_ptr = self.group_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
@@ -344,7 +345,8 @@ class Shape:
 
 class Solver:
     """Owns a firls_handle.  Tensors: b, x complex64 (FP32) / complex128
-    (FP64) n x n on the GPU, mask uint8 n x n."""
+    (FP64) n x n on the GPU, mask uint8 n x n (C x n x n, contiguous, for a
+    shape with C contrasts)."""
 
     def __init__(self, shapes: Sequence[Shape], *, prec: str = "fp32", max_slices: int = 1,
                  eps: float = 1e-10, max_outer: int = 50, pcg_iters: int = 20,
