@@ -8,7 +8,9 @@ seeded inputs drawn by ``synth``.
 
 Modules
 -------
-fourier  undersampled Fourier operator A = R F and its adjoint (Section 5.4)
+fourier  undersampled Fourier operator A = R F and its adjoint (Section 5.4);
+         a dense sensing matrix (random projections, Section 5.2) is the
+         other measurement operator, in firls.Operators
 haar     orthonormal 2D Haar transform Phi, Mallat layout (Section 3.1)
 tv       first-order differences D1, D2: periodic, and the paper's
          non-periodic matrices (Section 4.1)

@@ -57,14 +57,31 @@ class Operators:
     group_ptr: np.ndarray
     group_idx: np.ndarray
     C: int = 1          # contrasts (Section 5.6); x, mask, b are (C, n, n) when C > 1
+    Amat: Optional[np.ndarray] = None   # dense sensing matrix (M x N, real) instead of R F
 
     @classmethod
     def from_problem(cls, p, eps: Optional[float] = None, lam: Optional[float] = None):
+        Am = getattr(p, "Amat", None)
         return cls(n=p.n, psi=p.psi, levels=p.levels,
                    lam=p.lam if lam is None else lam,
                    eps=p.eps if eps is None else eps,
-                   mask=p.mask.astype(np.float64), b=p.mask * p.b,
-                   group_ptr=p.group_ptr, group_idx=p.group_idx, C=getattr(p, "C", 1))
+                   mask=None if Am is not None else p.mask.astype(np.float64),
+                   b=p.b.copy() if Am is not None else p.mask * p.b,
+                   group_ptr=p.group_ptr, group_idx=p.group_idx, C=getattr(p, "C", 1), Amat=Am)
+
+    # -- the measurement operator ---------------------------------------------
+    # CS-MRI: A = R F (Section 5.4).  Dense: A is an M x N matrix acting on the
+    # row-major image vector (the random projections of Section 5.2 and of the
+    # comparison with FOCUSS, Table 1).
+    def A(self, x):
+        if self.Amat is not None:
+            return self.Amat @ x.ravel()
+        return fourier.A(x, self.mask)
+
+    def AH(self, y):
+        if self.Amat is not None:
+            return (self.Amat.T @ y).reshape(self.n, self.n)
+        return fourier.AH(y, self.mask)
 
     # -- Psi and its adjoint ------------------------------------------------
     # With C contrasts Psi is block diagonal: Psi x = [Psi x_0; ...; Psi x_{C-1}]
@@ -116,10 +133,12 @@ class Operators:
 
     @property
     def rho(self) -> float:
+        if self.Amat is not None:        # mean of diag(A^T A)
+            return float(np.sum(self.Amat * self.Amat)) / self.Amat.shape[1]
         return fourier.rho(self.mask)
 
     def AHb(self):
-        return fourier.AH(self.b, self.mask)
+        return self.AH(self.b)
 
     # -- reweighting ----------------------------------------------------------
     def weights(self, x):
@@ -131,7 +150,7 @@ class Operators:
 
     # -- objective -----------------------------------------------------------
     def data_term(self, x) -> float:
-        r = fourier.A(x, self.mask) - self.b
+        r = self.A(x) - self.b
         return 0.5 * float(np.real(np.vdot(r, r)))
 
     def objective(self, x):
@@ -149,7 +168,7 @@ class Operators:
     # -- system and preconditioners -----------------------------------------
     def S(self, x, d):
         """S x = A^H A x + lambda Psi^T diag(d) Psi x (eq. 15 / eq. 39)."""
-        return fourier.AHA(x, self.mask) + self.lam * self.psi_adj(d * self.psi_fwd(x))
+        return self.AH(self.A(x)) + self.lam * self.psi_adj(d * self.psi_fwd(x))
 
     def _tv_bands(self, d):
         """(diagonal a of P = rho I + lambda (D1^T W1 D1 + D2^T W2 D2), W1, W2);

@@ -31,11 +31,11 @@ __all__ = [
     "rng", "phantom", "vd_mask", "radial_mask", "noise", "measure",
     "mallat_level_band", "groups_singletons", "groups_quadtree_pairs",
     "groups_tv_iso", "groups_tv_aniso", "groups_joint", "groups_jtv",
-    "Problem", "make_problem", "make_mc_problem", "cfg0", "cfg1", "cfg2",
+    "Problem", "make_problem", "make_mc_problem", "make_dense_problem", "cfg0", "cfg1", "cfg2",
     "cfg3_set", "CFG3_SIZES",
 ]
 
-PHANTOM, MASK, NOISE, PARAMS, CONTRAST = 0, 1, 2, 3, 4
+PHANTOM, MASK, NOISE, PARAMS, CONTRAST, SENSING = 0, 1, 2, 3, 4, 5
 
 
 def rng(seed: int, stream: int, sub: int = 0) -> np.random.Generator:
@@ -253,6 +253,7 @@ class Problem:
     seed: int
     name: str = ""
     C: int = 1
+    Amat: Optional[np.ndarray] = None   # dense sensing matrix (M x N); b then has M entries
 
     @property
     def rho(self) -> float:
@@ -335,6 +336,25 @@ def make_mc_problem(n: int, seed: int, *, C: int, psi: str, levels: int, groups:
     return Problem(n=n, psi=psi, levels=levels, lam=lam, eps=eps, mask=np.stack(masks),
                    b=np.stack(bs), truth=img, group_ptr=ptr, group_idx=idx, seed=seed,
                    name=name, C=C)
+
+
+def make_dense_problem(n: int, seed: int, *, m_frac: float, psi: str, levels: int, groups: str,
+                       lam: float, sigma: float, n_ellipses: int = 8, eps: float = 1e-10,
+                       name: str = "") -> Problem:
+    """Random-projection compressive sensing of an n x n image (Section 5.2:
+    a 64 x 64 patch measured by a random projection): A is M x N with
+    M = round(m_frac N) and i.i.d. N(0, 1/M) entries, b = A x + complex
+    noise (sigma per component)."""
+    img = phantom(n, n_ellipses, seed)
+    N = n * n
+    M = int(round(m_frac * N))
+    Am = rng(seed, SENSING).standard_normal((M, N)) / math.sqrt(M)
+    g = rng(seed, NOISE)
+    b = Am @ img.ravel() + sigma * (g.standard_normal(M) + 1j * g.standard_normal(M))
+    ptr, idx = _groups(groups, n, levels)
+    return Problem(n=n, psi=psi, levels=levels, lam=lam, eps=eps, mask=np.ones((n, n), dtype=np.uint8),
+                   b=b.astype(np.complex128), truth=img, group_ptr=ptr, group_idx=idx, seed=seed,
+                   name=name, Amat=Am)
 
 
 def cfg0(seed: int, n: int = 64) -> Problem:
