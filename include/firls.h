@@ -64,6 +64,12 @@ enum {
  * wrap), so (D1 x)[r,c] = x[r,c] - x[r-1,c] with (D1 x)[0,c] = x[0,c], and
  * likewise along rows. */
 enum { FIRLS_PSI_HAAR = 0, FIRLS_PSI_TV = 1, FIRLS_PSI_TV_PAPER = 2 };
+
+/* Measurement operator A.  FOURIER: A = R F, the masked unitary 2D DFT of
+ * CS-MRI (Section 5.4).  DENSE: a real M x N matrix on the row-major image
+ * vector (the random projections of Section 5.2); products with it run on
+ * MFMA. */
+enum { FIRLS_OP_FOURIER = 0, FIRLS_OP_DENSE = 1 };
 enum { FIRLS_FP64 = 0, FIRLS_FP32 = 1 };
 
 /* Preconditioner of the inner PCG.  PAPER is the paper's choice: eq. (17)
@@ -99,6 +105,13 @@ enum { FIRLS_PC_PAPER = 0, FIRLS_PC_JACOBI = 1, FIRLS_PC_NONE = 2 };
  *               D2 rows of pixel p (TV) across all contrasts.  Requires
  *               C * (n / 16 + n / 16) <= 512 (and C * n^2 / 512 <= 512 for
  *               TV); the learned start needs C = 1.
+ *   op          FIRLS_OP_FOURIER (default, 0) or FIRLS_OP_DENSE.
+ *   m, A        DENSE only: m measurements (1 <= m <= 32768) and the host
+ *               matrix A, double[m * n^2], row-major (row i is measurement
+ *               i on the row-major image).  rho = ||A||_F^2 / n^2, the mean
+ *               of diag(A^T A) (eq. 17).  A slice's b then holds m complex
+ *               values and its mask is not read (may be NULL).  Needs
+ *               channels = 1 and n^2 % 64 == 0; not for the learned start.
  * The arrays are copied at create; the caller keeps ownership. */
 typedef struct {
   int32_t n;
@@ -108,6 +121,9 @@ typedef struct {
   const int32_t* group_ptr;
   const int32_t* group_idx;
   int32_t channels;
+  int32_t op;
+  int32_t m;
+  const double* A;
 } firls_shape;
 
 /* Solver configuration.
@@ -295,12 +311,12 @@ enum {
   FIRLS_PROF_GROUP_W = 3,   /* group weights W and penalty partials */
   FIRLS_PROF_GROUP_D = 4,   /* d = diag(G^T W G) */
   FIRLS_PROF_R0_ROWFWD = 5, /* residual A^H b - S x: row FFT (Haar: and |Psi x|^2) */
-  FIRLS_PROF_R0_COL = 6,    /*   column pass with the data term */
+  FIRLS_PROF_R0_COL = 6,    /*   column pass with the data term (dense A: b - A x, A^T y) */
   FIRLS_PROF_R0_ROWINV = 7, /*   row inverse FFT + regulariser (Haar: and <r0, z0>) */
   FIRLS_PROF_R0_UPDATE = 8, /*   TV: z0 and <r0, z0> */
   FIRLS_PROF_CHECK = 9,     /* objective and stop rule */
   FIRLS_PROF_ROWFWD = 10,   /* PCG: first p and row FFT (Haar), or p = z + beta p and row FFT (TV) */
-  FIRLS_PROF_COL = 11,      /* PCG: column FFT, mask, column inverse FFT */
+  FIRLS_PROF_COL = 11,      /* PCG: column FFT, mask, column inverse FFT (dense A: A p, A^T y) */
   FIRLS_PROF_ROWINV = 12,   /* PCG: row inverse FFT + regulariser, <p, q> (Haar: and <q, P^{-1} q>) */
   FIRLS_PROF_UPDATE = 13,   /* PCG: x, r update, z and <r, z> (Haar: and the next p and row FFT) */
   FIRLS_PROF_LAST_X = 14,   /* PCG, Haar: x += alpha p after the last iteration */

@@ -74,13 +74,15 @@ class Operators:
     # row-major image vector (the random projections of Section 5.2 and of the
     # comparison with FOCUSS, Table 1).
     def A(self, x):
-        if self.Amat is not None:
-            return self.Amat @ x.ravel()
+        if self.Amat is not None:     # real A: act on real and imaginary parts
+            v = np.asarray(x).ravel()
+            return self.Amat @ v.real + 1j * (self.Amat @ v.imag)
         return fourier.A(x, self.mask)
 
     def AH(self, y):
         if self.Amat is not None:
-            return (self.Amat.T @ y).reshape(self.n, self.n)
+            y = np.asarray(y)
+            return (self.Amat.T @ y.real + 1j * (self.Amat.T @ y.imag)).reshape(self.n, self.n)
         return fourier.AH(y, self.mask)
 
     # -- Psi and its adjoint ------------------------------------------------

@@ -41,6 +41,10 @@ struct Shape {
   int n = 0, psi = 0, L = 0, n_groups = 0, n_coef = 0;
   int tvb = 0;   // TV boundary: 0 periodic, 1 the paper's non-periodic D
   int C = 1;     // contrasts, stacked as C blocks of n rows
+  bool dense = false;   // dense sensing matrix instead of the masked FFT
+  int M = 0, Mp = 0;    // its rows, and rows padded to the GEMM tile
+  void* d_A = nullptr;  // Mp x n^2 in the working precision
+  double rho_A = 0.0;   // mean diag(A^T A)
   size_t pixels() const { return (size_t)C * n * n; }
   int row_wgs() const { return C * n / band_rows(n); }                  // row-pass workgroups
   int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64)); }  // column-pass workgroups
@@ -149,7 +153,8 @@ struct firls_handle {
     const size_t vec = align256(s.pixels() * elt);
     const size_t nvec = s.psi == PSI_TV ? 6 : 4;
     return nvec * vec + 2 * align256((size_t)s.n_coef * relt) + align256((size_t)s.n_groups * relt) +
-           align256(s.pixels() / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
+           align256(s.pixels() / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double)) +
+           (s.dense ? align256((size_t)s.Mp * elt) : 0);
   }
 };
 
@@ -245,6 +250,9 @@ void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const 
   D.mbits = reinterpret_cast<uint16_t*>(base + o);
   o += align256(s.pixels() / 8);
   D.parts = reinterpret_cast<double*>(base + o);
+  o += align256((size_t)SLOT_COUNT * PMAX * sizeof(double));
+  if (s.dense) D.y = base + o;
+  D.rho_fixed = s.dense ? s.rho_A : 0.0;
   D.n = s.n;
   D.C = s.C;
   D.shape = 0;
@@ -267,6 +275,10 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.shape.tptr = s.d_tptr;
   P.shape.tidx = s.d_tidx;
   P.shape.perm = s.d_perm;
+  P.shape.A = s.d_A;
+  P.shape.M = s.M;
+  P.shape.Mp = s.Mp;
+  P.nofft = s.dense ? 1 : 0;
   P.tvb = s.tvb;
   P.shape.n_groups = s.n_groups;
   P.shape.n_coef = s.n_coef;
@@ -283,6 +295,12 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.npq = s.C * (s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0));
   P.ndata = s.C * (s.n / strip_cols(h->fp64));
   P.nrz = s.C * (s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC));
+  if (s.dense) {
+    // the A x / A p products write one partial per row tile
+    P.ndata = s.Mp / GEMM_BM;
+    P.npq = s.n / R + (s.psi == PSI_HAAR ? s.Mp / GEMM_BM : 0);
+    P.pq_gemm = s.psi == PSI_HAAR ? 1 : 0;
+  }
   P.nreg = (s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG;
   (void)shape_id;
   return P;
@@ -334,11 +352,41 @@ int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipS
 // outer iteration's preparation).  Haar: the row FFT of x also writes
 // |Phi x|^2, and the row-inverse pass of r0 = A^H b - S x also sums
 // <r0, z0>; TV: |D x|^2, weights, the residual passes and z0 = M^{-1} r0.
+// A x - b and A^T (b - A x) for a dense sensing matrix (the data term and
+// the A^H part of r0), in place of the row FFT and column pass.
+int launch_dense_residual(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
+  const GemmKernels* gk = gemm_kernels(h->fp64);
+  P.count = c;
+  const int ct = (c + GEMM_BS - 1) / GEMM_BS;
+  KLAUNCH(h, FIRLS_PROF_R0_COL, gk->g[G_AX_R0], P, dim3(s.Mp / GEMM_BM, ct), st);
+  KLAUNCH(h, FIRLS_PROF_R0_COL, gk->g[G_ATY], P, dim3(s.n * s.n / GEMM_BM, ct), st);
+  return FIRLS_OK;
+}
+
+// q's A^T A p part for a dense sensing matrix: y = A p, t = A^T y.
+int launch_dense_normal(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
+  const GemmKernels* gk = gemm_kernels(h->fp64);
+  P.count = c;
+  const int ct = (c + GEMM_BS - 1) / GEMM_BS;
+  KLAUNCH(h, FIRLS_PROF_COL, gk->g[G_AP], P, dim3(s.Mp / GEMM_BM, ct), st);
+  KLAUNCH(h, FIRLS_PROF_COL, gk->g[G_ATY], P, dim3(s.n * s.n / GEMM_BM, ct), st);
+  return FIRLS_OK;
+}
+
 int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
   const dim3 rows(s.row_wgs(), c);
-  if (s.psi == PSI_HAAR) {
+  if (s.dense) {
+    int rc = launch_weights(h, s, P, c, st);
+    if (rc || (rc = launch_dense_residual(h, s, P, c, st))) return rc;
+    if (s.psi == PSI_HAAR) {
+      KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
+    } else {
+      KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
+      KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
+    }
+  } else if (s.psi == PSI_HAAR) {
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQ_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
     KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
@@ -377,7 +425,12 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     } else {
       KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_Z], P, rows, st);
     }
-    KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.col_wgs(h->fp64), c), st);
+    if (s.dense) {
+      int rc = launch_dense_normal(h, s, P, c, st);
+      if (rc) return rc;
+    } else {
+      KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.col_wgs(h->fp64), c), st);
+    }
     KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
     if (haar && !fused) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar, P, rows, st);
     if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
@@ -411,7 +464,8 @@ int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg) 
 int check_slice(const firls_handle* h, const firls_slice& sl) {
   if (sl.shape_id < 0 || sl.shape_id >= (int)h->shapes.size()) return fail(FIRLS_E_INVALID, "shape_id out of range");
   if (!(sl.lambda > 0.0) || !std::isfinite(sl.lambda)) return fail(FIRLS_E_INVALID, "lambda must be positive and finite");
-  if (!sl.b || !sl.mask || !sl.x) return fail(FIRLS_E_INVALID, "b, mask and x must be device pointers");
+  if (!sl.b || !sl.x) return fail(FIRLS_E_INVALID, "b and x must be device pointers");
+  if (!sl.mask && !h->shapes[sl.shape_id].dense) return fail(FIRLS_E_INVALID, "mask must be a device pointer");
   return FIRLS_OK;
 }
 
@@ -473,8 +527,14 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     Params P = base_params(h, S, s, h->d_list + zlo[s]);
     h->ctx_group = s;
     h->ctx_count = c;
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
-    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
+    if (S.dense) {
+      P.count = c;
+      KLAUNCH(h, FIRLS_PROF_AHB, gemm_kernels(h->fp64)->g[G_ATB], P,
+              dim3(S.n * S.n / GEMM_BM, (c + GEMM_BS - 1) / GEMM_BS), st);
+    } else {
+      KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
+      KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
+    }
   }
   auto enqueue_prep = [&]() -> int {
     for (int s = 0; s < nsh; ++s) {
@@ -632,6 +692,35 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   s.psi = in.psi;
   s.C = in.channels <= 0 ? 1 : in.channels;
   if (s.C > 64) return fail(FIRLS_E_UNSUPPORTED, "at most 64 contrasts");
+  if (in.op == FIRLS_OP_DENSE) {
+    // dense sensing matrix: copied, converted to the working precision and
+    // padded with zero rows to the GEMM row tile
+    if (s.C != 1) return fail(FIRLS_E_UNSUPPORTED, "a dense sensing matrix needs channels = 1");
+    if (in.m < 1 || !in.A) return fail(FIRLS_E_INVALID, "a dense sensing matrix needs m >= 1 and A");
+    const size_t N = (size_t)n * n;
+    s.dense = true;
+    s.M = in.m;
+    s.Mp = (in.m + GEMM_BM - 1) / GEMM_BM * GEMM_BM;
+    if (s.Mp / GEMM_BM > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many measurements (m > 32768)");
+    if (N % GEMM_BM) return fail(FIRLS_E_UNSUPPORTED, "n^2 must be a multiple of 64");
+    double fro = 0.0;
+    for (size_t i = 0; i < (size_t)s.M * N; ++i) fro += in.A[i] * in.A[i];
+    s.rho_A = fro / (double)N;
+    if (!(s.rho_A > 0.0) || !std::isfinite(s.rho_A)) return fail(FIRLS_E_INVALID, "A must be finite and nonzero");
+    const size_t bytes = (size_t)s.Mp * N * h->relt;   // real entries
+    HIPCHK(hipMalloc(&s.d_A, bytes));
+    if (h->fp64) {
+      std::vector<double> a((size_t)s.Mp * N, 0.0);
+      std::copy(in.A, in.A + (size_t)s.M * N, a.begin());
+      HIPCHK(hipMemcpy(s.d_A, a.data(), bytes, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> a((size_t)s.Mp * N, 0.f);
+      for (size_t i = 0; i < (size_t)s.M * N; ++i) a[i] = (float)in.A[i];
+      HIPCHK(hipMemcpy(s.d_A, a.data(), bytes, hipMemcpyHostToDevice));
+    }
+  } else if (in.op != FIRLS_OP_FOURIER) {
+    return fail(FIRLS_E_INVALID, "unknown measurement operator");
+  }
   if (in.psi == FIRLS_PSI_HAAR) {
     const int maxL = 4;
     if (in.levels < 1) return fail(FIRLS_E_INVALID, "Haar levels must be >= 1");
@@ -747,6 +836,7 @@ void destroy_shapes(firls_handle* h) {
   for (auto& s : h->shapes) {
     for (int32_t* p : {s.d_gptr, s.d_gidx, s.d_tptr, s.d_tidx, s.d_perm})
       if (p) (void)hipFree(p);
+    if (s.d_A) (void)hipFree(s.d_A);
   }
   h->shapes.clear();
   for (auto& e : h->tw) (void)hipFree(e.second);
@@ -884,21 +974,26 @@ int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out)
 }
 
 int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask, void* x) {
-  if (!h || !b || !mask || !x) return fail(FIRLS_E_INVALID, "null argument");
+  if (!h || !b || !x) return fail(FIRLS_E_INVALID, "null argument");
   hipStream_t st = (hipStream_t)stream;
   int rc = op_begin(h, st, shape_id, 1);
   if (rc) return rc;
+  const Shape& s = h->shapes[shape_id];
+  if (!mask && !s.dense) return fail(FIRLS_E_INVALID, "null argument");
   h->h_desc[0].b = b;
   h->h_desc[0].mask = mask;
   h->h_desc[0].x = x;
   h->h_desc[0].lambda = 1.0;
   if ((rc = op_upload(h, st, 1))) return rc;
-  const Shape& s = h->shapes[shape_id];
   Params P = base_params(h, s, shape_id, h->d_list);
-  const int C = strip_cols(h->fp64);
+  P.count = 1;
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
-  LAUNCH(s.sk->col[COL_AHB], P, dim3(s.col_wgs(h->fp64), 1), st);
-  LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.row_wgs(), 1), st);
+  if (s.dense) {
+    LAUNCH(gemm_kernels(h->fp64)->g[G_ATB], P, dim3(s.n * s.n / GEMM_BM, 1), st);
+  } else {
+    LAUNCH(s.sk->col[COL_AHB], P, dim3(s.col_wgs(h->fp64), 1), st);
+    LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.row_wgs(), 1), st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
 }
@@ -924,11 +1019,12 @@ int firls_op_weights(firls_handle* h, void* stream, int32_t shape_id, const void
 
 int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8_t* mask, double lambda,
                     const void* x_w, const void* p, void* q) {
-  if (!h || !mask || !x_w || !p || !q) return fail(FIRLS_E_INVALID, "null argument");
+  if (!h || !x_w || !p || !q) return fail(FIRLS_E_INVALID, "null argument");
   if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
   hipStream_t st = (hipStream_t)stream;
   int rc = op_begin(h, st, shape_id, 2);
   if (rc) return rc;
+  if (!mask && !h->shapes[shape_id].dense) return fail(FIRLS_E_INVALID, "null argument");
   SliceDesc& A = h->h_desc[0];
   SliceDesc& B = h->h_desc[1];
   A.x = const_cast<void*>(x_w);
@@ -948,8 +1044,14 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
   if ((rc = launch_weights(h, s, PA, 1, st))) return rc;
   PB.k = 0;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.row_wgs(), 1), st);
-  LAUNCH(s.sk->col[COL_SP], PB, dim3(s.col_wgs(h->fp64), 1), st);
+  PB.count = 1;
+  if (s.dense) {
+    LAUNCH(gemm_kernels(h->fp64)->g[G_AP], PB, dim3(s.Mp / GEMM_BM, 1), st);
+    LAUNCH(gemm_kernels(h->fp64)->g[G_ATY], PB, dim3(s.n * s.n / GEMM_BM, 1), st);
+  } else {
+    LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.row_wgs(), 1), st);
+    LAUNCH(s.sk->col[COL_SP], PB, dim3(s.col_wgs(h->fp64), 1), st);
+  }
   LAUNCH(s.sk->rowinv[s.psi == PSI_HAAR ? RI_SP_HAAR : RI_SP_TV], PB, dim3(s.row_wgs(), 1), st);
   HIPCHK(hipStreamSynchronize(st));
   return FIRLS_OK;
@@ -957,11 +1059,12 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
 
 int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint8_t* mask, double lambda,
                      const void* x_w, const void* r, void* z) {
-  if (!h || !mask || !x_w || !r || !z) return fail(FIRLS_E_INVALID, "null argument");
+  if (!h || !x_w || !r || !z) return fail(FIRLS_E_INVALID, "null argument");
   if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
   hipStream_t st = (hipStream_t)stream;
   int rc = op_begin(h, st, shape_id, 2);
   if (rc) return rc;
+  if (!mask && !h->shapes[shape_id].dense) return fail(FIRLS_E_INVALID, "null argument");
   SliceDesc& A = h->h_desc[0];
   SliceDesc& B = h->h_desc[1];
   A.x = const_cast<void*>(x_w);
@@ -990,11 +1093,12 @@ int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint
 
 int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const void* b, const uint8_t* mask,
                        double lambda, const void* x, double* out3) {
-  if (!h || !b || !mask || !x || !out3) return fail(FIRLS_E_INVALID, "null argument");
+  if (!h || !b || !x || !out3) return fail(FIRLS_E_INVALID, "null argument");
   if (!(lambda > 0.0)) return fail(FIRLS_E_INVALID, "lambda must be positive");
   hipStream_t st = (hipStream_t)stream;
   int rc = op_begin(h, st, shape_id, 1);
   if (rc) return rc;
+  if (!mask && !h->shapes[shape_id].dense) return fail(FIRLS_E_INVALID, "null argument");
   SliceDesc& A = h->h_desc[0];
   A.x = const_cast<void*>(x);
   A.b = b;
@@ -1008,8 +1112,13 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const vo
   P.tau = 0.0;
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
   if ((rc = launch_weights(h, s, P, 1, st))) return rc;
-  LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.row_wgs(), 1), st);
-  LAUNCH(s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), 1), st);
+  if (s.dense) {
+    P.count = 1;
+    LAUNCH(gemm_kernels(h->fp64)->g[G_AX_R0], P, dim3(s.Mp / GEMM_BM, 1), st);
+  } else {
+    LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.row_wgs(), 1), st);
+    LAUNCH(s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), 1), st);
+  }
   LAUNCH(prec_kernels(h->fp64)->outer_check, P, dim3(1), st);
   HIPCHK(hipMemcpyAsync(h->h_state, h->d_state, sizeof(SliceState), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1032,7 +1141,8 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     int rc = check_slice(h, slices[i]);
     if (rc) return rc;
     if (h->shapes[slices[i].shape_id].n != n) return fail(FIRLS_E_INVALID, "every slice must have the network's image size");
-    if (h->shapes[slices[i].shape_id].C != 1) return fail(FIRLS_E_UNSUPPORTED, "the learned start is built for single-contrast shapes");
+    if (h->shapes[slices[i].shape_id].C != 1 || h->shapes[slices[i].shape_id].dense)
+      return fail(FIRLS_E_UNSUPPORTED, "the learned start is built for single-contrast masked-FFT shapes");
   }
   hipStream_t st = (hipStream_t)stream;
   const int ns = n_slices;

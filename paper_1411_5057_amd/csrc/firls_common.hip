@@ -12,6 +12,17 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
   const SliceDesc& D = P.desc[s];
+  if (D.rho_fixed > 0.0) {
+    // dense sensing matrix: rho = mean diag(A^T A), set by the host; no mask
+    if (threadIdx.x == 0) {
+      SliceState& S = P.state[s];
+      S.rho = D.rho_fixed;
+      S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
+      S.active = 1;
+      S.outer = S.pcg = S.status = S.converged = S.evals = 0;
+    }
+    return;
+  }
   const int n = D.n, rows = D.C * n, total = rows * n;
   // count the samples and pack the mask: word [c16][row] holds columns
   // 16 c16 .. 16 c16 + 15 of the row, bit c = column 16 c16 + c; rows run

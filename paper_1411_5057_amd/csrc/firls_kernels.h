@@ -170,8 +170,10 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
 #pragma unroll
       for (int s = 0; s < 16; ++s) sq[(row + s) * N + col] = (T)cabs2(v[s]);
     }
-    __syncthreads();
-    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
+    if (!P.nofft) {   // a dense sensing matrix takes p itself, not its row FFT
+      __syncthreads();
+      fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
+    }
   } else {
     double beta = 0.0;
     if (MODE != RF_STEP_HAAR && P.k > 0) {
@@ -253,8 +255,10 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         lds[Lay::at(i / N, i % N)] = pn;
       }
     }
-    __syncthreads();
-    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
+    if (!P.nofft) {   // a dense sensing matrix takes p itself, not its row FFT
+      __syncthreads();
+      fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
+    }
   }
 }
 
@@ -370,8 +374,16 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
     const T sgn = SP ? (T)1 : (T)-1;
     double acc = 0.0;
     if constexpr (HAAR) {
-      // A^H A part into LDS, then lambda Phi^T (d * Phi v) in registers
-      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, LdsIO<T, N>{lds});
+      // A^H A part into LDS (row inverse FFT, or with a dense sensing matrix
+      // the product A^T A v in t, row-major), then lambda Phi^T (d * Phi v)
+      // in registers
+      if (P.nofft) {
+        const C* av = static_cast<const C*>(D.t) + off;
+        for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = av[i];
+        __syncthreads();
+      } else {
+        fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, LdsIO<T, N>{lds});
+      }
       const T* d = static_cast<const T*>(D.d) + off;
       const T rho = (T)P.state[s_].rho;
       double acc2 = 0.0;
@@ -415,12 +427,18 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       const C* vch = vfull + ch * NN;
       const T* w1 = static_cast<const T*>(D.d) + ch * NN;
       const T* w2 = static_cast<const T*>(D.d) + (P.C + ch) * NN;
-      fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C val) {
+      auto emit = [&](int l, int q, C val) {
         const int i = l * N + q;
         const C o = val + tv_normal<T>(vch, w1, w2, N, lrow0 + l, q, P.tvb) * (lam * sgn);
         out[i] = o;
         if (SP) acc += cdot(v[i], o);
-      });
+      };
+      if (P.nofft) {
+        const C* av = static_cast<const C*>(D.t) + off;
+        for (int i = threadIdx.x; i < ROWS * N; i += NT) emit(i / N, i % N, av[i]);
+      } else {
+        fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, emit);
+      }
     }
     if constexpr (SP) {
       const double tot = block_sum(acc, red);

@@ -28,6 +28,12 @@ struct PrecKernels {
   Launcher outer_check;
 };
 
+// Dense sensing matrix products (GemmMode order).
+struct GemmKernels {
+  Launcher g[4];
+};
+const GemmKernels* gemm_kernels(bool fp64);
+
 // nullptr if the size is not built for that precision.
 const SizeKernels* size_kernels(bool fp64, int n);
 const PrecKernels* prec_kernels(bool fp64);

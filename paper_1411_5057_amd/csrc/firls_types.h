@@ -41,6 +41,14 @@ enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAA
 enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3, COL_SP_PQ = 4 };
 enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
 enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
+// Dense sensing matrix products (batched over the slices of a launch):
+//   G_ATB   x = A^T b            (zero-filled start)
+//   G_AX_R0 y = b - A x          (+ partials of 1/2 ||A x - b||^2)
+//   G_AP    y = A p              (+ partials of ||A p||^2 = <p, A^T A p>)
+//   G_ATY   t = A^T y
+enum GemmMode : int { G_ATB = 0, G_AX_R0 = 1, G_AP = 2, G_ATY = 3 };
+constexpr int GEMM_BM = 64;      // rows per workgroup tile
+constexpr int GEMM_BS = 32;      // slices (64 real columns) per workgroup tile
 
 // Per-slice device pointers.  Caller-owned: b, mask, x.  The rest is
 // library workspace.  Complex vectors are n x n interleaved (re, im) of the
@@ -60,7 +68,9 @@ struct SliceDesc {
   void* sq;
   void* W;
   uint16_t* mbits;   // mask bits: word [c16][row] = mask[row][16 c16 .. 16 c16 + 15]
+  void* y;           // dense sensing matrix only: A v (Mp complex)
   double* parts;
+  double rho_fixed;  // > 0: rho of a dense sensing matrix (mean diag A^T A); else from the mask
   double lambda;
   int32_t n;
   int32_t shape;
@@ -92,6 +102,9 @@ struct ShapeDev {
   const int32_t* perm;   // user coefficient index -> internal index
   int32_t n_groups;
   int32_t n_coef;
+  const void* A;         // dense sensing matrix, Mp x n^2 row-major (rows >= M zero), or null
+  int32_t M;             // measurements of the dense matrix
+  int32_t Mp;            // M rounded up to the GEMM row tile
 };
 
 // Kernel parameters (passed by value).
@@ -114,6 +127,9 @@ struct Params {
   int32_t no_data;       // objective check: take the data term as 0
   int32_t tvb;           // TV boundary: 0 periodic, 1 the paper's non-periodic D
   int32_t C;             // contrasts: the image is C blocks of n rows (one per contrast)
+  int32_t nofft;         // dense sensing matrix: row passes skip / replace the FFT
+  int32_t count;         // slices in ``list`` (GEMM column tiles)
+  int32_t pq_gemm;       // the A p product adds ||A p||^2 partials to <p, S p> (Haar)
   double eps;
   double tau;
   void* out;             // op entry points: extra output

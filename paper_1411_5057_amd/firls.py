@@ -26,6 +26,8 @@ FIRLS_W_MAXITER = 1
 FIRLS_PSI_HAAR = 0
 FIRLS_PSI_TV = 1
 FIRLS_PSI_TV_PAPER = 2
+FIRLS_OP_FOURIER = 0
+FIRLS_OP_DENSE = 1
 FIRLS_FP64 = 0
 FIRLS_FP32 = 1
 FIRLS_PC_PAPER = 0
@@ -47,7 +49,8 @@ PROF_CLASSES = 15
 class firls_shape(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("psi", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("n_groups", ctypes.c_int32), ("group_ptr", ctypes.POINTER(ctypes.c_int32)),
-                ("group_idx", ctypes.POINTER(ctypes.c_int32)), ("channels", ctypes.c_int32)]
+                ("group_idx", ctypes.POINTER(ctypes.c_int32)), ("channels", ctypes.c_int32),
+                ("op", ctypes.c_int32), ("m", ctypes.c_int32), ("A", ctypes.POINTER(ctypes.c_double))]
 
 
 class firls_config(ctypes.Structure):
@@ -142,7 +145,7 @@ def _check(code: int, where: str) -> int:
 
 
 def _ptr(t) -> int:
-    return int(t.data_ptr())
+    return 0 if t is None else int(t.data_ptr())
 
 
 def _stream(stream) -> Optional[int]:
@@ -325,8 +328,12 @@ class Net:
 class Shape:
     """Python description of a firls_shape (group map as int32 numpy CSR)."""
 
-    def __init__(self, n: int, psi: str, levels: int = 0, group_ptr=None, group_idx=None, channels: int = 1):
+    def __init__(self, n: int, psi: str, levels: int = 0, group_ptr=None, group_idx=None, channels: int = 1,
+                 A=None):
+        """A: optional dense sensing matrix (M x n^2, float64) in place of the
+        masked FFT."""
         self.n, self.psi, self.levels, self.channels = int(n), psi, int(levels), int(channels)
+        self.A = None if A is None else np.ascontiguousarray(A, dtype=np.float64)
         self.group_ptr = None if group_ptr is None else np.ascontiguousarray(group_ptr, dtype=np.int32)
         self.group_idx = None if group_idx is None else np.ascontiguousarray(group_idx, dtype=np.int32)
 
@@ -336,6 +343,10 @@ class Shape:
         s.psi = {"haar": FIRLS_PSI_HAAR, "tv": FIRLS_PSI_TV, "tvp": FIRLS_PSI_TV_PAPER}[self.psi]
         s.levels = self.levels
         s.channels = self.channels
+        if self.A is not None:
+            s.op = FIRLS_OP_DENSE
+            s.m = self.A.shape[0]
+            s.A = self.A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         if self.group_ptr is not None:
             s.n_groups = len(self.group_ptr) - 1
             s.group_ptr = self.group_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))

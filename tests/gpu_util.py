@@ -29,7 +29,8 @@ def to_np(t):
 
 def shape_of(prob):
     from paper_1411_5057_amd import firls as F
-    return F.Shape(prob.n, prob.psi, prob.levels, prob.group_ptr, prob.group_idx, getattr(prob, "C", 1))
+    return F.Shape(prob.n, prob.psi, prob.levels, prob.group_ptr, prob.group_idx, getattr(prob, "C", 1),
+                   getattr(prob, "Amat", None))
 
 
 def rel(a, b):
