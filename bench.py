@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--precond", choices=("paper", "jacobi", "none"), default="paper",
                     help="inner preconditioner: the paper's (eq. 17), Jacobi (diag S) or none (plain CG)")
     ap.add_argument("--no-tune", action="store_true", help="skip the sub-batch autotuner")
+    ap.add_argument("--workload", choices=("mri", "dense"), default="mri",
+                    help="mri: the 256^2 CS-MRI benchmark (default); dense: 64^2 images measured by one "
+                         "shared dense random projection (30%% of N rows), the MFMA path")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     return ap.parse_args()
@@ -178,6 +181,62 @@ def gap_stats(fe, fstar):
             "frac_le_1e-4": float(np.mean(g <= 1e-4))}
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def run_dense(a, torch, F):
+    """Random-projection compressive sensing (Section 5.2): B images of
+    64 x 64, one dense Gaussian sensing matrix with M = 0.3 N rows shared by
+    all of them, tree-group Haar.  The products with A are batched MFMA
+    GEMMs; their roofline is MFMA-bound."""
+    import synth
+    n, B, K = 64, a.slices, a.pcg
+    base = synth.make_dense_problem(n, 0, m_frac=0.3, psi="haar", levels=4, groups="quadtree", lam=0.03, sigma=0.01)
+    Am = base.Amat
+    M = Am.shape[0]
+    rs = np.random.default_rng(1)
+    bs = []
+    for s in range(B):
+        img = synth.phantom(n, 8, 5000 + s)
+        bs.append(Am @ img.ravel() + 0.01 * (rs.standard_normal(M) + 1j * rs.standard_normal(M)))
+    b = torch.from_numpy(np.stack(bs)).to(torch.complex64).cuda().contiguous()
+    shape = F.Shape(n, "haar", 4, base.group_ptr, base.group_idx, A=Am)
+    solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
+                      outer_tol=a.tau, eps=1e-10)
+    x = torch.zeros((B, n, n), dtype=torch.complex64, device="cuda")
+    items = [dict(b=b[i], mask=None, x=x[i], lam=base.lam) for i in range(B)]
+    run = lambda: (solver.solve_batched(items), None)
+    dt, (reps, _), _ = timed(solver, run, a.steps, a.warmup, False, torch)
+    _, _, prof = timed(solver, run, 1, 0, True, torch)
+    v = prof["col"]                       # the two GEMMs of every PCG iteration
+    flops = 2.0 * 2.0 * M * n * n * v["slice_launches"] / v["launches"]   # 2 real columns per slice
+    avg_s = v["ms"] / v["launches"] / 1e3
+    ach = flops / avg_s / 1e12
+    outer = np.array([r["outer_iters"] for r in reps])
+    out = {"metric": "solves/s, 64^2 random-projection CS (M = 0.3 N), tree-group Haar", "value": B * a.steps / dt,
+           "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded ellipse phantoms, one Gaussian N(0, 1/M) sensing matrix)",
+           "config": {"workload": f"{B} slices of 64x64, dense A {M}x{n * n}, 4-level Haar, quadtree groups, "
+                                  f"lambda 0.03, {K} PCG per outer, tau {a.tau:g} (max {a.max_outer})",
+                      "n": n, "m": M, "slices": B, "pcg_iters": K},
+           "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
+           "converged_frac": float(np.mean([r["converged"] for r in reps])),
+           "roofline": {"bound": "mfma", "kernel": "gemm (A p and A^T y)", "achieved": ach,
+                        "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_MFMA_PEAK_TFLOPS,
+                        "traffic": None, "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops},
+           "kernel_ms": {c: round(u["ms"], 3) for c, u in prof.items() if u["launches"]}}
+    if not a.no_gap:
+        ref = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.ref_outer, pcg_iters=K, outer_tol=0.0,
+                       eps=1e-10)
+        xr = torch.zeros_like(x)
+        rr = ref.solve_batched([dict(b=b[i], mask=None, x=xr[i], lam=base.lam) for i in range(B)])
+        out["gap_to_optimum"] = gap_stats(np.array([r["F_eps"] for r in reps]), np.array([r["F_eps"] for r in rr]))
+        ref.close()
+    print(json.dumps(out))
+    solver.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -190,6 +249,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload == "dense":
+        return run_dense(a, torch, F)
     B, n, K = a.slices, a.n, a.pcg
     if a.copy_calib_mb:
         src = torch.ones(a.copy_calib_mb << 18, dtype=torch.float32, device=dev)

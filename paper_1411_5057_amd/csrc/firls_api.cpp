@@ -134,6 +134,8 @@ struct firls_handle {
   // per-slice output pointers and a copy of the slice states
   void* ws_learn = nullptr;
   size_t ws_learn_cap = 0;
+  void* gscr = nullptr;     // split-K partial tiles of the dense-matrix GEMMs
+  size_t gscr_cap = 0;
 
   // Opt-in per-launch timing (firls_profile): one event pair per launch.
   struct ProfRec {
@@ -172,6 +174,9 @@ void free_batch(firls_handle* h) {
   if (h->ws_learn) (void)hipFree(h->ws_learn);
   h->ws_learn = nullptr;
   h->ws_learn_cap = 0;
+  if (h->gscr) (void)hipFree(h->gscr);
+  h->gscr = nullptr;
+  h->gscr_cap = 0;
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_desc) (void)hipFree(h->d_desc);
   if (h->d_state) (void)hipFree(h->d_state);
@@ -352,25 +357,64 @@ int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipS
 // outer iteration's preparation).  Haar: the row FFT of x also writes
 // |Phi x|^2, and the row-inverse pass of r0 = A^H b - S x also sums
 // <r0, z0>; TV: |D x|^2, weights, the residual passes and z0 = M^{-1} r0.
+// Split-K factor of a dense-matrix GEMM: enough workgroups to fill the
+// device (about 1024), a power of two dividing the K steps, at most 8.
+struct GemmPlan {
+  int rows, K, ct, split;
+  size_t scratch;   // bytes of partial tiles (0 without a split)
+};
+GemmPlan gemm_plan(const firls_handle* h, const Shape& s, int mode, int c) {
+  GemmPlan g{};
+  const bool trans = mode == G_ATB || mode == G_ATY;
+  g.rows = trans ? s.n * s.n : s.Mp;
+  g.K = trans ? s.Mp : s.n * s.n;
+  g.ct = (c + GEMM_BS - 1) / GEMM_BS;
+  const int tiles = g.rows / GEMM_BM * g.ct, steps = g.K / GEMM_BK;
+  g.split = 1;
+  while (g.split < 8 && tiles * g.split < 1024 && steps % (2 * g.split) == 0) g.split *= 2;
+  g.scratch = g.split > 1 ? (size_t)g.split * g.rows * g.ct * 2 * GEMM_BS * h->relt : 0;
+  return g;
+}
+
+// Scratch for every GEMM of c slices of a dense shape (before any capture).
+int ensure_gemm_scratch(firls_handle* h, hipStream_t st, const Shape& s, int c) {
+  size_t need = 0;
+  for (int m = 0; m < 4; ++m) need = std::max(need, gemm_plan(h, s, m, c).scratch);
+  if (need <= h->gscr_cap) return FIRLS_OK;
+  drop_graphs(h);
+  HIPCHK(hipStreamSynchronize(st));
+  if (h->gscr) HIPCHK(hipFree(h->gscr));
+  h->gscr = nullptr;
+  h->gscr_cap = 0;
+  if (hipMalloc(&h->gscr, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FIRLS_E_NOMEM, "GEMM scratch allocation failed");
+  }
+  h->gscr_cap = need;
+  return FIRLS_OK;
+}
+
+int launch_gemm(firls_handle* h, const Shape& s, Params P, int mode, int c, hipStream_t st, int cls) {
+  const GemmPlan g = gemm_plan(h, s, mode, c);
+  if (g.scratch > h->gscr_cap) return fail(FIRLS_E_INVALID, "GEMM scratch not prepared");
+  P.count = c;
+  P.gsplit = g.split;
+  P.gscr = h->gscr;
+  KLAUNCH(h, cls, gemm_kernels(h->fp64)->g[mode], P, dim3(g.rows / GEMM_BM, g.ct), st);
+  return FIRLS_OK;
+}
+
 // A x - b and A^T (b - A x) for a dense sensing matrix (the data term and
 // the A^H part of r0), in place of the row FFT and column pass.
 int launch_dense_residual(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
-  const GemmKernels* gk = gemm_kernels(h->fp64);
-  P.count = c;
-  const int ct = (c + GEMM_BS - 1) / GEMM_BS;
-  KLAUNCH(h, FIRLS_PROF_R0_COL, gk->g[G_AX_R0], P, dim3(s.Mp / GEMM_BM, ct), st);
-  KLAUNCH(h, FIRLS_PROF_R0_COL, gk->g[G_ATY], P, dim3(s.n * s.n / GEMM_BM, ct), st);
-  return FIRLS_OK;
+  int rc = launch_gemm(h, s, P, G_AX_R0, c, st, FIRLS_PROF_R0_COL);
+  return rc ? rc : launch_gemm(h, s, P, G_ATY, c, st, FIRLS_PROF_R0_COL);
 }
 
 // q's A^T A p part for a dense sensing matrix: y = A p, t = A^T y.
 int launch_dense_normal(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
-  const GemmKernels* gk = gemm_kernels(h->fp64);
-  P.count = c;
-  const int ct = (c + GEMM_BS - 1) / GEMM_BS;
-  KLAUNCH(h, FIRLS_PROF_COL, gk->g[G_AP], P, dim3(s.Mp / GEMM_BM, ct), st);
-  KLAUNCH(h, FIRLS_PROF_COL, gk->g[G_ATY], P, dim3(s.n * s.n / GEMM_BM, ct), st);
-  return FIRLS_OK;
+  int rc = launch_gemm(h, s, P, G_AP, c, st, FIRLS_PROF_COL);
+  return rc ? rc : launch_gemm(h, s, P, G_ATY, c, st, FIRLS_PROF_COL);
 }
 
 int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
@@ -505,6 +549,10 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     zlo[s] = pos;
     for (int i : zf_by_shape[s]) h->h_list[pos++] = i;
   }
+  for (int s = 0; s < nsh; ++s)
+    if (h->shapes[s].dense && !by_shape[s].empty() &&
+        (rc = ensure_gemm_scratch(h, st, h->shapes[s], (int)by_shape[s].size())))
+      return rc;
   HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
 
@@ -528,9 +576,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     h->ctx_group = s;
     h->ctx_count = c;
     if (S.dense) {
-      P.count = c;
-      KLAUNCH(h, FIRLS_PROF_AHB, gemm_kernels(h->fp64)->g[G_ATB], P,
-              dim3(S.n * S.n / GEMM_BM, (c + GEMM_BS - 1) / GEMM_BS), st);
+      if ((rc = launch_gemm(h, S, P, G_ATB, c, st, FIRLS_PROF_AHB))) return rc;
     } else {
       KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
       KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
@@ -989,7 +1035,7 @@ int firls_op_adjoint(firls_handle* h, void* stream, int32_t shape_id, const void
   P.count = 1;
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
   if (s.dense) {
-    LAUNCH(gemm_kernels(h->fp64)->g[G_ATB], P, dim3(s.n * s.n / GEMM_BM, 1), st);
+    if ((rc = ensure_gemm_scratch(h, st, s, 1)) || (rc = launch_gemm(h, s, P, G_ATB, 1, st, FIRLS_PROF_AHB))) return rc;
   } else {
     LAUNCH(s.sk->col[COL_AHB], P, dim3(s.col_wgs(h->fp64), 1), st);
     LAUNCH(s.sk->rowinv[RI_PLAIN], P, dim3(s.row_wgs(), 1), st);
@@ -1046,8 +1092,7 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
   PB.k = 0;
   PB.count = 1;
   if (s.dense) {
-    LAUNCH(gemm_kernels(h->fp64)->g[G_AP], PB, dim3(s.Mp / GEMM_BM, 1), st);
-    LAUNCH(gemm_kernels(h->fp64)->g[G_ATY], PB, dim3(s.n * s.n / GEMM_BM, 1), st);
+    if ((rc = ensure_gemm_scratch(h, st, s, 1)) || (rc = launch_dense_normal(h, s, PB, 1, st))) return rc;
   } else {
     LAUNCH(s.sk->rowfwd[RF_PLAIN], PB, dim3(s.row_wgs(), 1), st);
     LAUNCH(s.sk->col[COL_SP], PB, dim3(s.col_wgs(h->fp64), 1), st);
@@ -1113,8 +1158,7 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const vo
   LAUNCH(prec_kernels(h->fp64)->slice_init, P, dim3(1), st);
   if ((rc = launch_weights(h, s, P, 1, st))) return rc;
   if (s.dense) {
-    P.count = 1;
-    LAUNCH(gemm_kernels(h->fp64)->g[G_AX_R0], P, dim3(s.Mp / GEMM_BM, 1), st);
+    if ((rc = ensure_gemm_scratch(h, st, s, 1)) || (rc = launch_gemm(h, s, P, G_AX_R0, 1, st, FIRLS_PROF_R0_COL))) return rc;
   } else {
     LAUNCH(s.sk->rowfwd[RF_PLAIN], P, dim3(s.row_wgs(), 1), st);
     LAUNCH(s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), 1), st);

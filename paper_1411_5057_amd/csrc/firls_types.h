@@ -49,6 +49,7 @@ enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
 enum GemmMode : int { G_ATB = 0, G_AX_R0 = 1, G_AP = 2, G_ATY = 3 };
 constexpr int GEMM_BM = 64;      // rows per workgroup tile
 constexpr int GEMM_BS = 32;      // slices (64 real columns) per workgroup tile
+constexpr int GEMM_BK = 32;      // depth of one LDS stage of the GEMM
 
 // Per-slice device pointers.  Caller-owned: b, mask, x.  The rest is
 // library workspace.  Complex vectors are n x n interleaved (re, im) of the
@@ -130,6 +131,8 @@ struct Params {
   int32_t nofft;         // dense sensing matrix: row passes skip / replace the FFT
   int32_t count;         // slices in ``list`` (GEMM column tiles)
   int32_t pq_gemm;       // the A p product adds ||A p||^2 partials to <p, S p> (Haar)
+  int32_t gsplit;        // GEMM split-K factor (1: no split)
+  void* gscr;            // GEMM split-K partial tiles
   double eps;
   double tau;
   void* out;             // op entry points: extra output

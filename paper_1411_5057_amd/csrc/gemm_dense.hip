@@ -6,9 +6,10 @@
 // imaginary parts of slice j are columns 2j and 2j+1 of the right operand,
 // read in place from the slice's own vector (x, p, y or b).  Tiles of
 // GEMM_BM rows x 64 columns run on MFMA (FP32: v_mfma_f32_16x16x4f32, FP64:
-// v_mfma_f64_16x16x4f64), four waves of 32 x 32, with 16-deep slices of both
-// operands staged in LDS.  Per-slice partial sums (data term, ||A p||^2)
-// are reduced in a fixed order: one partial per row tile.
+// v_mfma_f64_16x16x4f64), four waves of 32 x 32, with 32-deep slices of both
+// operands staged in LDS and the next slices fetched meanwhile.  Per-slice
+// partial sums (data term, ||A p||^2) are reduced in a fixed order: one
+// partial per row tile.
 #include "firls_inst.h"
 
 namespace firls {
@@ -35,117 +36,56 @@ template <> struct Mfma<double> {
   __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-constexpr int BK = 16;          // depth of one LDS stage
+constexpr int BK = GEMM_BK;     // depth of one LDS stage
 constexpr int BN = 2 * GEMM_BS; // real columns per tile
 constexpr int PAD = 4;
 
 }  // namespace
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_gemm(Params P) {
-  using C = cplx<T>;
+// Epilogue of one 64 x 64 output tile: thread (wave, lane) owns the MFMA
+// output positions (mi, ni, r); ``val(mi, ni, r)`` gives the finished sum.
+// Scatters to the slices' vectors and, for G_AX_R0 / G_AP, writes one
+// per-slice partial of the squares (fixed reduction order).
+template <typename T, int MODE, class Val>
+__device__ __forceinline__ void gemm_epilogue(const Params& P, int row0, int j0, Val val,
+                                              double (&colpart)[2][BN]) {
   using M = Mfma<T>;
-  constexpr bool TRANS = (MODE == G_ATB || MODE == G_ATY);   // A^T v
-  __shared__ T As[BK][GEMM_BM + PAD];       // As[k][row]
-  __shared__ T Bs[BK][BN + PAD];            // Bs[k][col]
-  __shared__ double sq[GEMM_BM][BN + 1];    // squares for the per-slice partials
-  __shared__ double colsum[BN];
-  const int N = P.n * P.n;
-  const int Mp = P.shape.Mp, Mv = P.shape.M;
-  const int K = TRANS ? Mp : N;
-  const int row0 = blockIdx.x * GEMM_BM;
-  const int j0 = blockIdx.y * GEMM_BS;
-  const T* A = static_cast<const T*>(P.shape.A);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  // the slice whose operand column pair this thread loads (fixed for the loop)
-  const int jl = tid >> 3, part = tid & 7;
-  const int jg = j0 + jl;
-  const T* bsrc = nullptr;
-  if (jg < P.count) {
-    const SliceDesc& D = P.desc[P.list[jg]];
-    const void* v = MODE == G_ATB ? D.b : (MODE == G_AX_R0 ? D.x : (MODE == G_AP ? D.p : D.y));
-    bsrc = static_cast<const T*>(v);
-  }
-  const int kmax_b = MODE == G_ATB ? Mv : K;   // b has only M rows
-
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  typename M::V acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename M::V{0, 0, 0, 0};
-
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // A tile: GEMM_BM rows x BK, stored As[k][row]
-    if (!TRANS) {
-      const int r = tid >> 2, k4 = (tid & 3) * 4;
-      const T* src = A + (size_t)(row0 + r) * N + k0 + k4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[k4 + e][r] = src[e];
-    } else {
-      const int k = tid >> 4, r4 = (tid & 15) * 4;
-      const T* src = A + (size_t)(k0 + k) * N + row0 + r4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) As[k][r4 + e] = src[e];
-    }
-    // B tile: BK rows x BN columns; slice jl supplies 2 BK consecutive reals
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = part * 4 + e, kk = idx >> 1, c = idx & 1;
-      const int k = k0 + kk;
-      Bs[kk][2 * jl + c] = (bsrc && k < kmax_b) ? bsrc[2 * (size_t)k + c] : (T)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int k = kk + (lane >> 4);
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
-        const T a = As[k][wr + 16 * mi + (lane & 15)];
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = M::mac(a, Bs[k][wc + 16 * ni + (lane & 15)], acc[mi][ni]);
-      }
-    }
-    __syncthreads();
-  }
-
-  // epilogue: scatter to the slices' vectors, squares into LDS
   constexpr bool PARTIAL = (MODE == G_AX_R0 || MODE == G_AP);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int Mv = P.shape.M;
+  double csq[2] = {0.0, 0.0};
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int ni = 0; ni < 2; ++ni) {
+    const int col = wc + 16 * ni + (lane & 15);
+    const int j = j0 + (col >> 1), c = col & 1;
+    const bool live = j < P.count && P.state[P.list[j]].active;
+    T* dst = nullptr;
+    const T* bv = nullptr;
+    if (live) {
+      const SliceDesc& D = P.desc[P.list[j]];
+      dst = static_cast<T*>(MODE == G_ATB ? D.x : (MODE == G_ATY ? D.t : D.y));
+      bv = static_cast<const T*>(D.b);
+    }
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wr + 16 * mi + M::row(lane, r);
-        const int col = wc + 16 * ni + (lane & 15);
-        const int gr = row0 + row, j = j0 + (col >> 1), c = col & 1;
-        T v = acc[mi][ni][r];
-        double s2 = 0.0;
-        if (j < P.count) {
-          const int sid = P.list[j];
-          const SliceDesc& D = P.desc[sid];
-          if (P.state[sid].active) {
-            if (MODE == G_ATB) {
-              static_cast<T*>(D.x)[2 * (size_t)gr + c] = v;
-            } else if (MODE == G_ATY) {
-              static_cast<T*>(D.t)[2 * (size_t)gr + c] = v;
-            } else {
-              if (MODE == G_AX_R0) v = gr < Mv ? static_cast<const T*>(D.b)[2 * (size_t)gr + c] - v : (T)0;
-              static_cast<T*>(D.y)[2 * (size_t)gr + c] = v;
-              s2 = (double)v * (double)v;
-            }
-          }
-        }
-        if (PARTIAL) sq[row][col] = s2;
+        const int gr = row0 + wr + 16 * mi + M::row(lane, r);
+        T v = val(mi, ni, r);
+        if (MODE == G_AX_R0) v = (live && gr < Mv) ? bv[2 * (size_t)gr + c] - v : (T)0;
+        if (live) dst[2 * (size_t)gr + c] = v;
+        if (PARTIAL) csq[ni] += live ? (double)v * (double)v : 0.0;
       }
+  }
   if constexpr (PARTIAL) {
-    __syncthreads();
-    if (tid < BN) {
-      double t = 0.0;
-      for (int r = 0; r < GEMM_BM; ++r) t += sq[r][tid];
-      colsum[tid] = t;
+    // lanes l, l+16, l+32, l+48 hold the same column: fold them, then the
+    // two waves sharing a column block, always in the same order
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      csq[ni] += __shfl_xor(csq[ni], 16, 64);
+      csq[ni] += __shfl_xor(csq[ni], 32, 64);
+      if (lane < 16) colpart[wave >> 1][wc + 16 * ni + lane] = csq[ni];
     }
     __syncthreads();
     if (tid < GEMM_BS) {
@@ -154,7 +94,8 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
         const int sid = P.list[j];
         const SliceDesc& D = P.desc[sid];
         if (P.state[sid].active) {
-          const double tot = colsum[2 * tid] + colsum[2 * tid + 1];
+          const double tot = (colpart[0][2 * tid] + colpart[1][2 * tid]) + (colpart[0][2 * tid + 1] + colpart[1][2 * tid + 1]);
+          const int Mp = P.shape.Mp;
           if (MODE == G_AX_R0) slot_wptr(D, SLOT_DATA)[blockIdx.x] = 0.5 * tot;
           else if (P.pq_gemm) slot_wptr(D, SLOT_PQ0 + P.k)[P.npq - Mp / GEMM_BM + blockIdx.x] = tot;
         }
@@ -163,9 +104,141 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
   }
 }
 
+// Scratch index of output (row, real column) of split s: [s][row][col] with
+// gridDim.y * BN columns.
+__device__ __forceinline__ size_t gemm_scr(int s, int row, int rows, int col) {
+  return ((size_t)s * rows + row) * (size_t)(gridDim.y * BN) + col;
+}
+
+// One 64 x 64 output tile per workgroup (split s = blockIdx.z of P.gsplit
+// takes K range [s K / S, (s+1) K / S)); the next BK-deep slices of both
+// operands are fetched into registers while the current ones (in LDS) feed
+// the MFMAs, so global latency overlaps the arithmetic.  With a split the
+// raw sums go to scratch and k_gemm_reduce finishes them.
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_gemm(Params P) {
+  using M = Mfma<T>;
+  constexpr bool TRANS = (MODE == G_ATB || MODE == G_ATY);   // A^T v
+  __shared__ T As[BK][GEMM_BM + PAD];       // As[k][row]
+  __shared__ T Bs[BK][BN + PAD];            // Bs[k][col]
+  __shared__ double colpart[2][BN];
+  const int N = P.n * P.n;
+  const int Mp = P.shape.Mp, Mv = P.shape.M;
+  const int K = TRANS ? Mp : N;
+  const int KS = K / P.gsplit;              // a multiple of BK (host-checked)
+  const int kbeg = blockIdx.z * KS, kend = kbeg + KS;
+  const int row0 = blockIdx.x * GEMM_BM;
+  const int j0 = blockIdx.y * GEMM_BS;
+  const T* A = static_cast<const T*>(P.shape.A);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // operand fetch roles (fixed for the whole K loop)
+  //   A, not transposed: row ar, k offsets ak .. ak+7 (contiguous)
+  //   A, transposed:     k row ak, rows ar .. ar+7 (contiguous)
+  //   B: slice jl, reals 8 part .. 8 part + 7 of its 2 BK-long run
+  const int ar = TRANS ? (tid & 7) * 8 : tid >> 2;
+  const int ak = TRANS ? tid >> 3 : (tid & 3) * 8;
+  const int jl = tid >> 3, part = tid & 7;
+  const T* bsrc = nullptr;
+  if (j0 + jl < P.count) {
+    const SliceDesc& D = P.desc[P.list[j0 + jl]];
+    const void* v = MODE == G_ATB ? D.b : (MODE == G_AX_R0 ? D.x : (MODE == G_AP ? D.p : D.y));
+    bsrc = static_cast<const T*>(v);
+  }
+  const int kmax_b = MODE == G_ATB ? Mv : K;   // b has only M rows
+  T ra[8], rb[8];
+  auto fetch = [&](int k0) {
+    const T* src = TRANS ? A + (size_t)(k0 + ak) * N + row0 + ar : A + (size_t)(row0 + ar) * N + k0 + ak;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ra[e] = src[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + ((part * 8 + e) >> 1);
+      rb[e] = (bsrc && k < kmax_b) ? bsrc[2 * (size_t)k + (e & 1)] : (T)0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (TRANS) As[ak][ar + e] = ra[e];
+      else As[ak + e][ar] = ra[e];
+      Bs[(part * 8 + e) >> 1][2 * jl + (e & 1)] = rb[e];
+    }
+  };
+
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  typename M::V acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename M::V{0, 0, 0, 0};
+
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    stash();
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int k = kk + (lane >> 4);
+      T a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) a[mi] = As[k][wr + 16 * mi + (lane & 15)];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) b[ni] = Bs[k][wc + 16 * ni + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = M::mac(a[mi], b[ni], acc[mi][ni]);
+    }
+    __syncthreads();
+  }
+
+  if (P.gsplit > 1) {
+    T* scr = static_cast<T*>(P.gscr);
+    const int rows = TRANS ? N : Mp;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wr + 16 * mi + M::row(lane, r);
+          const int col = blockIdx.y * BN + wc + 16 * ni + (lane & 15);
+          scr[gemm_scr(blockIdx.z, row, rows, col)] = acc[mi][ni][r];
+        }
+    return;
+  }
+  gemm_epilogue<T, MODE>(P, row0, j0, [&](int mi, int ni, int r) { return acc[mi][ni][r]; }, colpart);
+}
+
+// Sum of the P.gsplit partial tiles (split order fixed), then the epilogue.
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_gemm_reduce(Params P) {
+  using M = Mfma<T>;
+  constexpr bool TRANS = (MODE == G_ATB || MODE == G_ATY);
+  __shared__ double colpart[2][BN];
+  const int rows = TRANS ? P.n * P.n : P.shape.Mp;
+  const int row0 = blockIdx.x * GEMM_BM, j0 = blockIdx.y * GEMM_BS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const T* scr = static_cast<const T*>(P.gscr);
+  auto val = [&](int mi, int ni, int r) {
+    const int row = row0 + wr + 16 * mi + M::row(lane, r);
+    const int col = blockIdx.y * BN + wc + 16 * ni + (lane & 15);
+    T v = (T)0;
+    for (int sp = 0; sp < P.gsplit; ++sp) v += scr[gemm_scr(sp, row, rows, col)];
+    return v;
+  };
+  gemm_epilogue<T, MODE>(P, row0, j0, val, colpart);
+}
+
 template <typename T, int MODE>
 hipError_t L_gemm(const Params& P, dim3 g, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm<T, MODE>), g, dim3(NT), 0, st, P);
+  hipLaunchKernelGGL((k_gemm<T, MODE>), dim3(g.x, g.y, P.gsplit), dim3(NT), 0, st, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || P.gsplit <= 1) return e;
+  hipLaunchKernelGGL((k_gemm_reduce<T, MODE>), g, dim3(NT), 0, st, P);
   return hipGetLastError();
 }
 
