@@ -45,6 +45,7 @@ struct Shape {
   int M = 0, Mp = 0;    // its rows, and rows padded to the GEMM tile
   void* d_A = nullptr;  // Mp x n^2 in the working precision
   double rho_A = 0.0;   // mean diag(A^T A)
+  int32_t* d_bgptr = nullptr;   // band-local group map: first group of every row band
   size_t pixels() const { return (size_t)C * n * n; }
   int row_wgs() const { return C * n / band_rows(n); }                  // row-pass workgroups
   int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64)); }  // column-pass workgroups
@@ -281,6 +282,7 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.shape.tidx = s.d_tidx;
   P.shape.perm = s.d_perm;
   P.shape.A = s.d_A;
+  P.shape.bgptr = s.d_bgptr;
   P.shape.M = s.M;
   P.shape.Mp = s.Mp;
   P.nofft = s.dense ? 1 : 0;
@@ -417,10 +419,12 @@ int launch_dense_normal(firls_handle* h, const Shape& s, Params P, int c, hipStr
   return rc ? rc : launch_gemm(h, s, P, G_ATY, c, st, FIRLS_PROF_COL);
 }
 
-int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+// Weights, residual and data term of the current x, then the objective
+// check (one outer iteration's preparation).
+int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int C = strip_cols(h->fp64);
   const dim3 rows(s.row_wgs(), c);
+  Params P = P0;
   if (s.dense) {
     int rc = launch_weights(h, s, P, c, st);
     if (rc || (rc = launch_dense_residual(h, s, P, c, st))) return rc;
@@ -430,6 +434,12 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P, int c, hipStre
       KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
       KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
     }
+  } else if (s.psi == PSI_HAAR && s.d_bgptr) {
+    // band-local groups: weights inside the residual's row pass
+    P.nreg = s.row_wgs();
+    KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQW_HAAR], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
+    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
   } else if (s.psi == PSI_HAAR) {
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQ_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
@@ -837,6 +847,48 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
     for (int i = 0; i < s.n_coef; ++i) perm[i] = i;
   }
   for (auto& v : idx) v = perm[v];
+  // Haar maps whose groups each lie inside one row band of the row passes
+  // (tree groups do) get their weights inside the residual's row pass:
+  // groups are ordered by band, and the band's |Psi x|^2 and W must fit in
+  // that pass's LDS
+  std::vector<int32_t> bgptr;
+  if (s.psi == PSI_HAAR && !s.dense) {
+    const int R = band_rows(n), nb = s.C * n / R;
+    const int64_t per = (int64_t)R * n;
+    std::vector<int> band(s.n_groups, -1);
+    bool local = true;
+    for (int g = 0; g < s.n_groups && local; ++g)
+      for (int j = ptr[g]; j < ptr[g + 1]; ++j) {
+        const int b = (int)(idx[j] / per);
+        if (band[g] < 0) band[g] = b;
+        else if (band[g] != b) { local = false; break; }
+      }
+    std::vector<int32_t> cnt(nb + 1, 0);
+    for (int g = 0; g < s.n_groups && local; ++g)
+      if (band[g] >= 0) cnt[band[g] + 1]++;
+      else local = false;                      // an empty group
+    if (local) {
+      for (int b = 0; b < nb; ++b) cnt[b + 1] += cnt[b];
+      const size_t lds = (size_t)R * (n + n / 16 + 1) * h->elt;
+      int most = 0;
+      for (int b = 0; b < nb; ++b) most = std::max(most, cnt[b + 1] - cnt[b]);
+      if ((size_t)(per + most) * h->relt <= lds) {
+        // stable reorder by band
+        std::vector<int32_t> order(s.n_groups), fill(cnt.begin(), cnt.end() - 1);
+        for (int g = 0; g < s.n_groups; ++g) order[fill[band[g]]++] = g;
+        std::vector<int32_t> p2(s.n_groups + 1, 0), i2;
+        i2.reserve(idx.size());
+        for (int k = 0; k < s.n_groups; ++k) {
+          const int g = order[k];
+          for (int j = ptr[g]; j < ptr[g + 1]; ++j) i2.push_back(idx[j]);
+          p2[k + 1] = (int32_t)i2.size();
+        }
+        ptr.swap(p2);
+        idx.swap(i2);
+        bgptr = cnt;
+      }
+    }
+  }
   std::vector<int32_t> tptr(s.n_coef + 1, 0), tidx(idx.size());
   for (int32_t v : idx) tptr[v + 1]++;
   for (int i = 0; i < s.n_coef; ++i) tptr[i + 1] += tptr[i];
@@ -850,7 +902,8 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   };
   int rc;
   if ((rc = up(&s.d_gptr, ptr)) || (rc = up(&s.d_gidx, idx)) || (rc = up(&s.d_tptr, tptr)) ||
-      (rc = up(&s.d_tidx, tidx)) || (rc = up(&s.d_perm, perm)))
+      (rc = up(&s.d_tidx, tidx)) || (rc = up(&s.d_perm, perm)) ||
+      (!bgptr.empty() && (rc = up(&s.d_bgptr, bgptr))))
     return rc;
   s.sk = size_kernels(h->fp64, n);
   if (!s.sk) return fail(FIRLS_E_UNSUPPORTED, "no kernels for this size");
@@ -880,7 +933,7 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
 
 void destroy_shapes(firls_handle* h) {
   for (auto& s : h->shapes) {
-    for (int32_t* p : {s.d_gptr, s.d_gidx, s.d_tptr, s.d_tidx, s.d_perm})
+    for (int32_t* p : {s.d_gptr, s.d_gidx, s.d_tptr, s.d_tidx, s.d_perm, s.d_bgptr})
       if (p) (void)hipFree(p);
     if (s.d_A) (void)hipFree(s.d_A);
   }

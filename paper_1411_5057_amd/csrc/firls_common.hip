@@ -55,36 +55,8 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
 __global__ __launch_bounds__(NT) void k_outer_check(Params P) {
   __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
-  SliceState& S = P.state[s];
-  if (!S.active) return;
-  const SliceDesc& D = P.desc[s];
-  const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
-  const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg, red);
-  const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg, red);
-  if (threadIdx.x != 0) return;
-  const double Fe = data + D.lambda * re;
-  const double F = data + D.lambda * r0;
-  const bool first = S.evals == 0;
-  const double prev = S.Fe;
-  S.Fe_prev = first ? Fe : prev;
-  S.rel = first ? 0.0 : (prev - Fe) / Fe;
-  S.Fe = Fe;
-  S.F = F;
-  S.data = data;
-  S.evals += 1;
-  if (!isfinite(Fe)) {
-    S.status = -5;  // FIRLS_E_NONFINITE
-    S.active = 0;
-  } else if (!first && P.tau > 0.0 && (prev - Fe) <= P.tau * Fe) {
-    S.converged = 1;
-    S.active = 0;
-  } else if (S.outer >= P.Tmax) {
-    if (P.tau > 0.0) S.status = 1;  // FIRLS_W_MAXITER
-    S.active = 0;
-  } else {
-    S.outer += 1;
-    S.pcg += P.K;
-  }
+  if (!P.state[s].active) return;
+  outer_check_wg(P, s, red);
 }
 
 // d in the caller's coefficient order: out[u] = d[perm[u]].

@@ -61,6 +61,7 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowfwd<T, N, RF_PCG_Z>, b);
   allow_lds(k_rowfwd<T, N, RF_STEP_HAAR>, b);
   allow_lds(k_rowfwd<T, N, RF_SQ_HAAR>, b);
+  allow_lds(k_rowfwd<T, N, RF_SQW_HAAR>, b);
   const size_t bc = lds_col_bytes<T, N>();
   allow_lds(k_col<T, N, COL_SP>, bc);
   allow_lds(k_col<T, N, COL_R0>, bc);
@@ -78,6 +79,7 @@ SizeKernels make_size_kernels() {
   k.rowfwd[RF_PCG_Z] = L_rowfwd<T, N, RF_PCG_Z>;
   k.rowfwd[RF_STEP_HAAR] = L_rowfwd<T, N, RF_STEP_HAAR>;
   k.rowfwd[RF_SQ_HAAR] = L_rowfwd<T, N, RF_SQ_HAAR>;
+  k.rowfwd[RF_SQW_HAAR] = L_rowfwd<T, N, RF_SQW_HAAR>;
   k.col[COL_SP] = L_col<T, N, COL_SP>;
   k.col[COL_R0] = L_col<T, N, COL_R0>;
   k.col[COL_AHB] = L_col<T, N, COL_AHB>;

@@ -106,6 +106,43 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
   else precond_tile_k<NEED_Z, N, PC_NONE>(v, dg, L, col, rho, lam, acc);
 }
 
+// Objective of the current x and the outer stopping rule of slice s (one
+// workgroup; every thread takes part in the sums).  F_eps = data + lambda
+// sum sqrt(s_g + eps); stop when (F_eps^{prev} - F_eps) <= tau F_eps after
+// the first evaluation, or once Tmax solves are done; otherwise count the
+// solve that follows.
+__device__ __forceinline__ void outer_check_wg(const Params& P, int s, double* red) {
+  SliceState& S = P.state[s];
+  const SliceDesc& D = P.desc[s];
+  const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
+  const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg, red);
+  const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg, red);
+  if (threadIdx.x != 0) return;
+  const double Fe = data + D.lambda * re;
+  const double F = data + D.lambda * r0;
+  const bool first = S.evals == 0;
+  const double prev = S.Fe;
+  S.Fe_prev = first ? Fe : prev;
+  S.rel = first ? 0.0 : (prev - Fe) / Fe;
+  S.Fe = Fe;
+  S.F = F;
+  S.data = data;
+  S.evals += 1;
+  if (!isfinite(Fe)) {
+    S.status = -5;  // FIRLS_E_NONFINITE
+    S.active = 0;
+  } else if (!first && P.tau > 0.0 && (prev - Fe) <= P.tau * Fe) {
+    S.converged = 1;
+    S.active = 0;
+  } else if (S.outer >= P.Tmax) {
+    if (P.tau > 0.0) S.status = 1;  // FIRLS_W_MAXITER
+    S.active = 0;
+  } else {
+    S.outer += 1;
+    S.pcg += P.K;
+  }
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // TV coefficients are stored in forward slots: slot (r, c) of D1 holds
@@ -151,6 +188,52 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   auto gdst = [&](int l, int q, C v) { t[t_index<T, N>(row0 + l, q)] = v; };
   if constexpr (MODE == RF_PLAIN) {
     const C* x = static_cast<const C*>(D.x) + off;
+    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
+  } else if constexpr (MODE == RF_SQW_HAAR) {
+    // Every group lies inside one row band (tree groups do: parent and child
+    // share a Haar tile), so the weights need nothing outside this band:
+    // |Phi x|^2 into LDS, W_g of the band's groups (eq. 12) and the penalty
+    // partials, then d = diag(G^T W G) of the band's coefficients (eq. 13),
+    // all on chip; the LDS is then reused for the row FFTs of x.
+    const C* x = static_cast<const C*>(D.x) + off;
+    T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
+    T* WL = sqL + ROWS * N;                         // the band's groups
+#pragma unroll
+    for (int k = 0; k < U::PER; ++k) {
+      if (!U::valid(k)) continue;
+      const int col = U::col(k), row = U::row(k);
+      C v[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) v[s] = x[(row + s) * N + col];
+      haar_col<false>(v, P.L, col);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) sqL[(row + s) * N + col] = (T)cabs2(v[s]);
+    }
+    __syncthreads();
+    const int g0 = P.shape.bgptr[blockIdx.x], g1 = P.shape.bgptr[blockIdx.x + 1];
+    double ae = 0.0, a0 = 0.0;
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
+      double s2 = 0.0;
+      for (int j = P.shape.gptr[g]; j < P.shape.gptr[g + 1]; ++j) s2 += (double)sqL[P.shape.gidx[j] - (int)off];
+      const double v = sqrt(s2 + P.eps);
+      WL[g - g0] = (T)(1.0 / v);
+      ae += v;
+      a0 += sqrt(s2);
+    }
+    __syncthreads();
+    T* d = static_cast<T*>(D.d) + off;
+    for (int j = threadIdx.x; j < ROWS * N; j += NT) {
+      double s2 = 0.0;
+      for (int t = P.shape.tptr[off + j]; t < P.shape.tptr[off + j + 1]; ++t) s2 += (double)WL[P.shape.tidx[t] - g0];
+      d[j] = (T)s2;
+    }
+    ae = block_sum(ae, red);       // also orders the LDS reads above before the FFT
+    a0 = block_sum(a0, red);
+    if (threadIdx.x == 0) {
+      slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
+      slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
+    }
+    __syncthreads();
     fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
   } else if constexpr (MODE == RF_SQ_HAAR) {
     // row FFTs of x and, from the same read, |Phi x|^2 per coefficient

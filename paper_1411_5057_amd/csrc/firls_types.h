@@ -37,7 +37,8 @@ enum Psi : int { PSI_HAAR = 0, PSI_TV = 1 };
 enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
 
 // Kernel variants (template modes).
-enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAAR = 3, RF_SQ_HAAR = 4 };
+enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAAR = 3, RF_SQ_HAAR = 4,
+                        RF_SQW_HAAR = 5 };
 enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3, COL_SP_PQ = 4 };
 enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
 enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
@@ -103,6 +104,7 @@ struct ShapeDev {
   const int32_t* perm;   // user coefficient index -> internal index
   int32_t n_groups;
   int32_t n_coef;
+  const int32_t* bgptr;  // band-local group maps: groups of row band b are bgptr[b] .. bgptr[b+1]-1
   const void* A;         // dense sensing matrix, Mp x n^2 row-major (rows >= M zero), or null
   int32_t M;             // measurements of the dense matrix
   int32_t Mp;            // M rounded up to the GEMM row tile
