@@ -2,6 +2,7 @@
 // buffers, and the forward / training entry points of the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -97,6 +98,29 @@ int forward(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0) {
   return FIRLS_OK;
 }
 
+// Inference: the whole network in one kernel (activations stay on chip),
+// one persistent workgroup per compute unit looping over 16 x 16 tiles.
+int forward_fused(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    CHK(hipGetDevice(&dev));
+    CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  NetArgs a{};
+  a.zf = zf;
+  a.x0 = x0;
+  for (int l = 0; l < LAYERS; ++l) {
+    a.w[l] = c->wf + c->geo[l].wfoff;
+    a.b[l] = c->bias + c->geo[l].boff_pad;
+  }
+  a.n = c->n;
+  a.batch = batch;
+  const int tiles = batch * (c->n / 16) * (c->n / 16);
+  CHK(launch_net_fwd(a, std::min(tiles, cus), st));
+  return FIRLS_OK;
+}
+
 // Forward, loss, backward; leaves the master-layout gradient in c->grad.
 int gradients(firls_cnn* c, hipStream_t st, int batch, const void* zf, const void* label, double* loss) {
   int rc = forward(c, st, batch, zf, c->x0);
@@ -142,7 +166,7 @@ int gradients(firls_cnn* c, hipStream_t st, int batch, const void* zf, const voi
 namespace firls {
 
 int cnn_forward(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0) {
-  return forward(c, st, batch, zf, x0);
+  return forward_fused(c, st, batch, zf, x0);
 }
 int cnn_image_side(const firls_cnn* c) { return c->n; }
 int cnn_max_batch(const firls_cnn* c) { return c->max_batch; }
@@ -237,7 +261,7 @@ int firls_cnn_forward(firls_cnn* c, void* stream, int32_t batch, const void* zf,
   if (batch <= 0 || batch > c->max_batch) return set_error(FIRLS_E_INVALID, "batch out of range");
   if (!c->have_params) return set_error(FIRLS_E_INVALID, "parameters not set");
   hipStream_t st = (hipStream_t)stream;
-  int rc = forward(c, st, batch, zf, x0);
+  int rc = forward_fused(c, st, batch, zf, x0);
   if (rc) return rc;
   CHK(hipStreamSynchronize(st));
   return FIRLS_OK;

@@ -33,6 +33,16 @@ struct ConvArgs {
   int n, batch;
 };
 
+// Fused inference of the whole network (packed bf16 weights and padded FP32
+// biases per layer, as the per-layer kernels use them).
+struct NetArgs {
+  const void* zf;       // complex float [B, n, n]
+  void* x0;             // complex float [B, n, n] = zf + f(zf)
+  const void* w[LAYERS];
+  const float* b[LAYERS];
+  int n, batch;
+};
+
 struct WgradArgs {
   const void* x;        // bf16 [B, n, n, CIN] layer input
   const void* gy;       // bf16 [B, n, n, COUT] output gradient
@@ -89,6 +99,7 @@ struct ChooseArgs {
 };
 
 hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs& a, hipStream_t st);
+hipError_t launch_net_fwd(const NetArgs& a, int grid, hipStream_t st);
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);

@@ -1,7 +1,8 @@
 """GPU parity of the warm-start network kernels against the FP64 oracle with
 bfloat16 emulation.
 
-Bars: network output f(zf) to 1e-3 relative L2 (bfloat16 outputs), weight
+Bars: network output f(zf) to 1e-3 relative L2 (bfloat16 outputs) and 2e-2
+of its largest magnitude at every pixel, weight
 gradients to 1e-2 relative L2 per layer (FP32 split-K sums of bfloat16
 products), one Adam step exact to FP32 rounding, and FIRLS finished from the
 learned start reaching the oracle's objective to 1e-5.
@@ -48,7 +49,11 @@ def test_forward(n, batch):
     net.forward(zt, x0)
     zfr = to_np(zt)                                   # the FP32 values the GPU saw
     ref, _ = cnn.forward(params, zfr, bf16_mode=True)
-    assert rel(to_np(x0) - zfr, ref - zfr) < 1e-3
+    got = to_np(x0) - zfr
+    assert rel(got, ref - zfr) < 1e-3
+    # every pixel, tile seams and image borders included: a bfloat16 rounding
+    # flip moves one output by far less than this
+    assert np.max(np.abs(got - (ref - zfr))) < 2e-2 * np.max(np.abs(ref - zfr))
 
 
 @pytest.mark.parametrize("n,batch", [(32, 2), (64, 2)])
