@@ -258,6 +258,86 @@ __device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src s
   }
 }
 
+// Forward FFT of LINES lines, a pointwise map of the spectrum, inverse FFT:
+// dst(line, pos, IFFT(mid(line, k, FFT(src))[k])).  In the Stockham order the
+// last forward stage (radix RL) leaves butterfly j of a line holding the
+// spectrum at positions j + r N / RL, exactly the inputs of butterfly j of
+// the first inverse stage (same radix, no twiddles), so the spectrum stays
+// in registers between the two transforms: one LDS round trip and two
+// barriers fewer than two fft_lines calls.
+template <typename T, int N, int LINES, int MAP, class Src, class Mid, class Dst>
+__device__ __forceinline__ void fft_lines_fwd_inv(cplx<T>* lds, const cplx<T>* tw, Src src, Mid mid, Dst dst) {
+  using P = Plan<N>;
+  constexpr int RL = P::S == 3 ? P::R2 : (P::S == 2 ? P::R1 : P::R0);
+  constexpr int NBL = N / RL;
+  LdsIO<T, N> io{lds};
+  using L = Stage<T, N, RL, NBL, LINES, MAP, false>;    // last forward stage
+  using I0 = Stage<T, N, RL, 1, LINES, MAP, true>;      // first inverse stage
+  cplx<T> v[L::ITER][RL];
+  if constexpr (P::S == 1) {
+    L::load(v, src, tw);
+  } else {
+    using S0 = Stage<T, N, P::R0, 1, LINES, MAP, false>;
+    {
+      cplx<T> v0[S0::ITER][P::R0];
+      S0::load(v0, src, tw);
+      __syncthreads();
+      S0::store(v0, io);
+      __syncthreads();
+    }
+    if constexpr (P::S == 3) {
+      using S1 = Stage<T, N, P::R1, P::R0, LINES, MAP, false>;
+      cplx<T> v1[S1::ITER][P::R1];
+      S1::load(v1, io, tw);
+      __syncthreads();
+      S1::store(v1, io);
+      __syncthreads();
+    }
+    L::load(v, io, tw);
+  }
+#pragma unroll
+  for (int i = 0; i < L::ITER; ++i) {
+    const int b = threadIdx.x + i * NT;
+    if (L::TOT % NT != 0 && b >= L::TOT) continue;
+    int line, j;
+    L::decode(b, line, j);
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[i][r] = mid(line, j + r * NBL, v[i][r]);
+    SmallDFT<T, RL, true>::run(v[i]);
+  }
+  if constexpr (P::S == 1) {
+    I0::store(v, dst);
+    __syncthreads();
+  } else {
+    __syncthreads();   // the last forward stage's LDS reads are done
+    I0::store(v, io);
+    __syncthreads();
+    if constexpr (P::S == 2) {
+      using I1 = Stage<T, N, P::R0, RL, LINES, MAP, true>;
+      cplx<T> u[I1::ITER][P::R0];
+      I1::load(u, io, tw);
+      __syncthreads();
+      I1::store(u, dst);
+      __syncthreads();
+    } else {
+      using I1 = Stage<T, N, P::R1, RL, LINES, MAP, true>;
+      {
+        cplx<T> u[I1::ITER][P::R1];
+        I1::load(u, io, tw);
+        __syncthreads();
+        I1::store(u, io);
+        __syncthreads();
+      }
+      using I2 = Stage<T, N, P::R0, RL * P::R1, LINES, MAP, true>;
+      cplx<T> u[I2::ITER][P::R0];
+      I2::load(u, io, tw);
+      __syncthreads();
+      I2::store(u, dst);
+      __syncthreads();
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Register-resident tile-local orthonormal Haar.
 //

@@ -350,7 +350,6 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__(NT) void k_col(Params P) {
   constexpr int COLS = Geo<T>::COLS;
   using C = cplx<T>;
-  using Lay = LdsLayout<N>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
@@ -367,36 +366,36 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   auto sampled = [&](int c, int row) { return (mw[row] >> (sh0 + c)) & 1u; };
   auto gsrc = [&](int c, int row) { return t[row * COLS + c]; };
   auto gdst = [&](int c, int row, C v) { t[row * COLS + c] = v; };
-  LdsIO<T, N> io{lds};
   const T sn = (T)1 / (T)N;
+  // the spectrum passes from the forward to the inverse column FFT in
+  // registers (fft_lines_fwd_inv); the partial sums of a mode are complete
+  // once the inverse has started, and are summed after it
   if constexpr (MODE == COL_SP) {
     const T sc = sn * sn;
-    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
-      lds[Lay::at(c, row)] = sampled(c, row) ? v * sc : C{(T)0, (T)0};
-    });
-    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
+      return sampled(c, row) ? v * sc : C{(T)0, (T)0};
+    }, gdst);
   } else if constexpr (MODE == COL_SP_PQ) {
     // as COL_SP, and the partials of <p, A^H A p> = ||m F p||^2 / n^2 go to
     // the <p, S p> slot after the row pass's partials
     const T sc = sn * sn;
     double acc = 0.0;
-    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
       C u{(T)0, (T)0};
       if (sampled(c, row)) {
         acc += (double)(cabs2t(v) * sc);
         u = v * sc;
       }
-      lds[Lay::at(c, row)] = u;
-    });
+      return u;
+    }, gdst);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[P.C * (N / band_rows(N)) + blockIdx.x] = tot;
-    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else if constexpr (MODE == COL_R0) {
     // k = (F x) at the sampled entries; keep m (b - k) / n for the inverse
     // and accumulate 1/2 ||m F x - b||^2.
     const C* b = static_cast<const C*>(D.b);
     double acc = 0.0;
-    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
       const size_t g = (size_t)(ch * N + row) * N + col0 + c;
       C u{(T)0, (T)0};
       if (sampled(c, row)) {
@@ -404,20 +403,18 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
         acc += cabs2(u);
         u = u * sn;
       }
-      lds[Lay::at(c, row)] = u;
-    });
+      return u;
+    }, gdst);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) slot_wptr(D, SLOT_DATA)[blockIdx.x] = 0.5 * tot;
-    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
   } else if constexpr (MODE == COL_DC) {
     // data consistency: keep F x where unsampled, put b where sampled
     // (k = m b + (1 - m) F x), then the column inverse with 1/n
     const C* b = static_cast<const C*>(D.b);
-    fft_lines<T, N, COLS, COLMAP, false>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
       const size_t g = (size_t)(ch * N + row) * N + col0 + c;
-      lds[Lay::at(c, row)] = (sampled(c, row) ? b[g] : v * sn) * sn;
-    });
-    fft_lines<T, N, COLS, COLMAP, true>(lds, tw, io, gdst);
+      return (sampled(c, row) ? b[g] : v * sn) * sn;
+    }, gdst);
   } else {
     const C* b = static_cast<const C*>(D.b);
     fft_lines<T, N, COLS, COLMAP, true>(lds, tw, [&](int c, int row) {
