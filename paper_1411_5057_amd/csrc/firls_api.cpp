@@ -46,6 +46,9 @@ struct Shape {
   void* d_A = nullptr;  // Mp x n^2 in the working precision
   double rho_A = 0.0;   // mean diag(A^T A)
   int32_t* d_bgptr = nullptr;   // band-local group map: first group of every row band
+  uint16_t* d_gell = nullptr;   // and its padded member / membership lists (ShapeDev)
+  uint16_t* d_tell = nullptr;
+  int ell_gw = 0, ell_tw = 0;
   size_t pixels() const { return (size_t)C * n * n; }
   int row_wgs() const { return C * n / band_rows(n); }                  // row-pass workgroups
   int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64)); }  // column-pass workgroups
@@ -283,6 +286,10 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.shape.perm = s.d_perm;
   P.shape.A = s.d_A;
   P.shape.bgptr = s.d_bgptr;
+  P.shape.gell = s.d_gell;
+  P.shape.tell = s.d_tell;
+  P.shape.gw = s.ell_gw;
+  P.shape.tw = s.ell_tw;
   P.shape.M = s.M;
   P.shape.Mp = s.Mp;
   P.nofft = s.dense ? 1 : 0;
@@ -905,6 +912,38 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
       (rc = up(&s.d_tidx, tidx)) || (rc = up(&s.d_perm, perm)) ||
       (!bgptr.empty() && (rc = up(&s.d_bgptr, bgptr))))
     return rc;
+  // small band-local groups also get the padded lists: one coalesced load
+  // per member instead of a pointer chase through the CSR arrays
+  if (!bgptr.empty()) {
+    const int64_t per = (int64_t)band_rows(n) * n;
+    int gw = 0, tw = 0;
+    for (int g = 0; g < s.n_groups; ++g) gw = std::max(gw, ptr[g + 1] - ptr[g]);
+    for (int i = 0; i < s.n_coef; ++i) tw = std::max(tw, tptr[i + 1] - tptr[i]);
+    auto pow2 = [](int v) { int w = 1; while (w < v) w *= 2; return w; };
+    gw = pow2(gw);
+    tw = pow2(tw);
+    if (gw <= ELL_MAX && tw <= ELL_MAX && per <= 0xFFFF) {
+      std::vector<uint16_t> gell((size_t)gw * s.n_groups, 0xFFFF), tell((size_t)tw * s.n_coef, 0xFFFF);
+      const int nb = (int)bgptr.size() - 1;
+      for (int b = 0; b < nb; ++b)
+        for (int g = bgptr[b]; g < bgptr[b + 1]; ++g)
+          for (int j = ptr[g]; j < ptr[g + 1]; ++j)
+            gell[(size_t)g * gw + (j - ptr[g])] = (uint16_t)(idx[j] - b * per);
+      for (int i = 0; i < s.n_coef; ++i) {
+        const int b = (int)(i / per);
+        for (int t = tptr[i]; t < tptr[i + 1]; ++t)
+          tell[(size_t)i * tw + (t - tptr[i])] = (uint16_t)(tidx[t] - bgptr[b]);
+      }
+      auto up16 = [&](uint16_t** dst, const std::vector<uint16_t>& v) -> int {
+        HIPCHK(hipMalloc(dst, std::max<size_t>(1, v.size()) * sizeof(uint16_t)));
+        if (!v.empty()) HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        return FIRLS_OK;
+      };
+      if ((rc = up16(&s.d_gell, gell)) || (rc = up16(&s.d_tell, tell))) return rc;
+      s.ell_gw = gw;
+      s.ell_tw = tw;
+    }
+  }
   s.sk = size_kernels(h->fp64, n);
   if (!s.sk) return fail(FIRLS_E_UNSUPPORTED, "no kernels for this size");
   // twiddles exp(-2 pi i k / n), computed in FP64
@@ -934,6 +973,8 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
 void destroy_shapes(firls_handle* h) {
   for (auto& s : h->shapes) {
     for (int32_t* p : {s.d_gptr, s.d_gidx, s.d_tptr, s.d_tidx, s.d_perm, s.d_bgptr})
+      if (p) (void)hipFree(p);
+    for (uint16_t* p : {s.d_gell, s.d_tell})
       if (p) (void)hipFree(p);
     if (s.d_A) (void)hipFree(s.d_A);
   }

@@ -430,6 +430,48 @@ struct Units {
 };
 
 // ---------------------------------------------------------------------------
+// Group weights.
+// ---------------------------------------------------------------------------
+// One padded list of w (1, 2, 4 or 8) 16-bit entries with a single load.
+__device__ __forceinline__ void ell_row(const uint16_t* p, int w, uint16_t (&e)[ELL_MAX]) {
+#pragma unroll
+  for (int m = 0; m < ELL_MAX; ++m) e[m] = 0xFFFFu;
+  if (w == 1) {
+    e[0] = p[0];
+  } else if (w == 2) {
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+    e[0] = (uint16_t)v;
+    e[1] = (uint16_t)(v >> 16);
+  } else if (w == 4) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16);
+    e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
+  } else {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16);
+    e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
+    e[4] = (uint16_t)v.z; e[5] = (uint16_t)(v.z >> 16);
+    e[6] = (uint16_t)v.w; e[7] = (uint16_t)(v.w >> 16);
+  }
+}
+
+// W = (s2 + eps)^(-1/2) (eq. 12), ve = sqrt(s2 + eps) and v0 = sqrt(s2) (the
+// smoothed and plain penalty terms) in the working precision: FP32 uses the
+// hardware square root and reciprocal square root (about 1 ulp), FP64 the
+// correctly rounded operations.
+__device__ __forceinline__ void group_weight(float s2, float eps, float& w, float& ve, float& v0) {
+  const float q = s2 + eps;
+  w = __builtin_amdgcn_rsqf(q);
+  ve = __builtin_amdgcn_sqrtf(q);
+  v0 = __builtin_amdgcn_sqrtf(s2);
+}
+__device__ __forceinline__ void group_weight(double s2, double eps, double& w, double& ve, double& v0) {
+  ve = sqrt(s2 + eps);
+  w = 1.0 / ve;
+  v0 = sqrt(s2);
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic FP64 reductions.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -194,38 +194,58 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     // share a Haar tile), so the weights need nothing outside this band:
     // |Phi x|^2 into LDS, W_g of the band's groups (eq. 12) and the penalty
     // partials, then d = diag(G^T W G) of the band's coefficients (eq. 13),
-    // all on chip; the LDS is then reused for the row FFTs of x.
+    // all on chip; x stays in registers meanwhile and then goes through the
+    // same LDS for the row FFTs.
     const C* x = static_cast<const C*>(D.x) + off;
     T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
     T* WL = sqL + ROWS * N;                         // the band's groups
+    C xv[U::PER][16];
 #pragma unroll
     for (int k = 0; k < U::PER; ++k) {
       if (!U::valid(k)) continue;
       const int col = U::col(k), row = U::row(k);
       C v[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) v[s] = x[(row + s) * N + col];
+      for (int s = 0; s < 16; ++s) v[s] = xv[k][s] = x[(row + s) * N + col];
       haar_col<false>(v, P.L, col);
 #pragma unroll
       for (int s = 0; s < 16; ++s) sqL[(row + s) * N + col] = (T)cabs2(v[s]);
     }
     __syncthreads();
     const int g0 = P.shape.bgptr[blockIdx.x], g1 = P.shape.bgptr[blockIdx.x + 1];
+    const ShapeDev& G = P.shape;
     double ae = 0.0, a0 = 0.0;
     for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
-      double s2 = 0.0;
-      for (int j = P.shape.gptr[g]; j < P.shape.gptr[g + 1]; ++j) s2 += (double)sqL[P.shape.gidx[j] - (int)off];
-      const double v = sqrt(s2 + P.eps);
-      WL[g - g0] = (T)(1.0 / v);
-      ae += v;
-      a0 += sqrt(s2);
+      T s2 = (T)0;
+      if (G.gell) {   // padded list: one load, members in the CSR order
+        uint16_t e[ELL_MAX];
+        ell_row(G.gell + (size_t)g * G.gw, G.gw, e);
+#pragma unroll
+        for (int m = 0; m < ELL_MAX; ++m)
+          if (m < G.gw && e[m] != 0xFFFFu) s2 += sqL[e[m]];
+      } else {
+        for (int j = G.gptr[g]; j < G.gptr[g + 1]; ++j) s2 += sqL[G.gidx[j] - (int)off];
+      }
+      T w, ve, v0;
+      group_weight(s2, (T)P.eps, w, ve, v0);
+      WL[g - g0] = w;
+      ae += (double)ve;
+      a0 += (double)v0;
     }
     __syncthreads();
     T* d = static_cast<T*>(D.d) + off;
     for (int j = threadIdx.x; j < ROWS * N; j += NT) {
-      double s2 = 0.0;
-      for (int t = P.shape.tptr[off + j]; t < P.shape.tptr[off + j + 1]; ++t) s2 += (double)WL[P.shape.tidx[t] - g0];
-      d[j] = (T)s2;
+      T s2 = (T)0;
+      if (G.tell) {
+        uint16_t e[ELL_MAX];
+        ell_row(G.tell + (off + j) * G.tw, G.tw, e);
+#pragma unroll
+        for (int m = 0; m < ELL_MAX; ++m)
+          if (m < G.tw && e[m] != 0xFFFFu) s2 += WL[e[m]];
+      } else {
+        for (int t = G.tptr[off + j]; t < G.tptr[off + j + 1]; ++t) s2 += WL[G.tidx[t] - g0];
+      }
+      d[j] = s2;
     }
     ae = block_sum(ae, red);       // also orders the LDS reads above before the FFT
     a0 = block_sum(a0, red);
@@ -233,8 +253,15 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
       slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
     }
+#pragma unroll
+    for (int k = 0; k < U::PER; ++k) {
+      if (!U::valid(k)) continue;
+      const int col = U::col(k), row = U::row(k);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) lds[Lay::at(row + s, col)] = xv[k][s];
+    }
     __syncthreads();
-    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
+    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
   } else if constexpr (MODE == RF_SQ_HAAR) {
     // row FFTs of x and, from the same read, |Phi x|^2 per coefficient
     const C* x = static_cast<const C*>(D.x) + off;

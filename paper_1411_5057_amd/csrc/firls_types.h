@@ -96,6 +96,8 @@ struct SliceState {
 };
 
 // Group map of one shape on the device (internal coefficient indices).
+constexpr int ELL_MAX = 8;        // widest padded group / membership list
+
 struct ShapeDev {
   const int32_t* gptr;   // [n_groups + 1]
   const int32_t* gidx;   // members
@@ -105,6 +107,13 @@ struct ShapeDev {
   int32_t n_groups;
   int32_t n_coef;
   const int32_t* bgptr;  // band-local group maps: groups of row band b are bgptr[b] .. bgptr[b+1]-1
+  // band-local maps with small groups, padded (ELLPACK) lists:
+  // gell[g * gw + m] = m-th member of group g, tell[j * tw + m] = m-th group
+  // holding coefficient j, both relative to the row band (member offset in
+  // the band, group offset from bgptr[b]); 0xFFFF pads
+  const uint16_t* gell;
+  const uint16_t* tell;
+  int32_t gw, tw;        // list widths: 1, 2, 4 or 8 (ELL_MAX)
   const void* A;         // dense sensing matrix, Mp x n^2 row-major (rows >= M zero), or null
   int32_t M;             // measurements of the dense matrix
   int32_t Mp;            // M rounded up to the GEMM row tile
