@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--precond", choices=("paper", "jacobi", "none"), default="paper",
                     help="inner preconditioner: the paper's (eq. 17), Jacobi (diag S) or none (plain CG)")
     ap.add_argument("--no-tune", action="store_true", help="skip the sub-batch autotuner")
+    ap.add_argument("--sub-batch", type=int, default=-1,
+                    help="slices per sub-batch instead of the autotuner's choice (0: all at once); "
+                         "profiler runs pin the unprofiled choice, since the profiler skews the trials")
     ap.add_argument("--workload", choices=("mri", "dense"), default="mri",
                     help="mri: the 256^2 CS-MRI benchmark (default); dense: 64^2 images measured by one "
                          "shared dense random projection (30%% of N rows), the MFMA path")
@@ -265,7 +268,11 @@ def main():
                       outer_tol=a.tau, eps=1e-10, precond=pc)
     x = torch.zeros_like(b)
     items = [dict(b=b[i], mask=m[i], x=x[i], lam=lams[i]) for i in range(B)]
-    chunk = solver.autotune(items) if not a.no_tune else 0
+    if a.sub_batch >= 0:
+        chunk = a.sub_batch
+        solver.set_chunk(chunk)
+    else:
+        chunk = solver.autotune(items) if not a.no_tune else 0
     use_learned = not a.no_learned and os.path.exists(a.weights) and n == 256
     net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4")) if use_learned else None
 
