@@ -335,20 +335,27 @@ hipEvent_t prof_event(firls_handle* h) {
   return h->ev_pool[h->ev_used++];
 }
 
-// Launch with optional timing; ``cls`` is a FIRLS_PROF_* class.
+struct TimingScope {   // launch_timing() set for one launcher call
+  TimingScope(hipEvent_t a, hipEvent_t b) { launch_timing() = {a, b}; }
+  ~TimingScope() { launch_timing() = {nullptr, nullptr}; }
+};
+
+// Launch with optional timing (the kernel's own start and end);
+// ``cls`` is a FIRLS_PROF_* class.
 #define KLAUNCH(h, cls, fn, P, grid, st)                                                \
   do {                                                                                  \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                              \
     if ((h)->profiling) {                                                               \
       a_ = prof_event(h);                                                               \
       b_ = prof_event(h);                                                               \
-      if (a_) (void)hipEventRecord(a_, (st));                                           \
+      if (!a_ || !b_) a_ = b_ = nullptr;                                                \
     }                                                                                   \
-    LAUNCH(fn, P, grid, st);                                                            \
-    if (a_ && b_) {                                                                     \
-      (void)hipEventRecord(b_, (st));                                                   \
+    {                                                                                   \
+      TimingScope ts_(a_, b_);                                                          \
+      LAUNCH(fn, P, grid, st);                                                          \
+    }                                                                                   \
+    if (a_ && b_)                                                                       \
       (h)->recs.push_back({(cls), (h)->ctx_group, (h)->ctx_it, (h)->ctx_phase, (h)->ctx_count, a_, b_}); \
-    }                                                                                   \
   } while (0)
 
 // Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.

@@ -70,9 +70,15 @@ __global__ __launch_bounds__(NT) void k_export_d(Params P) {
   if (u < P.shape.n_coef) out[u] = d[P.shape.perm[u]];
 }
 
+LaunchTiming& launch_timing() {
+  thread_local LaunchTiming t{nullptr, nullptr};
+  return t;
+}
+
 template <class K>
 hipError_t launch_static(K kern, const Params& P, dim3 g, hipStream_t st) {
-  hipLaunchKernelGGL(kern, g, dim3(NT), 0, st, P);
+  const LaunchTiming& t = launch_timing();
+  launch_kernel(kern, g, dim3(NT), 0, st, t.start, t.stop, P);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ constexpr size_t lds_col_bytes() {
 
 template <class K>
 hipError_t launch_dyn(K kern, size_t lds, const Params& P, dim3 g, hipStream_t st) {
-  hipLaunchKernelGGL(kern, g, dim3(NT), lds, st, P);
+  const LaunchTiming& t = launch_timing();
+  launch_kernel(kern, g, dim3(NT), lds, st, t.start, t.stop, P);
   return hipGetLastError();
 }
 

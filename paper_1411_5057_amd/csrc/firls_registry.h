@@ -1,9 +1,25 @@
 // Host-side tables of kernel launchers (internal).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include "firls_types.h"
 
 namespace firls {
+
+// Opt-in per-launch timing: while ``start`` is set (the handle's profiling
+// mode, one launcher call at a time on the calling thread), launches record
+// the kernel's own GPU start and end times in these events, the interval a
+// kernel trace reports, with no launch gap in it.
+struct LaunchTiming {
+  hipEvent_t start, stop;
+};
+LaunchTiming& launch_timing();
+
+template <class K, class... A>
+void launch_kernel(K kern, dim3 g, dim3 b, size_t lds, hipStream_t st, hipEvent_t start, hipEvent_t stop, A... args) {
+  if (start || stop) hipExtLaunchKernelGGL(kern, g, b, (uint32_t)lds, st, start, stop, 0u, args...);
+  else hipLaunchKernelGGL(kern, g, b, lds, st, args...);
+}
 
 using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
 

@@ -235,10 +235,14 @@ __global__ __launch_bounds__(NT) void k_gemm_reduce(Params P) {
 
 template <typename T, int MODE>
 hipError_t L_gemm(const Params& P, dim3 g, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm<T, MODE>), dim3(g.x, g.y, P.gsplit), dim3(NT), 0, st, P);
+  // with split-K the timed interval runs from the product's start to the
+  // reduction's end
+  const LaunchTiming& t = launch_timing();
+  const bool split = P.gsplit > 1;
+  launch_kernel(k_gemm<T, MODE>, dim3(g.x, g.y, P.gsplit), dim3(NT), 0, st, t.start, split ? nullptr : t.stop, P);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || P.gsplit <= 1) return e;
-  hipLaunchKernelGGL((k_gemm_reduce<T, MODE>), g, dim3(NT), 0, st, P);
+  if (e != hipSuccess || !split) return e;
+  launch_kernel(k_gemm_reduce<T, MODE>, g, dim3(NT), 0, st, nullptr, t.stop, P);
   return hipGetLastError();
 }
 
