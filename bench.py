@@ -51,7 +51,8 @@ def bytes_per_px(cls: str, K: int) -> float:
         "psi_sq": 12.0,        # read x; write |Phi x|^2 (TV only)
         "group_w": 10.0,       # read |z|^2 of members (~2 per group), write W
         "group_d": 12.0,       # read W of the groups of each coefficient (~2), write d
-        "r0_rowfwd": 20.0,     # read x; write t and |Phi x|^2
+        "r0_rowfwd": 36.0,     # read x, p; write x, t, d (x += alpha p of the last PCG step folded in;
+                               # the first evaluation of a slice skips p and the x write: 20)
         "r0_col": 25.0,        # read t, mask, b; write t
         "r0_rowinv": 28.0,     # read t, x, d; write r
         "r0_update": 12.0,     # read r, d (TV only)
@@ -136,11 +137,15 @@ def timed(solver, run, steps, warmup, profile, torch):
     return dt, out, prof
 
 
-def roofline_of(prof, n, K, dt):
+def roofline_of(prof, n, K, dt, slices):
     """Dominant PCG kernel by measured time: algorithmic bytes per launch
-    over its average HIP-event duration; plus the whole path's rate."""
+    over its average HIP-event duration; plus the whole path's rate.
+    ``slices`` solves of the instrumented step each start with one residual
+    pass that has no x update to fold in."""
     npx = n * n
     tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
+    if prof.get("r0_rowfwd", {}).get("launches", 0) and not prof.get("last_x", {}).get("launches", 0):
+        tot_bytes -= 16.0 * npx * slices
     pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update", "last_x")}
     dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
     v = prof[dom]
@@ -314,7 +319,7 @@ def main():
         out["weights"] = os.path.relpath(a.weights, ROOT)
     if prof:
         # the instrumented step does 1/steps of the timed work
-        out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps)
+        out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps, B)
         out["kernel_time_frac_of_instrumented_step"] = sum(v["ms"] for v in prof.values()) / 1e3 / dt_prof
     plain = None
     if use_learned:

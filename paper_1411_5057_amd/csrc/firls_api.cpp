@@ -433,6 +433,13 @@ int launch_dense_normal(firls_handle* h, const Shape& s, Params P, int c, hipStr
   return rc ? rc : launch_gemm(h, s, P, G_ATY, c, st, FIRLS_PROF_COL);
 }
 
+// The fused Haar PCG's closing x += alpha p rides in the next residual row
+// pass when that pass is the band-local weights pass (every PCG is followed
+// by a preparation: the stop test comes after the residual).
+bool fold_last_x(const firls_handle* h, const Shape& s) {
+  return s.psi == PSI_HAAR && h->cfg.precond == FIRLS_PC_PAPER && s.d_bgptr && !s.dense;
+}
+
 // Weights, residual and data term of the current x, then the objective
 // check (one outer iteration's preparation).
 int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStream_t st) {
@@ -449,8 +456,11 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
       KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
     }
   } else if (s.psi == PSI_HAAR && s.d_bgptr) {
-    // band-local groups: weights inside the residual's row pass
+    // band-local groups: weights inside the residual's row pass, which also
+    // applies the last PCG step's x update
     P.nreg = s.row_wgs();
+    P.fold_x = fold_last_x(h, s) ? 1 : 0;
+    P.k = h->cfg.pcg_iters - 1;
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQW_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
     KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
@@ -503,7 +513,7 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     if (haar && !fused) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar, P, rows, st);
     if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
   }
-  if (fused) {
+  if (fused && !fold_last_x(h, s)) {
     P.k = K - 1;
     KLAUNCH(h, FIRLS_PROF_LAST_X, s.sk->last_x, P, rows, st);
   }

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
       S.rho = D.rho_fixed;
       S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
       S.active = 1;
-      S.outer = S.pcg = S.status = S.converged = S.evals = 0;
+      S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
     }
     return;
   }
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
     S.rho = cnt / (double)total;
     S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
     S.active = 1;
-    S.outer = S.pcg = S.status = S.converged = S.evals = 0;
+    S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
   }
 }
 

@@ -141,6 +141,9 @@ __device__ __forceinline__ void outer_check_wg(const Params& P, int s, double* r
     S.outer += 1;
     S.pcg += P.K;
   }
+  // a slice that goes on runs K PCG iterations, whose last x += alpha p the
+  // next residual pass applies
+  if (P.fold_x) S.pend = S.active;
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -196,7 +199,17 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     // partials, then d = diag(G^T W G) of the band's coefficients (eq. 13),
     // all on chip; x stays in registers meanwhile and then goes through the
     // same LDS for the row FFTs.
-    const C* x = static_cast<const C*>(D.x) + off;
+    // With fold_x a pending x += alpha p of the last PCG iteration (alpha
+    // from its <r,z> and <p,q> sums) is applied first and x written back.
+    C* x = static_cast<C*>(D.x) + off;
+    const bool pend = P.fold_x && P.state[s_].pend;
+    T al = (T)0;
+    if (pend) {
+      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
+      const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+      al = (T)(pq > 0.0 ? rz / pq : 0.0);
+    }
+    const C* p = static_cast<const C*>(D.p) + off;
     T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
     T* WL = sqL + ROWS * N;                         // the band's groups
     C xv[U::PER][16];
@@ -204,9 +217,18 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     for (int k = 0; k < U::PER; ++k) {
       if (!U::valid(k)) continue;
       const int col = U::col(k), row = U::row(k);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) xv[k][s] = x[(row + s) * N + col];
+      if (pend) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          xv[k][s] = xv[k][s] + p[(row + s) * N + col] * al;
+          x[(row + s) * N + col] = xv[k][s];
+        }
+      }
       C v[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) v[s] = xv[k][s] = x[(row + s) * N + col];
+      for (int s = 0; s < 16; ++s) v[s] = xv[k][s];
       haar_col<false>(v, P.L, col);
 #pragma unroll
       for (int s = 0; s < 16; ++s) sqL[(row + s) * N + col] = (T)cabs2(v[s]);

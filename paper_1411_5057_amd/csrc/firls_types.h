@@ -93,6 +93,8 @@ struct SliceState {
   int32_t status;    // 0, FIRLS_W_MAXITER, FIRLS_E_NONFINITE
   int32_t converged;
   int32_t evals;     // objective evaluations done
+  int32_t pend;      // x += alpha p of the last PCG iteration not yet applied
+                     // (folded into the next residual row pass)
 };
 
 // Group map of one shape on the device (internal coefficient indices).
@@ -129,6 +131,7 @@ struct Params {
   int32_t n;
   int32_t L;             // Haar levels
   int32_t k;             // PCG iteration index
+  int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
   int32_t K;             // PCG iterations per outer iteration
   int32_t Tmax;
   int32_t precond;
