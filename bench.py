@@ -41,7 +41,12 @@ HBM_PEAK_GBS = 8000.0
 #   col    : read t, mask bits; write t
 #   rowinv : read t, p, d; write q
 #   update : read x, p, q, r, d; write x, r
-def bytes_per_px(cls: str, K: int) -> float:
+def bytes_per_px(cls: str, K: int, fused: bool = True) -> float:
+    """Algorithmic HBM bytes per pixel of one launch of a kernel class.
+    ``fused``: the paper's preconditioner, whose residual passes also carry
+    the last PCG step's x update and the first one's z0, p0 and row FFT."""
+    if not fused and cls in ("r0_rowfwd", "r0_rowinv"):
+        return {"r0_rowfwd": 20.0, "r0_rowinv": 28.0}[cls]
     return {
         "rowfwd": 28.0,        # first iteration: read r, d; write p, t
         "col": 16.125,         # read t, mask bits; write t
@@ -54,7 +59,7 @@ def bytes_per_px(cls: str, K: int) -> float:
         "r0_rowfwd": 36.0,     # read x, p; write x, t, d (x += alpha p of the last PCG step folded in;
                                # the first evaluation of a slice skips p and the x write: 20)
         "r0_col": 25.0,        # read t, mask, b; write t
-        "r0_rowinv": 28.0,     # read t, x, d; write r
+        "r0_rowinv": 44.0,     # read t, x, d; write r, p0 and t (z0, p0 and its row FFT folded in)
         "r0_update": 12.0,     # read r, d (TV only)
         "adjoint": 33.0,       # read b, mask; write t; read t; write x
     }.get(cls, 0.0)
@@ -137,19 +142,19 @@ def timed(solver, run, steps, warmup, profile, torch):
     return dt, out, prof
 
 
-def roofline_of(prof, n, K, dt, slices):
+def roofline_of(prof, n, K, dt, slices, fused=True):
     """Dominant PCG kernel by measured time: algorithmic bytes per launch
     over its average HIP-event duration; plus the whole path's rate.
     ``slices`` solves of the instrumented step each start with one residual
     pass that has no x update to fold in."""
     npx = n * n
-    tot_bytes = sum(bytes_per_px(c, K) * v["slice_launches"] * npx for c, v in prof.items())
+    tot_bytes = sum(bytes_per_px(c, K, fused) * v["slice_launches"] * npx for c, v in prof.items())
     if prof.get("r0_rowfwd", {}).get("launches", 0) and not prof.get("last_x", {}).get("launches", 0):
         tot_bytes -= 16.0 * npx * slices
     pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update", "last_x")}
     dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
     v = prof[dom]
-    per_launch_bytes = bytes_per_px(dom, K) * npx * v["slice_launches"] / v["launches"]
+    per_launch_bytes = bytes_per_px(dom, K, fused) * npx * v["slice_launches"] / v["launches"]
     avg_s = v["ms"] / v["launches"] / 1e3
     ach = per_launch_bytes / avg_s / 1e9
     tr = traffic_record()
@@ -319,7 +324,7 @@ def main():
         out["weights"] = os.path.relpath(a.weights, ROOT)
     if prof:
         # the instrumented step does 1/steps of the timed work
-        out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps, B)
+        out["roofline"], out["hbm_gbs_algorithmic"], out["kernel_ms"] = roofline_of(prof, n, K, dt / a.steps, B, a.precond == "paper")
         out["kernel_time_frac_of_instrumented_step"] = sum(v["ms"] for v in prof.values()) / 1e3 / dt_prof
     plain = None
     if use_learned:

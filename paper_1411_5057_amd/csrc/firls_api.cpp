@@ -440,12 +440,20 @@ bool fold_last_x(const firls_handle* h, const Shape& s) {
   return s.psi == PSI_HAAR && h->cfg.precond == FIRLS_PC_PAPER && s.d_bgptr && !s.dense;
 }
 
+// With the paper's preconditioner and the FFT operator, the residual's
+// row-inverse pass also forms z0, p0 = z0 and the row FFTs of p0, which is
+// all the first PCG iteration's row pass would do.
+bool p0_in_prep(const firls_handle* h, const Shape& s) {
+  return s.psi == PSI_HAAR && h->cfg.precond == FIRLS_PC_PAPER && !s.dense;
+}
+
 // Weights, residual and data term of the current x, then the objective
 // check (one outer iteration's preparation).
 int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const dim3 rows(s.row_wgs(), c);
   Params P = P0;
+  P.p0_prep = p0_in_prep(h, s) ? 1 : 0;
   if (s.dense) {
     int rc = launch_weights(h, s, P, c, st);
     if (rc || (rc = launch_dense_residual(h, s, P, c, st))) return rc;
@@ -496,8 +504,8 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
   for (int k = 0; k < K; ++k) {
     P.k = k;
     if (fused) {
-      if (k == 0) KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
-      else KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
+      if (k > 0) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
+      else if (!p0_in_prep(h, s)) KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
     } else if (haar) {
       KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
     } else {

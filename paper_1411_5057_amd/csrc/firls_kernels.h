@@ -68,6 +68,20 @@ __device__ __forceinline__ size_t t_index(int row, int col) {
 //   PC_PAPER : Phi^T ((Phi v) / (rho + lambda d))                 (eq. 17)
 //   PC_JACOBI: v / (rho + lambda diag(Phi^T diag(d) Phi))         (diag of S)
 //   PC_NONE  : v                                                  (plain CG)
+// The paper's preconditioner with the 16 weights d already in registers.
+template <bool NEED_Z, typename T>
+__device__ __forceinline__ void precond_tile_paper(cplx<T> (&v)[16], const T (&dv)[16], int L, int col, T rho,
+                                                   T lam, double& acc) {
+  haar_col<false>(v, L, col);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const T iv = pc_inv(rho + lam * dv[s]);
+    acc += (double)(cabs2t(v[s]) * iv);
+    if (NEED_Z) v[s] = v[s] * iv;
+  }
+  if (NEED_Z) haar_col<true>(v, L, col);
+}
+
 template <bool NEED_Z, int N, int PC, typename T>
 __device__ __forceinline__ void precond_tile_k(cplx<T> (&v)[16], const T* dg, int L, int col, T rho, T lam,
                                                double& acc) {
@@ -521,14 +535,18 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
         if (!U::valid(k)) continue;
         const int col = U::col(k), row = U::row(k);
         C w[16];
+        T dv[16];   // read once: the regulariser and the preconditioner both use it
         // <p, S p> = ||A p||^2 + lambda sum d |Phi p|^2: the first part
         // comes from the column pass, the second is summed here
 #pragma unroll
-        for (int s = 0; s < 16; ++s) w[s] = v[(row + s) * N + col];
+        for (int s = 0; s < 16; ++s) {
+          w[s] = v[(row + s) * N + col];
+          dv[s] = d[(row + s) * N + col];
+        }
         haar_col<false>(w, P.L, col);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-          const T ld = lam * d[(row + s) * N + col];
+          const T ld = lam * dv[s];
           if (SP) acc += (double)(ld * cabs2t(w[s]));
           w[s] = w[s] * (ld * sgn);
         }
@@ -542,13 +560,29 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
         // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
         if constexpr (SP) {
           // only the fused step (paper's preconditioner) uses <q, P^{-1} q>
-          if (P.precond == PC_PAPER) precond_tile_k<false, N, PC_PAPER>(w, d + row * N + col, P.L, col, rho, lam, acc2);
+          if (P.precond == PC_PAPER) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
+        } else if (P.p0_prep) {
+          // the first PCG iteration's start: z0 = P^{-1} r0, p0 = z0, whose
+          // row FFTs follow from this thread's own LDS cells (already read)
+          precond_tile_paper<true>(w, dv, P.L, col, rho, lam, acc2);
+          C* p = static_cast<C*>(D.p) + off;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            p[(row + s) * N + col] = w[s];
+            lds[Lay::at(row + s, col)] = w[s];
+          }
         } else {
           precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
         }
       }
       const double t2 = block_sum(acc2, red);
       if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
+      if (!SP && P.p0_prep) {
+        __syncthreads();
+        C* tout = static_cast<C*>(D.t);
+        fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
+                                             [&](int l, int q, C val) { tout[t_index<T, N>(row0 + l, q)] = val; });
+      }
     } else {
       // this band's contrast: its image, its D1 weights and its D2 weights
       const int ch = row0 / N, lrow0 = row0 - ch * N;
