@@ -265,11 +265,32 @@ __device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src s
 // the first inverse stage (same radix, no twiddles), so the spectrum stays
 // in registers between the two transforms: one LDS round trip and two
 // barriers fewer than two fft_lines calls.
+// Which spectrum positions this thread holds between the two transforms:
+// its i-th butterfly (i < ITER) is (line, j) and holds positions
+// j + r NBL, r < RL.
+template <typename T, int N, int LINES, int MAP>
+struct FwdInvMap {
+  using P = Plan<N>;
+  static constexpr int RL = P::S == 3 ? P::R2 : (P::S == 2 ? P::R1 : P::R0);
+  static constexpr int NBL = N / RL;
+  using L = Stage<T, N, RL, NBL, LINES, MAP, false>;
+  static constexpr int ITER = L::ITER;
+  __device__ __forceinline__ static bool at(int i, int& line, int& j) {
+    const int b = threadIdx.x + i * NT;
+    if (L::TOT % NT != 0 && b >= L::TOT) return false;
+    L::decode(b, line, j);
+    return true;
+  }
+};
+
+// ``mid(i, r, line, pos, v)`` gets the spectrum value v at (line, pos), the
+// r-th value of this thread's i-th butterfly (FwdInvMap).
 template <typename T, int N, int LINES, int MAP, class Src, class Mid, class Dst>
 __device__ __forceinline__ void fft_lines_fwd_inv(cplx<T>* lds, const cplx<T>* tw, Src src, Mid mid, Dst dst) {
   using P = Plan<N>;
-  constexpr int RL = P::S == 3 ? P::R2 : (P::S == 2 ? P::R1 : P::R0);
-  constexpr int NBL = N / RL;
+  using Map = FwdInvMap<T, N, LINES, MAP>;
+  constexpr int RL = Map::RL;
+  constexpr int NBL = Map::NBL;
   LdsIO<T, N> io{lds};
   using L = Stage<T, N, RL, NBL, LINES, MAP, false>;    // last forward stage
   using I0 = Stage<T, N, RL, 1, LINES, MAP, true>;      // first inverse stage
@@ -297,12 +318,10 @@ __device__ __forceinline__ void fft_lines_fwd_inv(cplx<T>* lds, const cplx<T>* t
   }
 #pragma unroll
   for (int i = 0; i < L::ITER; ++i) {
-    const int b = threadIdx.x + i * NT;
-    if (L::TOT % NT != 0 && b >= L::TOT) continue;
     int line, j;
-    L::decode(b, line, j);
+    if (!Map::at(i, line, j)) continue;
 #pragma unroll
-    for (int r = 0; r < RL; ++r) v[i][r] = mid(line, j + r * NBL, v[i][r]);
+    for (int r = 0; r < RL; ++r) v[i][r] = mid(i, r, line, j + r * NBL, v[i][r]);
     SmallDFT<T, RL, true>::run(v[i]);
   }
   if constexpr (P::S == 1) {

@@ -431,21 +431,34 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
   auto gdst = [&](int c, int row, C v) { t[row * COLS + c] = v; };
   const T sn = (T)1 / (T)N;
   // the spectrum passes from the forward to the inverse column FFT in
-  // registers (fft_lines_fwd_inv); the partial sums of a mode are complete
-  // once the inverse has started, and are summed after it
+  // registers (fft_lines_fwd_inv); the mask bits of the positions this
+  // thread will hold are fetched first, so no load waits between the
+  // transforms; the partial sums of a mode are complete once the inverse
+  // has started, and are summed after it
+  using Map = FwdInvMap<T, N, COLS, COLMAP>;
+  uint32_t mine[Map::ITER];   // bit r: position r of butterfly i sampled
+#pragma unroll
+  for (int i = 0; i < Map::ITER; ++i) {
+    int c, j;
+    mine[i] = 0u;
+    if (!Map::at(i, c, j)) continue;
+#pragma unroll
+    for (int r = 0; r < Map::RL; ++r) mine[i] |= (uint32_t)sampled(c, j + r * Map::NBL) << r;
+  }
+  auto smp = [&](int i, int r) { return (mine[i] >> r) & 1u; };
   if constexpr (MODE == COL_SP) {
     const T sc = sn * sn;
-    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
-      return sampled(c, row) ? v * sc : C{(T)0, (T)0};
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int i, int r, int c, int row, C v) {
+      return smp(i, r) ? v * sc : C{(T)0, (T)0};
     }, gdst);
   } else if constexpr (MODE == COL_SP_PQ) {
     // as COL_SP, and the partials of <p, A^H A p> = ||m F p||^2 / n^2 go to
     // the <p, S p> slot after the row pass's partials
     const T sc = sn * sn;
     double acc = 0.0;
-    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int i, int r, int c, int row, C v) {
       C u{(T)0, (T)0};
-      if (sampled(c, row)) {
+      if (smp(i, r)) {
         acc += (double)(cabs2t(v) * sc);
         u = v * sc;
       }
@@ -458,10 +471,10 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     // and accumulate 1/2 ||m F x - b||^2.
     const C* b = static_cast<const C*>(D.b);
     double acc = 0.0;
-    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int i, int r, int c, int row, C v) {
       const size_t g = (size_t)(ch * N + row) * N + col0 + c;
       C u{(T)0, (T)0};
-      if (sampled(c, row)) {
+      if (smp(i, r)) {
         u = b[g] - v * sn;
         acc += cabs2(u);
         u = u * sn;
@@ -474,9 +487,9 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     // data consistency: keep F x where unsampled, put b where sampled
     // (k = m b + (1 - m) F x), then the column inverse with 1/n
     const C* b = static_cast<const C*>(D.b);
-    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int c, int row, C v) {
+    fft_lines_fwd_inv<T, N, COLS, COLMAP>(lds, tw, gsrc, [&](int i, int r, int c, int row, C v) {
       const size_t g = (size_t)(ch * N + row) * N + col0 + c;
-      return (sampled(c, row) ? b[g] : v * sn) * sn;
+      return (smp(i, r) ? b[g] : v * sn) * sn;
     }, gdst);
   } else {
     const C* b = static_cast<const C*>(D.b);
