@@ -196,7 +196,9 @@ int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_r
 /* Many independent slices of any configured shapes in one call; slices of
  * the same shape share every launch, converged slices drop out at outer
  * iteration boundaries.  reports[i] belongs to slices[i].  Returns the
- * worst status (error < 0 first, else the largest warning). */
+ * worst status (error < 0 first, else the largest warning);
+ * FIRLS_E_INVALID for n_slices <= 0 or more than the handle's max_slices
+ * in one sub-batch, before any work. */
 int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices,
                         const firls_slice* slices, firls_report* reports);
 

@@ -359,13 +359,15 @@ struct TimingScope {   // launch_timing() set for one launcher call
   } while (0)
 
 // Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.
-int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st) {
+// ``penalty_only``: W and the penalty partials, without d (enough for F_eps).
+int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st,
+                   bool penalty_only = false) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int C = strip_cols(h->fp64);
   if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.row_wgs(), c), st);
   else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3(((int)s.pixels() + 4 * NT - 1) / (4 * NT), c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
-  KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
+  if (!penalty_only)
+    KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
   return FIRLS_OK;
 }
 
@@ -1105,6 +1107,8 @@ int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_r
 int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices,
                         firls_report* reports) {
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  if (n_slices <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
+  if (!slices || !reports) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
   g_err.clear();
   return run_batch(h, (hipStream_t)stream, n_slices, slices, reports, h->cfg.max_outer, h->cfg.outer_tol);
 }
@@ -1372,7 +1376,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
       // the penalty: no Fourier pass is needed.
       P.no_data = 1;
       LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
-      int r2 = launch_weights(h, S, P, c, st);
+      int r2 = launch_weights(h, S, P, c, st, true);
       if (r2) return r2;
       LAUNCH(prec_kernels(false)->outer_check, P, dim3(c), st);
     }
