@@ -513,11 +513,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Sum of ``count`` partials of a slot, in a fixed order.
-__device__ __forceinline__ double slot_sum(const double* slot, int count, double* red) {
+// Sum of ``count`` partials of a slot, in a fixed order, formed by every
+// wave on its own (lane l adds partials l, l + 64, ..., then a butterfly):
+// no barrier, and every wave of every workgroup gets the same bits.
+__device__ __forceinline__ double slot_sum(const double* slot, int count) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < count; i += NT) v += slot[i];
-  return block_sum(v, red);
+  for (int i = threadIdx.x & 63; i < count; i += 64) v += slot[i];
+  return wave_sum(v);
 }
 
 __device__ __forceinline__ const double* slot_ptr(const SliceDesc& D, int s) { return D.parts + (size_t)s * PMAX; }

@@ -128,9 +128,9 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
 __device__ __forceinline__ void outer_check_wg(const Params& P, int s, double* red) {
   SliceState& S = P.state[s];
   const SliceDesc& D = P.desc[s];
-  const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata, red);
-  const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg, red);
-  const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg, red);
+  const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata);
+  const double re = slot_sum(slot_ptr(D, SLOT_REG_EPS), P.nreg);
+  const double r0 = slot_sum(slot_ptr(D, SLOT_REG0), P.nreg);
   if (threadIdx.x != 0) return;
   const double Fe = data + D.lambda * re;
   const double F = data + D.lambda * r0;
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     const bool pend = P.fold_x && P.state[s_].pend;
     T al = (T)0;
     if (pend) {
-      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-      const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
+      const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
       al = (T)(pq > 0.0 ? rz / pq : 0.0);
     }
     const C* p = static_cast<const C*>(D.p) + off;
@@ -323,8 +323,8 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   } else {
     double beta = 0.0;
     if (MODE != RF_STEP_HAAR && P.k > 0) {
-      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz, red);
+      const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
+      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz);
       beta = rzo > 0.0 ? rz / rzo : 0.0;
     }
     const T bt = (T)beta;
@@ -332,9 +332,9 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     if constexpr (MODE == RF_STEP_HAAR) {
       // end of iteration k - 1 (alpha, x, r, <r_k, z_k>) and start of
       // iteration k (z_k, p_k = z_k + beta p_{k-1}) in one pass
-      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz, red);
-      const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq, red);
-      const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz, red);
+      const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz);
+      const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq);
+      const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz);
       const double ald = pqo > 0.0 ? rzo / pqo : 0.0;
       const double rzn = ald * ald * qqo - rzo;
       const T al = (T)ald;
@@ -660,8 +660,8 @@ __global__ __launch_bounds__(NT) void k_update_haar(Params P) {
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
-  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
+  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
   const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
   C* x = static_cast<C*>(D.x) + off;
   C* r = static_cast<C*>(D.r[0]) + off;
@@ -696,8 +696,8 @@ __global__ __launch_bounds__(NT) void k_last_x(Params P) {
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
-  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+  const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
+  const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
   const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
@@ -810,8 +810,8 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   const T* d2 = static_cast<const T*>(D.d) + (size_t)P.C * n * n + cb;
   T al = (T)0;
   if constexpr (MODE != UP_INIT) {
-    const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz, red);
-    const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq, red);
+    const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
+    const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
     al = (T)(pq > 0.0 ? rz / pq : 0.0);
   }
   const C* q = static_cast<const C*>(D.q) + cb;
