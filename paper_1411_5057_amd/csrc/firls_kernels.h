@@ -234,9 +234,12 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
 #pragma unroll
       for (int s = 0; s < 16; ++s) xv[k][s] = x[(row + s) * N + col];
       if (pend) {
+        C pv[16];   // all loads before the first store (see the update step)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) pv[s] = p[(row + s) * N + col];
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-          xv[k][s] = xv[k][s] + p[(row + s) * N + col] * al;
+          xv[k][s] = xv[k][s] + pv[s] * al;
           x[(row + s) * N + col] = xv[k][s];
         }
       }
@@ -350,15 +353,30 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         if (!U::valid(k)) continue;
         const int col = U::col(k), row = U::row(k);
         C v[16];
-        // p_{k-1} waits in this thread's own LDS cells until beta p is added
+        // p_{k-1} waits in this thread's own LDS cells until beta p is added.
+        // Loads go ahead of the stores in chunks: the compiler cannot prove
+        // that x, r, p and q do not overlap, so it keeps every load after
+        // the stores before it.
+        constexpr int CH = 8;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int g = (row + s) * N + col;
-          const C po = p[g];
-          lds[Lay::at(row + s, col)] = po;
-          x[g] = x[g] + po * al;
-          v[s] = r[g] - q[g] * al;
-          r[g] = v[s];
+        for (int s0 = 0; s0 < 16; s0 += CH) {
+          C po[CH], xo[CH], qo[CH];
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int g = (row + s0 + u) * N + col;
+            po[u] = p[g];
+            xo[u] = x[g];
+            v[s0 + u] = r[g];
+            qo[u] = q[g];
+          }
+#pragma unroll
+          for (int u = 0; u < CH; ++u) {
+            const int g = (row + s0 + u) * N + col;
+            lds[Lay::at(row + s0 + u, col)] = po[u];
+            x[g] = xo[u] + po[u] * al;
+            v[s0 + u] = v[s0 + u] - qo[u] * al;
+            r[g] = v[s0 + u];
+          }
         }
         precond_tile_k<true, N, PC_PAPER>(v, d + row * N + col, P.L, col, rhot, lam, acc);
 #pragma unroll
@@ -385,11 +403,13 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         for (int s = 0; s < 16; ++s) v[s] = r[(row + s) * N + col];
         double unused = 0.0;
         precond_tile<true, N>(v, d + row * N + col, P.L, col, rho, lam, P.precond, unused);
+        C po[16];   // p is not read at k = 0; its loads go before the stores
+#pragma unroll
+        for (int s = 0; s < 16; ++s) po[s] = P.k > 0 ? p[(row + s) * N + col] : C{(T)0, (T)0};
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-          const int g = (row + s) * N + col;
-          const C pn = P.k > 0 ? v[s] + p[g] * bt : v[s];   // p is not read at k = 0
-          p[g] = pn;
+          const C pn = P.k > 0 ? v[s] + po[s] * bt : v[s];
+          p[(row + s) * N + col] = pn;
           lds[Lay::at(row + s, col)] = pn;
         }
       }
@@ -675,12 +695,25 @@ __global__ __launch_bounds__(NT) void k_update_haar(Params P) {
     if (!U::valid(k)) continue;
     const int col = U::col(k), row = U::row(k);
     C v[16];
+    constexpr int CH = 8;   // loads ahead of stores, as in the fused step
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int g = (row + s) * N + col;
-      x[g] = x[g] + p[g] * al;
-      v[s] = r[g] - q[g] * al;
-      r[g] = v[s];
+    for (int s0 = 0; s0 < 16; s0 += CH) {
+      C xo[CH], po[CH], qo[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int g = (row + s0 + u) * N + col;
+        xo[u] = x[g];
+        po[u] = p[g];
+        v[s0 + u] = r[g];
+        qo[u] = q[g];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int g = (row + s0 + u) * N + col;
+        x[g] = xo[u] + po[u] * al;
+        v[s0 + u] = v[s0 + u] - qo[u] * al;
+        r[g] = v[s0 + u];
+      }
     }
     precond_tile<false, N>(v, d + row * N + col, P.L, col, rho, lam, P.precond, acc);
   }
@@ -701,7 +734,23 @@ __global__ __launch_bounds__(NT) void k_last_x(Params P) {
   const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
-  for (int i = threadIdx.x; i < ROWS * N; i += NT) x[i] = x[i] + p[i] * al;
+  // E elements per thread, CH at a time with their loads ahead of their
+  // stores (a band always holds a multiple of NT pixels)
+  constexpr int TOT = ROWS * N, E = TOT / NT;
+  static_assert(TOT % NT == 0, "band not a multiple of the workgroup");
+  constexpr int CH = E % 8 == 0 ? 8 : (E % 4 == 0 ? 4 : (E % 3 == 0 ? 3 : 1));
+#pragma unroll
+  for (int e0 = 0; e0 < E; e0 += CH) {
+    C xv[CH], pv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = threadIdx.x + (e0 + u) * NT;
+      xv[u] = x[i];
+      pv[u] = p[i];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) x[threadIdx.x + (e0 + u) * NT] = xv[u] + pv[u] * al;
+  }
 }
 
 // ---------------------------------------------------------------------------
