@@ -456,6 +456,9 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
   const dim3 rows(s.row_wgs(), c);
   Params P = P0;
   P.p0_prep = p0_in_prep(h, s) ? 1 : 0;
+  // Haar: the residual's row-inverse pass, the last of the preparation,
+  // also runs the stop test (TV keeps its own launch after the z0 pass)
+  P.check_r0 = s.psi == PSI_HAAR ? 1 : 0;
   if (s.dense) {
     int rc = launch_weights(h, s, P, c, st);
     if (rc || (rc = launch_dense_residual(h, s, P, c, st))) return rc;
@@ -488,7 +491,7 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
     KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
   }
-  KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
+  if (!P.check_r0) KLAUNCH(h, FIRLS_PROF_CHECK, pk->outer_check, P, dim3(c), st);
   return FIRLS_OK;
 }
 

@@ -53,10 +53,9 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
 // after the first evaluation, or once Tmax solves are done; otherwise count
 // the solve that follows.
 __global__ __launch_bounds__(NT) void k_outer_check(Params P) {
-  __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
   if (!P.state[s].active) return;
-  outer_check_wg(P, s, red);
+  outer_check_wg(P, s);
 }
 
 // d in the caller's coefficient order: out[u] = d[perm[u]].

@@ -125,7 +125,7 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
 // sum sqrt(s_g + eps); stop when (F_eps^{prev} - F_eps) <= tau F_eps after
 // the first evaluation, or once Tmax solves are done; otherwise count the
 // solve that follows.
-__device__ __forceinline__ void outer_check_wg(const Params& P, int s, double* red) {
+__device__ __forceinline__ void outer_check_wg(const Params& P, int s) {
   SliceState& S = P.state[s];
   const SliceDesc& D = P.desc[s];
   const double data = P.no_data ? 0.0 : slot_sum(slot_ptr(D, SLOT_DATA), P.ndata);
@@ -549,6 +549,10 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
     const T lam = (T)D.lambda;
     const T sgn = SP ? (T)1 : (T)-1;
     double acc = 0.0;
+    // the objective and stop test of this outer iteration (every partial it
+    // needs is complete before this pass): the slice's first workgroup runs
+    // it; a stopped slice's workgroups that start later just exit
+    if (!SP && P.check_r0 && blockIdx.x == 0) outer_check_wg(P, s_);
     if constexpr (HAAR) {
       // A^H A part into LDS (row inverse FFT, or with a dense sensing matrix
       // the product A^T A v in t, row-major), then lambda Phi^T (d * Phi v)

@@ -133,6 +133,7 @@ struct Params {
   int32_t k;             // PCG iteration index
   int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
   int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs
+  int32_t check_r0;      // ... and its first workgroup runs the outer check (Haar)
   int32_t K;             // PCG iterations per outer iteration
   int32_t Tmax;
   int32_t precond;
