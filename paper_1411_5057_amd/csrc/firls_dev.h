@@ -375,9 +375,33 @@ __device__ __forceinline__ void fft_lines_fwd_inv(cplx<T>* lds, const cplx<T>* t
 // lane ^ st through cross-lane shuffles.  The library's coefficient layout
 // (weights d, |Psi x|^2) is this in-place layout.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ cplx<T> shfl_xor_c(cplx<T> v, int m) {
-  return cplx<T>{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+// The value of lane ^ ST (ST = 1, 2, 4 or 8: inside a row of 16 lanes)
+// through DPP moves instead of an LDS permute: quad_perm [1,0,3,2] and
+// [2,3,0,1] for 1 and 2, row_ror:8 for 8, and for 4 the lane takes
+// row_ror:12 (lane + 4) or row_ror:4 (lane - 4) by its bit 2.
+template <int ST>
+__device__ __forceinline__ int xor_lane_i(int x) {
+  static_assert(ST == 1 || ST == 2 || ST == 4 || ST == 8, "stride inside a DPP row");
+  if constexpr (ST == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+  else if constexpr (ST == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+  else if constexpr (ST == 8) return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+  else {
+    const int up = __builtin_amdgcn_update_dpp(0, x, 0x12C, 0xF, 0xF, false);
+    const int dn = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);
+    return (threadIdx.x & 4) ? dn : up;
+  }
+}
+template <int ST>
+__device__ __forceinline__ float xor_lane(float v) { return __int_as_float(xor_lane_i<ST>(__float_as_int(v))); }
+template <int ST>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane_i<ST>((int)(b & 0xFFFFFFFFll)), hi = xor_lane_i<ST>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <int ST, typename T>
+__device__ __forceinline__ cplx<T> xor_lane_c(cplx<T> v) {
+  return cplx<T>{xor_lane<ST>(v.x), xor_lane<ST>(v.y)};
 }
 
 template <int ST, typename T>
@@ -389,8 +413,8 @@ __device__ __forceinline__ void haar_level(cplx<T> (&v)[16], int col) {
   for (int s = 0; s < 16; s += 2 * ST) {
     const cplx<T> S = v[s] + v[s + ST];
     const cplx<T> D = v[s] - v[s + ST];
-    const cplx<T> So = shfl_xor_c(S, ST);
-    const cplx<T> Do = shfl_xor_c(D, ST);
+    const cplx<T> So = xor_lane_c<ST>(S);
+    const cplx<T> Do = xor_lane_c<ST>(D);
     if (active) {
       v[s] = (right ? So - S : S + So) * h;
       v[s + ST] = (right ? Do - D : D + Do) * h;
@@ -424,7 +448,7 @@ __device__ __forceinline__ void haar_diag_level(T (&v)[16], int col) {
 #pragma unroll
   for (int s = 0; s < 16; s += 2 * ST) {
     const T S = v[s] + v[s + ST];
-    const T So = __shfl_xor(S, ST, 64);
+    const T So = xor_lane<ST>(S);
     if (active) v[s] = v[s + ST] = (S + So) * (T)0.25;
   }
 }
