@@ -517,10 +517,29 @@ __device__ __forceinline__ void group_weight(double s2, double eps, double& w, d
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions.
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes; every lane gets the same bits: pairs inside rows
+// of 16 lanes through DPP (lane ^ 1, 2, 4, 8), then lane ^ 16 through a
+// swizzle, then lane 0's and lane 32's halves read as scalars and added in
+// one order.
+__device__ __forceinline__ double swizzle_xor16(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xFFFFFFFFll), (16 << 10) | 0x1F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), (16 << 10) | 0x1F);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += xor_lane<1>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<4>(v);
+  v += xor_lane<8>(v);
+  v += swizzle_xor16(v);
+  return read_lane(v, 0) + read_lane(v, 32);
 }
 
 // Sum over the workgroup; every thread gets the result.  ``red`` is a
