@@ -795,7 +795,7 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
     s.M = in.m;
     s.Mp = (in.m + GEMM_BM - 1) / GEMM_BM * GEMM_BM;
     if (s.Mp / GEMM_BM > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many measurements (m > 32768)");
-    if (N % GEMM_BM) return fail(FIRLS_E_UNSUPPORTED, "n^2 must be a multiple of 64");
+    if (N % GEMM_BM) return fail(FIRLS_E_UNSUPPORTED, "n^2 must be a multiple of " + std::to_string(GEMM_BM));
     double fro = 0.0;
     for (size_t i = 0; i < (size_t)s.M * N; ++i) fro += in.A[i] * in.A[i];
     s.rho_A = fro / (double)N;

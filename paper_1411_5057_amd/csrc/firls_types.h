@@ -48,7 +48,7 @@ enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
 //   G_AP    y = A p              (+ partials of ||A p||^2 = <p, A^T A p>)
 //   G_ATY   t = A^T y
 enum GemmMode : int { G_ATB = 0, G_AX_R0 = 1, G_AP = 2, G_ATY = 3 };
-constexpr int GEMM_BM = 64;      // rows per workgroup tile
+constexpr int GEMM_BM = 128;     // rows per workgroup tile
 constexpr int GEMM_BS = 32;      // slices (64 real columns) per workgroup tile
 constexpr int GEMM_BK = 32;      // depth of one LDS stage of the GEMM
 

@@ -6,7 +6,7 @@
 // imaginary parts of slice j are columns 2j and 2j+1 of the right operand,
 // read in place from the slice's own vector (x, p, y or b).  Tiles of
 // GEMM_BM rows x 64 columns run on MFMA (FP32: v_mfma_f32_16x16x4f32, FP64:
-// v_mfma_f64_16x16x4f64), four waves of 32 x 32, with 32-deep slices of both
+// v_mfma_f64_16x16x4f64), four waves of GEMM_BM/2 x 32, with 32-deep slices of both
 // operands staged in LDS and the next slices fetched meanwhile.  Per-slice
 // partial sums (data term, ||A p||^2) are reduced in a fixed order: one
 // partial per row tile.
@@ -38,11 +38,17 @@ template <> struct Mfma<double> {
 
 constexpr int BK = GEMM_BK;     // depth of one LDS stage
 constexpr int BN = 2 * GEMM_BS; // real columns per tile
-constexpr int PAD = 4;
+constexpr int MI = GEMM_BM / 32;   // 16-row MFMA tiles per wave (two waves share the rows)
+constexpr int WR = GEMM_BM / 2;    // rows per wave
+constexpr int NI = BN / 32;        // 16-column MFMA tiles per wave (two waves share the columns)
+constexpr int WC = BN / 2;         // columns per wave
+// LDS row padding: a stride of 16 banks (mod 32) puts the four k rows one
+// MFMA operand read touches on disjoint banks
+constexpr int PAD = 16;
 
 }  // namespace
 
-// Epilogue of one 64 x 64 output tile: thread (wave, lane) owns the MFMA
+// Epilogue of one GEMM_BM x 64 output tile: thread (wave, lane) owns the MFMA
 // output positions (mi, ni, r); ``val(mi, ni, r)`` gives the finished sum.
 // Scatters to the slices' vectors and, for G_AX_R0 / G_AP, writes one
 // per-slice partial of the squares (fixed reduction order).
@@ -52,11 +58,13 @@ __device__ __forceinline__ void gemm_epilogue(const Params& P, int row0, int j0,
   using M = Mfma<T>;
   constexpr bool PARTIAL = (MODE == G_AX_R0 || MODE == G_AP);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * WR, wc = (wave & 1) * WC;
   const int Mv = P.shape.M;
-  double csq[2] = {0.0, 0.0};
+  double csq[NI];
 #pragma unroll
-  for (int ni = 0; ni < 2; ++ni) {
+  for (int ni = 0; ni < NI; ++ni) csq[ni] = 0.0;
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni) {
     const int col = wc + 16 * ni + (lane & 15);
     const int j = j0 + (col >> 1), c = col & 1;
     const bool live = j < P.count && P.state[P.list[j]].active;
@@ -68,7 +76,7 @@ __device__ __forceinline__ void gemm_epilogue(const Params& P, int row0, int j0,
       bv = static_cast<const T*>(D.b);
     }
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wr + 16 * mi + M::row(lane, r);
@@ -82,7 +90,7 @@ __device__ __forceinline__ void gemm_epilogue(const Params& P, int row0, int j0,
     // lanes l, l+16, l+32, l+48 hold the same column: fold them, then the
     // two waves sharing a column block, always in the same order
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
+    for (int ni = 0; ni < NI; ++ni) {
       csq[ni] += __shfl_xor(csq[ni], 16, 64);
       csq[ni] += __shfl_xor(csq[ni], 32, 64);
       if (lane < 16) colpart[wave >> 1][wc + 16 * ni + lane] = csq[ni];
@@ -110,7 +118,7 @@ __device__ __forceinline__ size_t gemm_scr(int s, int row, int rows, int col) {
   return ((size_t)s * rows + row) * (size_t)(gridDim.y * BN) + col;
 }
 
-// One 64 x 64 output tile per workgroup (split s = blockIdx.z of P.gsplit
+// One GEMM_BM x 64 output tile per workgroup (split s = blockIdx.z of P.gsplit
 // takes K range [s K / S, (s+1) K / S)); the next BK-deep slices of both
 // operands are fetched into registers while the current ones (in LDS) feed
 // the MFMAs, so global latency overlaps the arithmetic.  With a split the
@@ -133,12 +141,14 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   // operand fetch roles (fixed for the whole K loop)
-  //   A, not transposed: row ar, k offsets ak .. ak+7 (contiguous)
-  //   A, transposed:     k row ak, rows ar .. ar+7 (contiguous)
-  //   B: slice jl, reals 8 part .. 8 part + 7 of its 2 BK-long run
-  const int ar = TRANS ? (tid & 7) * 8 : tid >> 2;
-  const int ak = TRANS ? tid >> 3 : (tid & 3) * 8;
-  const int jl = tid >> 3, part = tid & 7;
+  //   A, not transposed: row ar, k offsets ak .. ak+AE-1 (contiguous)
+  //   A, transposed:     k row ak, rows ar .. ar+AE-1 (contiguous)
+  //   B: slice jl, reals BE part .. BE part + BE-1 of its 2 BK-long run
+  constexpr int AE = GEMM_BM * BK / NT;            // A values per thread and stage
+  const int ar = TRANS ? (tid % (GEMM_BM / AE)) * AE : tid / (BK / AE);
+  const int ak = TRANS ? tid / (GEMM_BM / AE) : (tid % (BK / AE)) * AE;
+  constexpr int BE = 2 * BK * GEMM_BS / NT;          // B reals per thread and stage
+  const int jl = tid / (2 * BK / BE), part = tid % (2 * BK / BE);
   const T* bsrc = nullptr;
   if (j0 + jl < P.count) {
     const SliceDesc& D = P.desc[P.list[j0 + jl]];
@@ -146,32 +156,33 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
     bsrc = static_cast<const T*>(v);
   }
   const int kmax_b = MODE == G_ATB ? Mv : K;   // b has only M rows
-  T ra[8], rb[8];
+  T ra[AE], rb[BE];
   auto fetch = [&](int k0) {
     const T* src = TRANS ? A + (size_t)(k0 + ak) * N + row0 + ar : A + (size_t)(row0 + ar) * N + k0 + ak;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) ra[e] = src[e];
+    for (int e = 0; e < AE; ++e) ra[e] = src[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + ((part * 8 + e) >> 1);
+    for (int e = 0; e < BE; ++e) {
+      const int k = k0 + ((part * BE + e) >> 1);
       rb[e] = (bsrc && k < kmax_b) ? bsrc[2 * (size_t)k + (e & 1)] : (T)0;
     }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < AE; ++e) {
       if (TRANS) As[ak][ar + e] = ra[e];
       else As[ak + e][ar] = ra[e];
-      Bs[(part * 8 + e) >> 1][2 * jl + (e & 1)] = rb[e];
     }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) Bs[(part * BE + e) >> 1][2 * jl + (e & 1)] = rb[e];
   };
 
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  typename M::V acc[2][2];
+  const int wr = (wave >> 1) * WR, wc = (wave & 1) * WC;
+  typename M::V acc[MI][NI];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MI; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = typename M::V{0, 0, 0, 0};
+    for (int b = 0; b < NI; ++b) acc[a][b] = typename M::V{0, 0, 0, 0};
 
   fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -181,15 +192,15 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int k = kk + (lane >> 4);
-      T a[2], b[2];
+      T a[MI], b[NI];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) a[mi] = As[k][wr + 16 * mi + (lane & 15)];
+      for (int mi = 0; mi < MI; ++mi) a[mi] = As[k][wr + 16 * mi + (lane & 15)];
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) b[ni] = Bs[k][wc + 16 * ni + (lane & 15)];
+      for (int ni = 0; ni < NI; ++ni) b[ni] = Bs[k][wc + 16 * ni + (lane & 15)];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = M::mac(a[mi], b[ni], acc[mi][ni]);
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = M::mac(a[mi], b[ni], acc[mi][ni]);
     }
     __syncthreads();
   }
@@ -198,9 +209,9 @@ __global__ __launch_bounds__(NT) void k_gemm(Params P) {
     T* scr = static_cast<T*>(P.gscr);
     const int rows = TRANS ? N : Mp;
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
+      for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = row0 + wr + 16 * mi + M::row(lane, r);
@@ -221,16 +232,30 @@ __global__ __launch_bounds__(NT) void k_gemm_reduce(Params P) {
   const int rows = TRANS ? P.n * P.n : P.shape.Mp;
   const int row0 = blockIdx.x * GEMM_BM, j0 = blockIdx.y * GEMM_BS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * WR, wc = (wave & 1) * WC;
   const T* scr = static_cast<const T*>(P.gscr);
-  auto val = [&](int mi, int ni, int r) {
-    const int row = row0 + wr + 16 * mi + M::row(lane, r);
-    const int col = blockIdx.y * BN + wc + 16 * ni + (lane & 15);
-    T v = (T)0;
-    for (int sp = 0; sp < P.gsplit; ++sp) v += scr[gemm_scr(sp, row, rows, col)];
-    return v;
-  };
-  gemm_epilogue<T, MODE>(P, row0, j0, val, colpart);
+  // every partial of this thread's 16 outputs is loaded before the
+  // epilogue's first store (which the compiler would otherwise keep every
+  // later load behind); splits are added in their fixed order
+  T sum[MI][NI][4];
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sum[mi][ni][r] = (T)0;
+  for (int sp = 0; sp < P.gsplit; ++sp)
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wr + 16 * mi + M::row(lane, r);
+          const int col = blockIdx.y * BN + wc + 16 * ni + (lane & 15);
+          sum[mi][ni][r] += scr[gemm_scr(sp, row, rows, col)];
+        }
+  gemm_epilogue<T, MODE>(P, row0, j0, [&](int mi, int ni, int r) { return sum[mi][ni][r]; }, colpart);
 }
 
 template <typename T, int MODE>
