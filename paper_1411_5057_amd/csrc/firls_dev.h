@@ -556,6 +556,28 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Two sums over the workgroup with one pair of barriers; ``red`` holds
+// 2 NT / 64 doubles.  Each result is bitwise what block_sum gives.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[wid] = a;
+    red[NT / 64 + wid] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    sa += red[w];
+    sb += red[NT / 64 + w];
+  }
+  a = sa;
+  b = sb;
+}
+
 // Sum of ``count`` partials of a slot, in a fixed order, formed by every
 // wave on its own (lane l adds partials l, l + 64, ..., then a butterfly):
 // no barrier, and every wave of every workgroup gets the same bits.

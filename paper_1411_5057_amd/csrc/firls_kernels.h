@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   using U = Units<N, ROWS>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
@@ -286,8 +286,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       }
       d[j] = s2;
     }
-    ae = block_sum(ae, red);       // also orders the LDS reads above before the FFT
-    a0 = block_sum(a0, red);
+    block_sum2(ae, a0, red);       // also orders the LDS reads above before the FFT
     if (threadIdx.x == 0) {
       slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
       slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
@@ -784,7 +783,7 @@ __global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
 // penalty partials sum sqrt(s_g + eps), sum sqrt(s_g).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_group_w(Params P) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const T* sq = static_cast<const T*>(D.sq);
   T* W = static_cast<T*>(D.W);
@@ -802,8 +801,7 @@ __global__ __launch_bounds__(NT) void k_group_w(Params P) {
       a0 += sqrt(s);
     }
   }
-  ae = block_sum(ae, red);
-  a0 = block_sum(a0, red);
+  block_sum2(ae, a0, red);
   if (threadIdx.x == 0) {
     slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
     slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
