@@ -498,6 +498,35 @@ __device__ __forceinline__ void ell_row(const uint16_t* p, int w, uint16_t (&e)[
   }
 }
 
+// A padded list of compile-time width W (1, 2, 4 or 8 entries) in one load.
+template <int W>
+__device__ __forceinline__ void ell_row_w(const uint16_t* p, uint16_t (&e)[W]) {
+  static_assert(W == 1 || W == 2 || W == 4 || W == 8, "list width");
+  if constexpr (W == 1) {
+    e[0] = p[0];
+  } else if constexpr (W == 2) {
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+    e[0] = (uint16_t)v; e[1] = (uint16_t)(v >> 16);
+  } else if constexpr (W == 4) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16); e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
+  } else {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16); e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
+    e[4] = (uint16_t)v.z; e[5] = (uint16_t)(v.z >> 16); e[6] = (uint16_t)v.w; e[7] = (uint16_t)(v.w >> 16);
+  }
+}
+
+// Sum over a list of the LDS values it names (0xFFFF pads), in list order.
+template <int W, typename T>
+__device__ __forceinline__ T ell_gather(const uint16_t (&e)[W], const T* vals) {
+  T s = (T)0;
+#pragma unroll
+  for (int m = 0; m < W; ++m)
+    if (e[m] != 0xFFFFu) s += vals[e[m]];
+  return s;
+}
+
 // W = (s2 + eps)^(-1/2) (eq. 12), ve = sqrt(s2 + eps) and v0 = sqrt(s2) (the
 // smoothed and plain penalty terms) in the working precision: FP32 uses the
 // hardware square root and reciprocal square root (about 1 ulp), FP64 the

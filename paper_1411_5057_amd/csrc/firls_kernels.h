@@ -26,6 +26,8 @@
 // Row passes work on bands of band_rows(n) full rows; the Haar parts run in
 // registers on 16-row tile columns (haar_col), the FFT parts through LDS.
 #pragma once
+#include <type_traits>
+
 #include "firls_dev.h"
 
 namespace firls {
@@ -188,6 +190,51 @@ __device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, cons
 }
 
 // ---------------------------------------------------------------------------
+// Weights of the groups g0 .. g1-1 of one row band from |Phi x|^2 in LDS
+// (lists of width W, member offsets within the band): W_g into WL and the
+// penalty partials.  Each thread takes groups g0 + tid + k NT, eight at a
+// time, their list loads first.
+template <int W, typename T>
+__device__ __forceinline__ void band_group_weights(const uint16_t* gell, int g0, int g1, const T* sqL, T* WL, T eps,
+                                                   double& ae, double& a0) {
+  for (int gb = g0 + (int)threadIdx.x; gb < g1; gb += 8 * NT) {
+    uint16_t e[8][W];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int g = gb + u * NT;
+      if (g < g1) ell_row_w<W>(gell + (size_t)g * W, e[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int g = gb + u * NT;
+      if (g < g1) {
+        T w, ve, v0;
+        group_weight(ell_gather<W>(e[u], sqL), eps, w, ve, v0);
+        WL[g - g0] = w;
+        ae += (double)ve;
+        a0 += (double)v0;
+      }
+    }
+  }
+}
+
+// d of the band's PIX coefficients: sum of W over the groups in each
+// coefficient's list (width W, group offsets from the band's first group).
+template <int W, int PIX, typename T>
+__device__ __forceinline__ void band_d(const uint16_t* tell, const T* WL, T* d) {
+  static_assert(PIX % NT == 0, "band not a multiple of the workgroup");
+  constexpr int E = PIX / NT;
+  constexpr int CH = E % 8 == 0 ? 8 : (E % 4 == 0 ? 4 : (E % 3 == 0 ? 3 : 1));
+#pragma unroll
+  for (int c = 0; c < E; c += CH) {
+    uint16_t e[CH][W];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) ell_row_w<W>(tell + (size_t)(threadIdx.x + (c + u) * NT) * W, e[u]);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) d[threadIdx.x + (c + u) * NT] = ell_gather<W>(e[u], WL);
+  }
+}
+
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   constexpr int ROWS = band_rows(N);
@@ -254,37 +301,47 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     const int g0 = P.shape.bgptr[blockIdx.x], g1 = P.shape.bgptr[blockIdx.x + 1];
     const ShapeDev& G = P.shape;
     double ae = 0.0, a0 = 0.0;
-    for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
-      T s2 = (T)0;
-      if (G.gell) {   // padded list: one load, members in the CSR order
-        uint16_t e[ELL_MAX];
-        ell_row(G.gell + (size_t)g * G.gw, G.gw, e);
-#pragma unroll
-        for (int m = 0; m < ELL_MAX; ++m)
-          if (m < G.gw && e[m] != 0xFFFFu) s2 += sqL[e[m]];
-      } else {
-        for (int j = G.gptr[g]; j < G.gptr[g + 1]; ++j) s2 += sqL[G.gidx[j] - (int)off];
-      }
-      T w, ve, v0;
-      group_weight(s2, (T)P.eps, w, ve, v0);
-      WL[g - g0] = w;
-      ae += (double)ve;
-      a0 += (double)v0;
-    }
-    __syncthreads();
     T* d = static_cast<T*>(D.d) + off;
-    for (int j = threadIdx.x; j < ROWS * N; j += NT) {
-      T s2 = (T)0;
-      if (G.tell) {
-        uint16_t e[ELL_MAX];
-        ell_row(G.tell + (off + j) * G.tw, G.tw, e);
-#pragma unroll
-        for (int m = 0; m < ELL_MAX; ++m)
-          if (m < G.tw && e[m] != 0xFFFFu) s2 += WL[e[m]];
-      } else {
-        for (int t = G.tptr[off + j]; t < G.tptr[off + j + 1]; ++t) s2 += WL[G.tidx[t] - g0];
+    if (G.gell) {
+      // padded lists of compile-time width: each thread's list loads are
+      // issued together, ahead of the LDS gathers that use them
+      auto groups = [&](auto wtag) {
+        constexpr int W = decltype(wtag)::value;
+        band_group_weights<W>(G.gell, g0, g1, sqL, WL, (T)P.eps, ae, a0);
+      };
+      switch (G.gw) {
+        case 1: groups(std::integral_constant<int, 1>{}); break;
+        case 2: groups(std::integral_constant<int, 2>{}); break;
+        case 4: groups(std::integral_constant<int, 4>{}); break;
+        default: groups(std::integral_constant<int, 8>{}); break;
       }
-      d[j] = s2;
+      __syncthreads();
+      auto members = [&](auto wtag) {
+        constexpr int W = decltype(wtag)::value;
+        band_d<W, ROWS * N>(G.tell + off * W, WL, d);
+      };
+      switch (G.tw) {
+        case 1: members(std::integral_constant<int, 1>{}); break;
+        case 2: members(std::integral_constant<int, 2>{}); break;
+        case 4: members(std::integral_constant<int, 4>{}); break;
+        default: members(std::integral_constant<int, 8>{}); break;
+      }
+    } else {
+      for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
+        T s2 = (T)0;
+        for (int j = G.gptr[g]; j < G.gptr[g + 1]; ++j) s2 += sqL[G.gidx[j] - (int)off];
+        T w, ve, v0;
+        group_weight(s2, (T)P.eps, w, ve, v0);
+        WL[g - g0] = w;
+        ae += (double)ve;
+        a0 += (double)v0;
+      }
+      __syncthreads();
+      for (int j = threadIdx.x; j < ROWS * N; j += NT) {
+        T s2 = (T)0;
+        for (int t = G.tptr[off + j]; t < G.tptr[off + j + 1]; ++t) s2 += WL[G.tidx[t] - g0];
+        d[j] = s2;
+      }
     }
     block_sum2(ae, a0, red);       // also orders the LDS reads above before the FFT
     if (threadIdx.x == 0) {
