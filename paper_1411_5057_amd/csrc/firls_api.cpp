@@ -359,10 +359,16 @@ struct TimingScope {   // launch_timing() set for one launcher call
   } while (0)
 
 // Weights of the current x: |Psi x|^2, W per group (+ penalty partials), d.
-// ``penalty_only``: W and the penalty partials, without d (enough for F_eps).
+// ``penalty_only``: the penalty partials without d (enough for F_eps); with
+// band-local groups one pass from x (the callers then read s.row_wgs()
+// partials, P.nreg).
 int launch_weights(firls_handle* h, const Shape& s, const Params& P, int c, hipStream_t st,
                    bool penalty_only = false) {
   const PrecKernels* pk = prec_kernels(h->fp64);
+  if (penalty_only && s.psi == PSI_HAAR && s.d_bgptr && !s.dense) {
+    KLAUNCH(h, FIRLS_PROF_GROUP_W, s.sk->rowfwd[RF_PEN_HAAR], P, dim3(s.row_wgs(), c), st);
+    return FIRLS_OK;
+  }
   if (s.psi == PSI_HAAR) KLAUNCH(h, FIRLS_PROF_PSI_SQ, s.sk->psi_sq_haar, P, dim3(s.row_wgs(), c), st);
   else KLAUNCH(h, FIRLS_PROF_PSI_SQ, pk->psi_sq_tv, P, dim3(((int)s.pixels() + 4 * NT - 1) / (4 * NT), c), st);
   KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
@@ -1378,6 +1384,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
       // the data-consistency step sets m F x0 = b), so F_eps is lambda times
       // the penalty: no Fourier pass is needed.
       P.no_data = 1;
+      if (S.psi == PSI_HAAR && S.d_bgptr && !S.dense) P.nreg = S.row_wgs();   // one partial per band
       LAUNCH(prec_kernels(false)->slice_init, P, dim3(c), st);
       int r2 = launch_weights(h, S, P, c, st, true);
       if (r2) return r2;

@@ -63,6 +63,7 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowfwd<T, N, RF_STEP_HAAR>, b);
   allow_lds(k_rowfwd<T, N, RF_SQ_HAAR>, b);
   allow_lds(k_rowfwd<T, N, RF_SQW_HAAR>, b);
+  allow_lds(k_rowfwd<T, N, RF_PEN_HAAR>, b);
   const size_t bc = lds_col_bytes<T, N>();
   allow_lds(k_col<T, N, COL_SP>, bc);
   allow_lds(k_col<T, N, COL_R0>, bc);
@@ -81,6 +82,7 @@ SizeKernels make_size_kernels() {
   k.rowfwd[RF_STEP_HAAR] = L_rowfwd<T, N, RF_STEP_HAAR>;
   k.rowfwd[RF_SQ_HAAR] = L_rowfwd<T, N, RF_SQ_HAAR>;
   k.rowfwd[RF_SQW_HAAR] = L_rowfwd<T, N, RF_SQW_HAAR>;
+  k.rowfwd[RF_PEN_HAAR] = L_rowfwd<T, N, RF_PEN_HAAR>;
   k.col[COL_SP] = L_col<T, N, COL_SP>;
   k.col[COL_R0] = L_col<T, N, COL_R0>;
   k.col[COL_AHB] = L_col<T, N, COL_AHB>;

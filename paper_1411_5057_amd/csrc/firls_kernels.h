@@ -253,7 +253,9 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   if constexpr (MODE == RF_PLAIN) {
     const C* x = static_cast<const C*>(D.x) + off;
     fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, [&](int l, int q) { return x[l * N + q]; }, gdst);
-  } else if constexpr (MODE == RF_SQW_HAAR) {
+  } else if constexpr (MODE == RF_SQW_HAAR || MODE == RF_PEN_HAAR) {
+    // RF_PEN_HAAR: only the penalty partials of x (no x update, d or FFT).
+    constexpr bool PEN = MODE == RF_PEN_HAAR;
     // Every group lies inside one row band (tree groups do: parent and child
     // share a Haar tile), so the weights need nothing outside this band:
     // |Phi x|^2 into LDS, W_g of the band's groups (eq. 12) and the penalty
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     // With fold_x a pending x += alpha p of the last PCG iteration (alpha
     // from its <r,z> and <p,q> sums) is applied first and x written back.
     C* x = static_cast<C*>(D.x) + off;
-    const bool pend = P.fold_x && P.state[s_].pend;
+    const bool pend = !PEN && P.fold_x && P.state[s_].pend;
     T al = (T)0;
     if (pend) {
       const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
@@ -315,16 +317,18 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         case 4: groups(std::integral_constant<int, 4>{}); break;
         default: groups(std::integral_constant<int, 8>{}); break;
       }
-      __syncthreads();
-      auto members = [&](auto wtag) {
-        constexpr int W = decltype(wtag)::value;
-        band_d<W, ROWS * N>(G.tell + off * W, WL, d);
-      };
-      switch (G.tw) {
-        case 1: members(std::integral_constant<int, 1>{}); break;
-        case 2: members(std::integral_constant<int, 2>{}); break;
-        case 4: members(std::integral_constant<int, 4>{}); break;
-        default: members(std::integral_constant<int, 8>{}); break;
+      if constexpr (!PEN) {
+        __syncthreads();
+        auto members = [&](auto wtag) {
+          constexpr int W = decltype(wtag)::value;
+          band_d<W, ROWS * N>(G.tell + off * W, WL, d);
+        };
+        switch (G.tw) {
+          case 1: members(std::integral_constant<int, 1>{}); break;
+          case 2: members(std::integral_constant<int, 2>{}); break;
+          case 4: members(std::integral_constant<int, 4>{}); break;
+          default: members(std::integral_constant<int, 8>{}); break;
+        }
       }
     } else {
       for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
@@ -336,11 +340,13 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         ae += (double)ve;
         a0 += (double)v0;
       }
-      __syncthreads();
-      for (int j = threadIdx.x; j < ROWS * N; j += NT) {
-        T s2 = (T)0;
-        for (int t = G.tptr[off + j]; t < G.tptr[off + j + 1]; ++t) s2 += WL[G.tidx[t] - g0];
-        d[j] = s2;
+      if constexpr (!PEN) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < ROWS * N; j += NT) {
+          T s2 = (T)0;
+          for (int t = G.tptr[off + j]; t < G.tptr[off + j + 1]; ++t) s2 += WL[G.tidx[t] - g0];
+          d[j] = s2;
+        }
       }
     }
     block_sum2(ae, a0, red);       // also orders the LDS reads above before the FFT
@@ -348,15 +354,17 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
       slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
     }
+    if constexpr (!PEN) {
 #pragma unroll
-    for (int k = 0; k < U::PER; ++k) {
-      if (!U::valid(k)) continue;
-      const int col = U::col(k), row = U::row(k);
+      for (int k = 0; k < U::PER; ++k) {
+        if (!U::valid(k)) continue;
+        const int col = U::col(k), row = U::row(k);
 #pragma unroll
-      for (int s = 0; s < 16; ++s) lds[Lay::at(row + s, col)] = xv[k][s];
+        for (int s = 0; s < 16; ++s) lds[Lay::at(row + s, col)] = xv[k][s];
+      }
+      __syncthreads();
+      fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
     }
-    __syncthreads();
-    fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds}, gdst);
   } else if constexpr (MODE == RF_SQ_HAAR) {
     // row FFTs of x and, from the same read, |Phi x|^2 per coefficient
     const C* x = static_cast<const C*>(D.x) + off;

@@ -25,7 +25,7 @@ using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
 
 // Kernels that depend on the image side (FFT length).
 struct SizeKernels {
-  Launcher rowfwd[6];
+  Launcher rowfwd[7];
   Launcher col[5];
   Launcher rowinv[5];
   Launcher psi_sq_haar;

@@ -38,7 +38,7 @@ enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
 
 // Kernel variants (template modes).
 enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAAR = 3, RF_SQ_HAAR = 4,
-                        RF_SQW_HAAR = 5 };
+                        RF_SQW_HAAR = 5, RF_PEN_HAAR = 6 };
 enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3, COL_SP_PQ = 4 };
 enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
 enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
