@@ -475,29 +475,6 @@ struct Units {
 // ---------------------------------------------------------------------------
 // Group weights.
 // ---------------------------------------------------------------------------
-// One padded list of w (1, 2, 4 or 8) 16-bit entries with a single load.
-__device__ __forceinline__ void ell_row(const uint16_t* p, int w, uint16_t (&e)[ELL_MAX]) {
-#pragma unroll
-  for (int m = 0; m < ELL_MAX; ++m) e[m] = 0xFFFFu;
-  if (w == 1) {
-    e[0] = p[0];
-  } else if (w == 2) {
-    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
-    e[0] = (uint16_t)v;
-    e[1] = (uint16_t)(v >> 16);
-  } else if (w == 4) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16);
-    e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
-  } else {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
-    e[0] = (uint16_t)v.x; e[1] = (uint16_t)(v.x >> 16);
-    e[2] = (uint16_t)v.y; e[3] = (uint16_t)(v.y >> 16);
-    e[4] = (uint16_t)v.z; e[5] = (uint16_t)(v.z >> 16);
-    e[6] = (uint16_t)v.w; e[7] = (uint16_t)(v.w >> 16);
-  }
-}
-
 // A padded list of compile-time width W (1, 2, 4 or 8 entries) in one load.
 template <int W>
 __device__ __forceinline__ void ell_row_w(const uint16_t* p, uint16_t (&e)[W]) {

@@ -794,7 +794,6 @@ template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_last_x(Params P) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
-  __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE(blockIdx.y)
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
