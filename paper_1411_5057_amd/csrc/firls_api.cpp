@@ -112,10 +112,13 @@ struct firls_handle {
   SliceDesc* h_desc = nullptr;
   SliceState* h_state = nullptr;
   int32_t* h_list = nullptr;
+  // stop-test words, (evaluations << 1) | active per slice, in host memory
+  // the kernels write to directly (coherent, mapped)
+  int32_t* h_flags = nullptr;
+  int32_t* d_flags = nullptr;
   hipEvent_t ev = nullptr;
-  hipEvent_t ev2 = nullptr;
 
-  // graph replay of the per-outer-iteration launch blocks
+  // graph replay of one outer iteration's launches
   bool use_graphs = true;
   hipStream_t own = nullptr;          // work stream when the caller passes the null stream
   hipEvent_t ev_in = nullptr;
@@ -130,7 +133,7 @@ struct firls_handle {
       return counts == o.counts && Tmax == o.Tmax && tau == o.tau && ws == o.ws && desc == o.desc && stream == o.stream;
     }
   } gkey;
-  hipGraphExec_t g_prep = nullptr, g_pcg = nullptr;
+  hipGraphExec_t g_iter = nullptr;
   // sub-batch size chosen by firls_autotune (0: the whole batch at once)
   int chunk = 0;
 
@@ -167,9 +170,8 @@ struct firls_handle {
 namespace {
 
 void drop_graphs(firls_handle* h) {
-  if (h->g_prep) (void)hipGraphExecDestroy(h->g_prep);
-  if (h->g_pcg) (void)hipGraphExecDestroy(h->g_pcg);
-  h->g_prep = h->g_pcg = nullptr;
+  if (h->g_iter) (void)hipGraphExecDestroy(h->g_iter);
+  h->g_iter = nullptr;
   h->gkey = firls_handle::GraphKey{};
 }
 
@@ -188,6 +190,7 @@ void free_batch(firls_handle* h) {
   if (h->h_desc) (void)hipHostFree(h->h_desc);
   if (h->h_state) (void)hipHostFree(h->h_state);
   if (h->h_list) (void)hipHostFree(h->h_list);
+  if (h->h_flags) (void)hipHostFree(h->h_flags);
   h->ws = nullptr;
   h->ws_cap = 0;
   h->d_desc = nullptr;
@@ -196,6 +199,7 @@ void free_batch(firls_handle* h) {
   h->h_desc = nullptr;
   h->h_state = nullptr;
   h->h_list = nullptr;
+  h->h_flags = h->d_flags = nullptr;
   h->cap_slices = 0;
 }
 
@@ -222,12 +226,20 @@ int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
     if (h->h_desc) HIPCHK(hipHostFree(h->h_desc));
     if (h->h_state) HIPCHK(hipHostFree(h->h_state));
     if (h->h_list) HIPCHK(hipHostFree(h->h_list));
+    if (h->h_flags) HIPCHK(hipHostFree(h->h_flags));
+    h->h_desc = nullptr;
+    h->h_state = nullptr;
+    h->h_list = nullptr;
+    h->h_flags = h->d_flags = nullptr;
+    h->cap_slices = 0;
     HIPCHK(hipMalloc(&h->d_desc, sizeof(SliceDesc) * want));
     HIPCHK(hipMalloc(&h->d_state, sizeof(SliceState) * want));
     HIPCHK(hipMalloc(&h->d_list, sizeof(int32_t) * 2 * want));
     HIPCHK(hipHostMalloc(&h->h_desc, sizeof(SliceDesc) * want, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc(&h->h_state, sizeof(SliceState) * 3 * want, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h->h_state, sizeof(SliceState) * want, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&h->h_list, sizeof(int32_t) * 2 * want, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&h->h_flags, sizeof(int32_t) * want, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->d_flags), h->h_flags, 0));
     h->cap_slices = want;
   }
   return FIRLS_OK;
@@ -643,6 +655,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       Params P = base_params(h, S, s, h->d_list + lo[s]);
       P.Tmax = Tmax;
       P.tau = tau;
+      P.stop_flags = h->d_flags;
       h->ctx_group = s;
       h->ctx_count = c;
       int r2;
@@ -663,8 +676,8 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     }
     return FIRLS_OK;
   };
-  // Every outer iteration launches the same two blocks with the same
-  // arguments, so they are captured once as graphs and replayed.
+  // Every outer iteration launches the same kernels with the same arguments,
+  // so one iteration is captured once as a graph and replayed.
   const bool graphs = h->use_graphs && !h->profiling && st != nullptr;
   if (graphs) {
     firls_handle::GraphKey key;
@@ -674,66 +687,85 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     key.ws = h->ws;
     key.desc = h->d_desc;
     key.stream = st;
-    if (!(key == h->gkey) || !h->g_prep || !h->g_pcg) {
+    if (!(key == h->gkey) || !h->g_iter) {
       drop_graphs(h);
-      hipGraph_t gp = nullptr, gq = nullptr;
+      hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       rc = enqueue_prep();
-      hipError_t e1 = hipStreamEndCapture(st, &gp);
-      if (rc) return rc;
-      HIPCHK(e1);
-      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_pcg();
-      hipError_t e2 = hipStreamEndCapture(st, &gq);
-      if (rc) return rc;
-      HIPCHK(e2);
-      HIPCHK(hipGraphInstantiate(&h->g_prep, gp, nullptr, nullptr, 0));
-      HIPCHK(hipGraphInstantiate(&h->g_pcg, gq, nullptr, nullptr, 0));
-      (void)hipGraphDestroy(gp);
-      (void)hipGraphDestroy(gq);
+      if (!rc) rc = enqueue_pcg();
+      hipError_t e = hipStreamEndCapture(st, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      HIPCHK(e);
+      e = hipGraphInstantiate(&h->g_iter, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e);
       h->gkey = key;
     }
   }
-  // The host learns which slices are still active one iteration late:
-  // iteration it + 1 is enqueued before the stop-test record of iteration it
-  // is read, so the GPU never waits for the host.  Kernels of slices that
-  // have stopped exit at their first instruction, so the iteration enqueued
-  // after the last slice stopped costs only its launches.
-  hipEvent_t evs[2] = {h->ev, h->ev2};
-  auto ring = [&](int j) { return h->h_state + (size_t)(1 + (j & 1)) * h->cap_slices; };
-  auto read_active = [&](int j) {
-    const SliceState* hs = ring(j);
+  // The outer check of each slice writes (evaluations << 1) | active to
+  // host memory at the start of every iteration.  Before launching
+  // iteration it the host polls for iteration it - 1's words, so the GPU
+  // works through that iteration's PCG launches meanwhile; once no slice is
+  // active nothing more is launched, and only the PCG launches of the last
+  // iteration run empty (kernels of stopped slices exit at once).
+  for (int i = 0; i < ns; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
+  auto read_active = [&](int j, bool& done) {
+    std::vector<int> cnt(nsh, 0);
     int active = 0;
-    act_pcg.emplace_back(nsh, 0);
+    done = true;
     for (int i = 0; i < ns; ++i) {
-      active += hs[i].active;
-      act_pcg.back()[sl[i].shape_id] += hs[i].active;
+      const int32_t w = __atomic_load_n(h->h_flags + i, __ATOMIC_ACQUIRE);
+      if ((w & 1) && (w >> 1) <= j) done = false;
+      active += w & 1;
+      cnt[sl[i].shape_id] += w & 1;
     }
+    if (done) act_pcg.push_back(cnt);
     return active;
+  };
+  // Polls until iteration j's outer checks have all reported.  The event
+  // recorded after iteration j's launches bounds the wait: once it has
+  // completed, every word is final.
+  auto wait_checks = [&](int j, int& active) -> int {
+    bool done = false;
+    for (unsigned spin = 1;; ++spin) {
+      active = read_active(j, done);
+      if (done) return FIRLS_OK;
+      if (spin % 64) continue;
+      const hipError_t e = hipEventQuery(h->ev);
+      if (e == hipErrorNotReady) continue;
+      HIPCHK(e);
+      active = read_active(j, done);
+      if (done) return FIRLS_OK;
+      return fail(FIRLS_E_HIP, "an outer check did not report");
+    }
   };
   bool stopped = false;
   for (int it = 0; it <= Tmax; ++it) {
-    h->ctx_it = it;
-    h->ctx_phase = 1;
-    if (graphs) HIPCHK(hipGraphLaunch(h->g_prep, st));
-    else if ((rc = enqueue_prep())) return rc;
-    HIPCHK(hipMemcpyAsync(ring(it), h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(evs[it & 1], st));
-    h->ctx_phase = 2;
-    if (graphs) HIPCHK(hipGraphLaunch(h->g_pcg, st));
-    else if ((rc = enqueue_pcg())) return rc;
     if (it >= 1) {
-      HIPCHK(hipEventSynchronize(evs[(it - 1) & 1]));
-      if (!read_active(it - 1)) {
-        act_pcg.emplace_back(nsh, 0);   // iteration it ran with no active slice
+      int active = 0;
+      if ((rc = wait_checks(it - 1, active))) return rc;
+      if (!active) {
         stopped = true;
         break;
       }
     }
+    h->ctx_it = it;
+    if (graphs) {
+      HIPCHK(hipGraphLaunch(h->g_iter, st));
+    } else {
+      h->ctx_phase = 1;
+      if ((rc = enqueue_prep())) return rc;
+      h->ctx_phase = 2;
+      if ((rc = enqueue_pcg())) return rc;
+    }
+    HIPCHK(hipEventRecord(h->ev, st));
   }
   if (!stopped) {
-    HIPCHK(hipEventSynchronize(evs[Tmax & 1]));
-    (void)read_active(Tmax);
+    int active = 0;
+    if ((rc = wait_checks(Tmax, active))) return rc;
   }
   HIPCHK(hipStreamSynchronize(st));
   if (h->profiling && (rc = prof_collect(h, act_pcg))) return rc;
@@ -1078,8 +1110,7 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
       return fail(rc, msg);
     }
   }
-  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev2, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&h->ev, hipEventDisableTiming) != hipSuccess) {
     destroy_shapes(h);
     delete h;
     return fail(FIRLS_E_HIP, "event creation failed");
@@ -1094,7 +1125,6 @@ int firls_destroy(firls_handle* h) {
   free_batch(h);
   destroy_shapes(h);
   if (h->ev) (void)hipEventDestroy(h->ev);
-  if (h->ev2) (void)hipEventDestroy(h->ev2);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->own) (void)hipStreamDestroy(h->own);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1460,7 +1490,8 @@ int firls_set_chunk(firls_handle* h, int32_t chunk) {
   return FIRLS_OK;
 }
 
-int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen) {
+int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen,
+                   int32_t* graphs) {
   if (!h || !slices || n_slices <= 0) return fail(FIRLS_E_INVALID, "bad argument");
   if (n_slices > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
   g_err.clear();
@@ -1485,16 +1516,20 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     std::string line;
     while (std::getline(in, line)) {
       const size_t bar = line.rfind('|');
-      if (bar != std::string::npos && line.substr(0, bar) == key) {
-        h->chunk = std::atoi(line.c_str() + bar + 1);
+      const size_t bar2 = bar == std::string::npos ? bar : line.rfind('|', bar - 1);
+      if (bar2 != std::string::npos && line.substr(0, bar2) == key) {
+        h->chunk = std::atoi(line.c_str() + bar2 + 1);
+        h->use_graphs = std::atoi(line.c_str() + bar + 1) != 0;
         if (chosen) *chosen = h->chunk;
+        if (graphs) *graphs = h->use_graphs ? 1 : 0;
         return FIRLS_OK;
       }
     }
   }
   // snapshot every x (trials overwrite it) and time a few outer iterations
-  // per candidate sub-batch size; each candidate runs twice, the second run
-  // (graphs already captured) is timed
+  // per candidate sub-batch size and launch mode (graph replay or direct
+  // launches); each candidate runs twice, the second run (graphs already
+  // captured) is timed
   size_t bytes = 0;
   std::vector<size_t> xb(n_slices);
   for (int i = 0; i < n_slices; ++i) {
@@ -1524,11 +1559,17 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
   const int T = std::max(1, std::min(3, h->cfg.max_outer));
   double best = 1e300;
   int best_c = 0;
+  bool best_g = true;
+  const int chunk0 = h->chunk;
+  const bool graphs0 = h->use_graphs;
   const bool prof = h->profiling;
   h->profiling = false;
-  for (int c : cands) {
+  for (int trial = 0; trial < 2 * (int)cands.size(); ++trial) {
     if (rc) break;
+    const int c = cands[trial / 2];
+    const bool g = trial % 2 == 0;
     h->chunk = c;
+    h->use_graphs = g;
     double t = 0.0;
     for (int rep_i = 0; rep_i < 2 && !rc; ++rep_i) {
       if ((rc = copy_all(false))) break;
@@ -1542,18 +1583,25 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     if (!rc && t < best) {
       best = t;
       best_c = c;
+      best_g = g;
     }
   }
   h->profiling = prof;
   if (!rc) rc = copy_all(false);
   (void)hipStreamSynchronize(st);
   (void)hipFree(snap);
-  if (rc) return rc;
+  if (rc) {
+    h->chunk = chunk0;
+    h->use_graphs = graphs0;
+    return rc;
+  }
   h->chunk = best_c;
+  h->use_graphs = best_g;
   if (chosen) *chosen = best_c;
+  if (graphs) *graphs = best_g ? 1 : 0;
   if (cache) {
     std::ofstream out(cache, std::ios::app);
-    out << key << "|" << best_c << "\n";
+    out << key << "|" << best_c << "|" << (best_g ? 1 : 0) << "\n";
   }
   return FIRLS_OK;
 }

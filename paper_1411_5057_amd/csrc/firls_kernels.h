@@ -160,6 +160,10 @@ __device__ __forceinline__ void outer_check_wg(const Params& P, int s) {
   // a slice that goes on runs K PCG iterations, whose last x += alpha p the
   // next residual pass applies
   if (P.fold_x) S.pend = S.active;
+  // the host polls this word to learn when the test ran and its outcome: a
+  // system-scope store goes straight to host memory
+  if (P.stop_flags)
+    __hip_atomic_store(P.stop_flags + s, (S.evals << 1) | S.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }

@@ -152,6 +152,8 @@ struct Params {
   double eps;
   double tau;
   void* out;             // op entry points: extra output
+  int32_t* stop_flags;   // host-mapped word per slice, (evaluations << 1) | active,
+                         // written by the outer check (null: not written)
 };
 
 }  // namespace firls

@@ -79,6 +79,56 @@ class firls_report(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+# numpy views of the two batch records (same layout as the structures
+# above), so a batch is marshalled column by column
+SLICE_DTYPE = np.dtype([("shape_id", "<i4"), ("x_is_init", "<i4"), ("lambda_", "<f8"), ("b", "<u8"),
+                        ("mask", "<u8"), ("x", "<u8")])
+REPORT_DTYPE = np.dtype([("status", "<i4"), ("outer_iters", "<i4"), ("pcg_iters", "<i4"), ("converged", "<i4"),
+                         ("F", "<f8"), ("F_eps", "<f8"), ("data", "<f8"), ("rel_change", "<f8")])
+for _dt, _st in ((SLICE_DTYPE, firls_slice), (REPORT_DTYPE, firls_report)):
+    assert _dt.itemsize == ctypes.sizeof(_st)
+    assert all(_dt.fields[f][1] == getattr(_st, f).offset for f, _ in _st._fields_)
+
+
+def slice_array(items, init: Optional[bool] = None) -> np.ndarray:
+    """items (dicts with b, mask, x, lam, shape_id, x_is_init) -> firls_slice
+    records; ``init`` overrides every x_is_init."""
+    a = np.empty(len(items), SLICE_DTYPE)
+    a["shape_id"] = [it.get("shape_id", 0) for it in items]
+    a["x_is_init"] = ([bool(it.get("x_is_init", False)) for it in items] if init is None else bool(init))
+    a["lambda_"] = [it["lam"] for it in items]
+    a["b"] = [_ptr(it["b"]) for it in items]
+    a["mask"] = [_ptr(it["mask"]) for it in items]
+    a["x"] = [_ptr(it["x"]) for it in items]
+    return a
+
+
+def report_dicts(r: np.ndarray) -> List[dict]:
+    names = r.dtype.names
+    return [dict(zip(names, t)) for t in r.tolist()]
+
+
+def _as(a: np.ndarray, st):
+    return a.ctypes.data_as(ctypes.POINTER(st))
+
+
+class Batch:
+    """A batch marshalled once, for repeated solves of the same buffers (a
+    serving loop that refills b, mask and x in place).  Holds the items, so
+    their tensors stay alive.  Solves of a Batch return the reports as a
+    numpy structured array with the fields of firls_report (one record per
+    slice, in item order)."""
+
+    def __init__(self, items: List[dict], init: Optional[bool] = None):
+        self.items = list(items)
+        self.slices = slice_array(self.items, init)
+        self.reports = np.zeros(len(self.items), REPORT_DTYPE)
+        self.used = np.zeros(len(self.items), np.int32)
+
+    def __len__(self):
+        return len(self.items)
+
+
 _lib = None
 
 
@@ -108,7 +158,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_last_error": ([], ctypes.c_char_p),
         "firls_set_graphs": ([vp, i32], ctypes.c_int),
         "firls_set_chunk": ([vp, i32], ctypes.c_int),
-        "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32)], ctypes.c_int),
+        "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                           ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
         "firls_cnn_create": ([i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "firls_cnn_destroy": ([vp], ctypes.c_int),
@@ -377,6 +428,7 @@ class Solver:
         self.cfg = cfg
         self.prec = prec
         self.handle = firls_create(cfg)
+        self.graphs = True
 
     def close(self):
         if self.handle:
@@ -395,16 +447,23 @@ class Solver:
         firls_solve(self.handle, _stream(stream), sl, rep)
         return rep.as_dict()
 
-    def solve_batched(self, items: List[dict], stream=None) -> List[dict]:
-        """items: dicts with b, mask, x, lam, shape_id (0), x_is_init (False)."""
-        n = len(items)
-        arr = (firls_slice * n)()
-        for i, it in enumerate(items):
-            arr[i] = firls_slice(int(it.get("shape_id", 0)), int(bool(it.get("x_is_init", False))),
-                                 float(it["lam"]), _ptr(it["b"]), _ptr(it["mask"]), _ptr(it["x"]))
-        reps = (firls_report * n)()
-        firls_solve_batched(self.handle, _stream(stream), n, arr, reps)
-        return [r.as_dict() for r in reps]
+    def prepare(self, items: List[dict], learned: bool = False) -> Batch:
+        """Marshal a batch once (``learned``: for solve_batched_learned, whose
+        slices all count as initialised)."""
+        return Batch(items, True if learned else None)
+
+    def solve_batched(self, items, stream=None):
+        """items: dicts with b, mask, x, lam, shape_id (0), x_is_init (False),
+        or a Batch from prepare().  Returns one report dict per item (a
+        structured array for a Batch)."""
+        if isinstance(items, Batch):
+            firls_solve_batched(self.handle, _stream(stream), len(items), _as(items.slices, firls_slice),
+                                _as(items.reports, firls_report))
+            return items.reports.copy()
+        arr = slice_array(items)
+        reps = np.zeros(len(items), REPORT_DTYPE)
+        firls_solve_batched(self.handle, _stream(stream), len(items), _as(arr, firls_slice), _as(reps, firls_report))
+        return report_dicts(reps)
 
     # single-operator entry points
     def adjoint(self, b, mask, x, shape_id=0, stream=None):
@@ -422,39 +481,38 @@ class Solver:
     def objective(self, b, mask, lam, x, shape_id=0, stream=None):
         return firls_op_objective(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
 
-    def solve_batched_learned(self, net: "Net", items: List[dict], stream=None):
+    def solve_batched_learned(self, net: "Net", items, stream=None):
         """Like solve_batched, started from the network (returns reports and
-        the per-slice flag of whether the learned start was kept)."""
-        n = len(items)
-        arr = (firls_slice * n)()
-        for i, it in enumerate(items):
-            arr[i] = firls_slice(int(it.get("shape_id", 0)), 1, float(it["lam"]), _ptr(it["b"]),
-                                 _ptr(it["mask"]), _ptr(it["x"]))
-        reps = (firls_report * n)()
-        used = (ctypes.c_int32 * n)()
-        firls_solve_batched_learned(self.handle, net.handle, _stream(stream), n, arr, reps, used)
-        return [r.as_dict() for r in reps], [int(u) for u in used]
-
-    def _slices(self, items, init=None):
-        n = len(items)
-        arr = (firls_slice * n)()
-        for i, it in enumerate(items):
-            x_init = int(bool(it.get("x_is_init", False))) if init is None else init
-            arr[i] = firls_slice(int(it.get("shape_id", 0)), x_init, float(it["lam"]), _ptr(it["b"]),
-                                 _ptr(it["mask"]), _ptr(it["x"]))
-        return arr
+        the per-slice flag of whether the learned start was kept).  items may
+        be a Batch from prepare(..., learned=True)."""
+        if isinstance(items, Batch):
+            firls_solve_batched_learned(self.handle, net.handle, _stream(stream), len(items),
+                                        _as(items.slices, firls_slice), _as(items.reports, firls_report),
+                                        _as(items.used, ctypes.c_int32))
+            return items.reports.copy(), items.used.copy()
+        arr = slice_array(items, True)
+        reps = np.zeros(len(items), REPORT_DTYPE)
+        used = np.zeros(len(items), np.int32)
+        firls_solve_batched_learned(self.handle, net.handle, _stream(stream), len(items), _as(arr, firls_slice),
+                                    _as(reps, firls_report), _as(used, ctypes.c_int32))
+        return report_dicts(reps), [int(u) for u in used]
 
     def set_graphs(self, enable: bool):
         _check(load().firls_set_graphs(self.handle, int(enable)), "firls_set_graphs")
+        self.graphs = bool(enable)
 
     def set_chunk(self, chunk: int):
         _check(load().firls_set_chunk(self.handle, int(chunk)), "firls_set_chunk")
 
     def autotune(self, items: List[dict], stream=None) -> int:
-        arr = self._slices(items)
-        chosen = ctypes.c_int32()
-        _check(load().firls_autotune(self.handle, _stream(stream), len(items), arr, ctypes.byref(chosen)),
+        """Picks the sub-batch size (returned) and the launch mode (kept in
+        ``self.graphs``: True for graph replay) for these slices."""
+        arr = slice_array(items)
+        chosen, graphs = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().firls_autotune(self.handle, _stream(stream), len(items), _as(arr, firls_slice),
+                                     ctypes.byref(chosen), ctypes.byref(graphs)),
                "firls_autotune")
+        self.graphs = bool(graphs.value)
         return chosen.value
 
     def profile(self, enable: bool):

@@ -116,6 +116,15 @@ def test_learned_solve_reaches_oracle_optimum():
         ref = firls(ops, T, 20, tau=tau, x1=start)
         fe = ops.objective(to_np(it["x"]))[0]
         assert abs(fe - ref.F_eps) <= 1e-5 * ref.F_eps
+    # the same slices marshalled once (Solver.prepare): identical reports,
+    # start choices and x
+    items2 = [dict(it, x=torch.zeros_like(it["x"])) for it in items]
+    reps2, used2 = s.solve_batched_learned(net, s.prepare(items2, learned=True))
+    assert list(used2) == list(used)
+    for r, q in zip(reps2, reps):
+        assert r["F_eps"] == q["F_eps"] and r["outer_iters"] == q["outer_iters"]
+    for a, b in zip(items, items2):
+        assert torch.equal(a["x"], b["x"])
 
 
 def test_bad_network_falls_back_to_zero_filled():

@@ -252,6 +252,39 @@ def test_chunked_batches_and_autotune():
         assert torch.equal(a["x"], b["x"])
     before = [it["x"].clone() for it in parts]
     chosen = s.autotune(parts)
-    assert chosen in (0, 32)
+    assert chosen in (0, 32) and isinstance(s.graphs, bool)
     for a, b in zip(before, parts):
         assert torch.equal(a, b["x"])
+    # the tuned sub-batch size and launch mode give the same results
+    r2 = s.solve_batched(parts)
+    assert [r["F_eps"] for r in r2] == [r["F_eps"] for r in r0]
+    for a, b in zip(whole, parts):
+        assert torch.equal(a["x"], b["x"])
+
+
+def test_prepared_batch_matches_item_lists():
+    """A batch marshalled once (Solver.prepare) and solved twice gives the
+    same reports and x as the item-list call; slices of two sizes stop at
+    different outer iterations, so the host's polling of the stop words
+    sees slices finish one by one."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 80 + i, psi="haar", levels=4, groups="quadtree", lam=0.035 * (1 + i % 3),
+                                sigma=0.01, frac=0.2) for i in range(6)]
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=6, max_outer=30, pcg_iters=4, outer_tol=1e-4)
+    ref_items = _batch(torch, probs)
+    ref = s.solve_batched(ref_items)
+    outers = sorted({r["outer_iters"] for r in ref})
+    assert len(outers) > 1
+    items = _batch(torch, probs)
+    batch = s.prepare(items)
+    for _ in range(2):
+        for it in items:
+            it["x"].zero_()
+        reps = s.solve_batched(batch)
+        assert len(reps) == len(ref)
+        for r, q in zip(reps, ref):
+            for f in ("status", "outer_iters", "pcg_iters", "converged", "F", "F_eps", "data", "rel_change"):
+                assert r[f] == q[f], f
+        for a, b in zip(ref_items, items):
+            assert torch.equal(a["x"], b["x"])

@@ -34,3 +34,32 @@ def test_binding_has_no_cpu_fallback():
     """The binding never imports the oracle."""
     src = open(os.path.join(ROOT, "paper_1411_5057_amd", "firls.py")).read()
     assert "oracle" not in src
+
+
+def test_batch_records_match_the_abi_structures():
+    """The column-wise batch marshalling writes the same bytes as filling
+    the ctypes structures one by one, and report records read back the same
+    fields (host memory only: the data pointers are of CPU tensors)."""
+    import numpy as np
+    import torch
+    from paper_1411_5057_amd import firls as F
+    b = torch.zeros(3, 16, 16, dtype=torch.complex64)
+    m = torch.zeros(3, 16, 16, dtype=torch.uint8)
+    x = torch.zeros_like(b)
+    items = [dict(b=b[i], mask=m[i] if i != 1 else None, x=x[i], lam=0.01 * (i + 1), shape_id=i % 2,
+                  x_is_init=(i == 2)) for i in range(3)]
+    want = (F.firls_slice * 3)()
+    for i, it in enumerate(items):
+        want[i] = F.firls_slice(i % 2, int(i == 2), 0.01 * (i + 1), b[i].data_ptr(),
+                                0 if i == 1 else m[i].data_ptr(), x[i].data_ptr())
+    got = F.slice_array(items)
+    assert got.tobytes() == bytes(want)
+    forced = F.slice_array(items, True)
+    assert list(forced["x_is_init"]) == [1, 1, 1]
+    reps = (F.firls_report * 2)()
+    reps[0] = F.firls_report(0, 7, 28, 1, 1.5, 1.25, 0.5, 1e-6)
+    reps[1] = F.firls_report(-5, 3, 12, 0, 2.5, 2.25, 1.5, 0.0)
+    arr = np.frombuffer(bytes(reps), dtype=F.REPORT_DTYPE)
+    assert F.report_dicts(arr) == [r.as_dict() for r in reps]
+    batch = F.Batch(items)
+    assert len(batch) == 3 and batch.slices.tobytes() == bytes(want)
