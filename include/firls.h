@@ -292,9 +292,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
  * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
 
-/* Solve batches in sub-batches of ``chunk`` slices, one after the other
- * (0: the whole batch at once).  Smaller sub-batches keep their working
- * set in the device's last-level cache. */
+/* Solve at most ``chunk`` slices at a time (0: the whole batch at once);
+ * a smaller working set stays in the device's last-level cache.  A batch
+ * of one masked-FFT shape is streamed: ``chunk`` slots start with the
+ * first slices, and a slot whose slice has stopped takes the next one in
+ * batch order at the following outer iteration, so slow slices do not hold
+ * up the rest.  Other batches run in sub-batches of ``chunk`` slices, one
+ * after the other.  Results do not depend on the setting. */
 int firls_set_chunk(firls_handle* h, int32_t chunk);
 
 /* Time a few outer iterations of these slices for candidate sub-batch sizes

@@ -116,6 +116,9 @@ struct firls_handle {
   // the kernels write to directly (coherent, mapped)
   int32_t* h_flags = nullptr;
   int32_t* d_flags = nullptr;
+  // slot refills of a streamed batch, read by k_refill (coherent, mapped)
+  RefillRec* h_refill = nullptr;
+  RefillRec* d_refill = nullptr;
   hipEvent_t ev = nullptr;
 
   // graph replay of one outer iteration's launches
@@ -191,6 +194,7 @@ void free_batch(firls_handle* h) {
   if (h->h_state) (void)hipHostFree(h->h_state);
   if (h->h_list) (void)hipHostFree(h->h_list);
   if (h->h_flags) (void)hipHostFree(h->h_flags);
+  if (h->h_refill) (void)hipHostFree(h->h_refill);
   h->ws = nullptr;
   h->ws_cap = 0;
   h->d_desc = nullptr;
@@ -200,6 +204,7 @@ void free_batch(firls_handle* h) {
   h->h_state = nullptr;
   h->h_list = nullptr;
   h->h_flags = h->d_flags = nullptr;
+  h->h_refill = h->d_refill = nullptr;
   h->cap_slices = 0;
 }
 
@@ -227,10 +232,12 @@ int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
     if (h->h_state) HIPCHK(hipHostFree(h->h_state));
     if (h->h_list) HIPCHK(hipHostFree(h->h_list));
     if (h->h_flags) HIPCHK(hipHostFree(h->h_flags));
+    if (h->h_refill) HIPCHK(hipHostFree(h->h_refill));
     h->h_desc = nullptr;
     h->h_state = nullptr;
     h->h_list = nullptr;
     h->h_flags = h->d_flags = nullptr;
+    h->h_refill = h->d_refill = nullptr;
     h->cap_slices = 0;
     HIPCHK(hipMalloc(&h->d_desc, sizeof(SliceDesc) * want));
     HIPCHK(hipMalloc(&h->d_state, sizeof(SliceState) * want));
@@ -240,6 +247,8 @@ int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
     HIPCHK(hipHostMalloc(&h->h_list, sizeof(int32_t) * 2 * want, hipHostMallocDefault));
     HIPCHK(hipHostMalloc(&h->h_flags, sizeof(int32_t) * want, hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->d_flags), h->h_flags, 0));
+    HIPCHK(hipHostMalloc(&h->h_refill, sizeof(RefillRec) * want, hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->d_refill), h->h_refill, 0));
     h->cap_slices = want;
   }
   return FIRLS_OK;
@@ -554,12 +563,15 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
 // Fold the timed launches of one run_batch into the per-class totals.
 // Units are active slices: a launch at outer iteration ``it`` counts the
 // slices of its group still active when it ran.
-int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg) {
+// act_prep[it]: slots of each shape active entering iteration it's
+// residual pass (it >= 1); act_pcg[it]: active in its PCG iterations.
+int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg,
+                 const std::vector<std::vector<int>>& act_prep) {
   for (const auto& r : h->recs) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
     int units = r.count;
-    if (r.phase == 1 && r.it > 0) units = act_pcg[r.it - 1][r.group];
+    if (r.phase == 1 && r.it > 0) units = act_prep[r.it][r.group];
     if (r.phase == 2) units = act_pcg[r.it][r.group];
     h->prof_ms[r.cls] += ms;
     h->prof_launches[r.cls] += 1;
@@ -578,27 +590,38 @@ int check_slice(const firls_handle* h, const firls_slice& sl) {
   return FIRLS_OK;
 }
 
-// The batched outer loop shared by every solve entry point (one sub-batch).
-int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
-  if (ns <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
-  if (ns > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
+// The batched outer loop shared by every solve entry point.  The first
+// ``slots`` slices start at once.  With slots < ns (a streamed batch: one
+// masked-FFT shape) each slot takes the next queued slice as soon as its
+// own slice stops, so a sub-batch never idles behind its slowest slice;
+// the final states of finished slices are kept behind the slot states.
+int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_slice* sl, firls_report* rep, int Tmax,
+              double tau) {
+  if (ns <= 0 || slots <= 0 || slots > ns) return fail(FIRLS_E_INVALID, "n_slices must be positive");
+  if (slots > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
   if (!sl || !rep) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
   for (int i = 0; i < ns; ++i) {
     int rc = check_slice(h, sl[i]);
     if (rc) return rc;
   }
-  std::vector<size_t> off(ns);
+  const bool streamed = slots < ns;
+  if (streamed) {
+    for (int i = 1; i < ns; ++i)
+      if (sl[i].shape_id != sl[0].shape_id) return fail(FIRLS_E_INVALID, "a streamed batch needs one shape");
+    if (h->shapes[sl[0].shape_id].dense) return fail(FIRLS_E_INVALID, "a streamed batch needs a masked-FFT shape");
+  }
+  std::vector<size_t> off(slots);
   size_t need = 0;
-  for (int i = 0; i < ns; ++i) {
+  for (int i = 0; i < slots; ++i) {
     off[i] = need;
     need += h->slice_bytes(h->shapes[sl[i].shape_id]);
   }
-  int rc = ensure_capacity(h, st, need, ns);
+  int rc = ensure_capacity(h, st, need, streamed ? slots + ns : slots);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(st));  // pinned staging below may still feed an earlier copy
   const int nsh = (int)h->shapes.size();
   std::vector<std::vector<int>> by_shape(nsh), zf_by_shape(nsh);
-  for (int i = 0; i < ns; ++i) {
+  for (int i = 0; i < slots; ++i) {
     fill_desc(h, h->h_desc[i], h->shapes[sl[i].shape_id], off[i], &sl[i]);
     h->h_desc[i].shape = sl[i].shape_id;
     by_shape[sl[i].shape_id].push_back(i);
@@ -618,35 +641,33 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     if (h->shapes[s].dense && !by_shape[s].empty() &&
         (rc = ensure_gemm_scratch(h, st, h->shapes[s], (int)by_shape[s].size())))
       return rc;
-  HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * slots, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
 
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int C = strip_cols(h->fp64);
-  std::vector<std::vector<int>> act_pcg;
+  std::vector<std::vector<int>> act_pcg, act_prep(1);
   h->ctx_phase = 0;
   h->ctx_it = 0;
   h->ctx_group = 0;
-  h->ctx_count = ns;
+  h->ctx_count = slots;
   {
     Params P = base_params(h, h->shapes[0], 0, h->d_list);
-    KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(ns), st);
+    KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(slots), st);
   }
-  // x^1 = A^H b for slices without a warm start (Section 3.3)
-  for (int s = 0; s < nsh; ++s) {
-    const int c = (int)zf_by_shape[s].size();
-    if (!c) continue;
+  // x^1 = A^H b for slices without a warm start (Section 3.3); ``list``
+  // holds the c slots of shape s that need it
+  auto launch_ahb = [&](int s, const int32_t* list, int c) -> int {
     const Shape& S = h->shapes[s];
-    Params P = base_params(h, S, s, h->d_list + zlo[s]);
+    Params P = base_params(h, S, s, list);
     h->ctx_group = s;
     h->ctx_count = c;
-    if (S.dense) {
-      if ((rc = launch_gemm(h, S, P, G_ATB, c, st, FIRLS_PROF_AHB))) return rc;
-    } else {
-      KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
-      KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
-    }
-  }
+    if (S.dense) return launch_gemm(h, S, P, G_ATB, c, st, FIRLS_PROF_AHB);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->col[COL_AHB], P, dim3(S.col_wgs(h->fp64), c), st);
+    KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
+    return FIRLS_OK;
+  };
+  for (int s = 0; s < nsh; ++s)
+    if (!zf_by_shape[s].empty() && (rc = launch_ahb(s, h->d_list + zlo[s], (int)zf_by_shape[s].size()))) return rc;
   auto enqueue_prep = [&]() -> int {
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
@@ -705,22 +726,27 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       h->gkey = key;
     }
   }
-  // The outer check of each slice writes (evaluations << 1) | active to
-  // host memory at the start of every iteration.  Before launching
-  // iteration it the host polls for iteration it - 1's words, so the GPU
-  // works through that iteration's PCG launches meanwhile; once no slice is
-  // active nothing more is launched, and only the PCG launches of the last
-  // iteration run empty (kernels of stopped slices exit at once).
-  for (int i = 0; i < ns; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
+  // The outer check of each slot writes (evaluations << 1) | active to host
+  // memory at the start of every iteration.  Before launching iteration it
+  // the host polls for iteration it - 1's words, so the GPU works through
+  // that iteration's PCG launches meanwhile; once no slot is active (and no
+  // slice is queued) nothing more is launched, and only the PCG launches of
+  // the last iteration run empty (kernels of stopped slices exit at once).
+  // A slot refilled at iteration k has made it - k evaluations by then.
+  std::vector<int> slot_slice(slots), start_it(slots, 0), fin(ns, -1);
+  std::vector<char> settled(slots, 0);   // stopped, queue empty: its slice's state stays in the slot
+  for (int i = 0; i < slots; ++i) slot_slice[i] = i;
+  int next = slots;   // next queued slice
+  for (int i = 0; i < slots; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
   auto read_active = [&](int j, bool& done) {
     std::vector<int> cnt(nsh, 0);
     int active = 0;
     done = true;
-    for (int i = 0; i < ns; ++i) {
+    for (int i = 0; i < slots; ++i) {
       const int32_t w = __atomic_load_n(h->h_flags + i, __ATOMIC_ACQUIRE);
-      if ((w & 1) && (w >> 1) <= j) done = false;
+      if ((w & 1) && (w >> 1) <= j - start_it[i]) done = false;
       active += w & 1;
-      cnt[sl[i].shape_id] += w & 1;
+      cnt[sl[slot_slice[i]].shape_id] += w & 1;
     }
     if (done) act_pcg.push_back(cnt);
     return active;
@@ -742,15 +768,52 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
       return fail(FIRLS_E_HIP, "an outer check did not report");
     }
   };
-  bool stopped = false;
-  for (int it = 0; it <= Tmax; ++it) {
-    if (it >= 1) {
-      int active = 0;
-      if ((rc = wait_checks(it - 1, active))) return rc;
-      if (!active) {
-        stopped = true;
-        break;
+  // Streamed batches: slots whose slice stopped take the next queued slices
+  // at once (zero-filled starts first, so they form a prefix of the refill
+  // list).  Waiting to refill several slots together measured slower: an
+  // iteration's time does not shrink in proportion to its idle slots.
+  int32_t* d_refill_list = h->d_list + 2 * slots;
+  auto refill = [&](int it, int& count) -> int {
+    count = 0;
+    std::vector<RefillRec> zf, given;
+    for (int i = 0; i < slots; ++i) {
+      if (settled[i] || (__atomic_load_n(h->h_flags + i, __ATOMIC_ACQUIRE) & 1)) continue;
+      const int old = slot_slice[i];
+      if (next >= ns) {
+        settled[i] = 1;
+        fin[old] = i;
+        continue;
       }
+      const firls_slice& q = sl[next];
+      RefillRec r{q.b, q.mask, q.x, q.lambda, i, old};
+      (q.x_is_init ? given : zf).push_back(r);
+      fin[old] = slots + old;
+      slot_slice[i] = next++;
+      start_it[i] = it;
+      __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
+    }
+    count = (int)(zf.size() + given.size());
+    if (!count) return FIRLS_OK;
+    std::copy(zf.begin(), zf.end(), h->h_refill);
+    std::copy(given.begin(), given.end(), h->h_refill + zf.size());
+    RefillArgs A{h->d_refill, count, slots, h->d_desc, h->d_state, d_refill_list};
+    HIPCHK(launch_refill(A, st));
+    h->ctx_phase = 0;
+    int r2;
+    if (!zf.empty() && (r2 = launch_ahb(sl[0].shape_id, d_refill_list, (int)zf.size()))) return r2;
+    return FIRLS_OK;
+  };
+  const long max_it = (long)ns * (Tmax + 1) + 1;
+  for (int it = 0;; ++it) {
+    if (it > max_it) return fail(FIRLS_E_HIP, "the outer loop did not end");
+    if (it >= 1) {
+      int active = 0, added = 0;
+      if ((rc = wait_checks(it - 1, active))) return rc;
+      if (streamed && (rc = refill(it, added))) return rc;
+      if (!active && !added) break;
+      std::vector<int> cnt = act_pcg.back();
+      cnt[sl[0].shape_id] += added;
+      act_prep.push_back(cnt);
     }
     h->ctx_it = it;
     if (graphs) {
@@ -763,16 +826,15 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     }
     HIPCHK(hipEventRecord(h->ev, st));
   }
-  if (!stopped) {
-    int active = 0;
-    if ((rc = wait_checks(Tmax, active))) return rc;
-  }
   HIPCHK(hipStreamSynchronize(st));
-  if (h->profiling && (rc = prof_collect(h, act_pcg))) return rc;
-  HIPCHK(hipMemcpy(h->h_state, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToHost));
+  if (h->profiling && (rc = prof_collect(h, act_pcg, act_prep))) return rc;
+  for (int i = 0; i < slots; ++i)
+    if (!settled[i]) fin[slot_slice[i]] = i;
+  const int nstate = streamed ? slots + ns : slots;
+  HIPCHK(hipMemcpy(h->h_state, h->d_state, sizeof(SliceState) * nstate, hipMemcpyDeviceToHost));
   int worst = FIRLS_OK;
   for (int i = 0; i < ns; ++i) {
-    const SliceState& S = h->h_state[i];
+    const SliceState& S = h->h_state[fin[i]];
     firls_report& r = rep[i];
     r.status = S.status;
     r.outer_iters = S.outer;
@@ -789,10 +851,12 @@ int run_chunk(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
   return worst;
 }
 
-// Runs the slices in sub-batches of h->chunk (all at once when 0) on the
-// caller's stream, or on the library's own stream ordered after the null
-// stream when the caller passes the null stream (graphs need a capturable
-// stream).
+// Runs the slices on the caller's stream, or on the library's own stream
+// ordered after the null stream when the caller passes the null stream
+// (graphs need a capturable stream).  With a sub-batch size h->chunk below
+// the batch size, a batch of one masked-FFT shape is streamed through
+// h->chunk slots; other batches run in sub-batches of h->chunk one after
+// the other (all at once when 0).
 int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, firls_report* rep, int Tmax, double tau) {
   hipStream_t ws = st;
   if (!st && h->use_graphs) {
@@ -804,13 +868,21 @@ int run_batch(firls_handle* h, hipStream_t st, int ns, const firls_slice* sl, fi
     HIPCHK(hipStreamWaitEvent(h->own, h->ev_in, 0));
     ws = h->own;
   }
-  const int chunk = h->chunk > 0 ? h->chunk : ns;
+  const int chunk = h->chunk > 0 ? std::min(h->chunk, ns) : ns;
+  bool one_shape = ns > 0 && sl != nullptr;
+  for (int i = 1; one_shape && i < ns; ++i) one_shape = sl[i].shape_id == sl[0].shape_id;
   int worst = FIRLS_OK;
-  for (int c0 = 0; c0 < ns; c0 += chunk) {
-    const int cn = std::min(chunk, ns - c0);
-    int rc = run_chunk(h, ws, cn, sl + c0, rep + c0, Tmax, tau);
-    if (rc < 0) return rc;
-    worst = std::max(worst, rc);
+  if (chunk < ns && one_shape && sl[0].shape_id >= 0 && sl[0].shape_id < (int)h->shapes.size() &&
+      !h->shapes[sl[0].shape_id].dense) {
+    worst = run_chunk(h, ws, chunk, ns, sl, rep, Tmax, tau);
+    if (worst < 0) return worst;
+  } else {
+    for (int c0 = 0; c0 < ns; c0 += chunk) {
+      const int cn = std::min(chunk, ns - c0);
+      int rc = run_chunk(h, ws, cn, cn, sl + c0, rep + c0, Tmax, tau);
+      if (rc < 0) return rc;
+      worst = std::max(worst, rc);
+    }
   }
   if (ws != st) HIPCHK(hipStreamSynchronize(ws));
   return worst;

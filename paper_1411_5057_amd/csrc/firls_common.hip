@@ -8,14 +8,11 @@ namespace firls {
 
 // rho = (number of sampled entries) / n^2, the mean (indeed every entry) of
 // diag(A^H A) for the unitary F (Section 5.4), and a fresh outer-loop state.
-__global__ __launch_bounds__(NT) void k_slice_init(Params P) {
-  __shared__ double red[NT / 64];
-  const int s = P.list[blockIdx.x];
-  const SliceDesc& D = P.desc[s];
+// One workgroup per slice; ``mask`` is the slice's mask (D.mask).
+__device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& S, double* red) {
   if (D.rho_fixed > 0.0) {
     // dense sensing matrix: rho = mean diag(A^T A), set by the host; no mask
     if (threadIdx.x == 0) {
-      SliceState& S = P.state[s];
       S.rho = D.rho_fixed;
       S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
       S.active = 1;
@@ -31,7 +28,7 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   const int words = total / 16;
   for (int w = threadIdx.x; w < words; w += NT) {
     const int c16 = w / rows, row = w - c16 * rows;
-    const uint8_t* src = D.mask + (size_t)row * n + c16 * 16;
+    const uint8_t* src = mask + (size_t)row * n + c16 * 16;
     unsigned int bits = 0;
 #pragma unroll
     for (int c = 0; c < 16; ++c) bits |= (src[c] != 0 ? 1u : 0u) << c;
@@ -40,12 +37,42 @@ __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   }
   cnt = block_sum(cnt, red);
   if (threadIdx.x == 0) {
-    SliceState& S = P.state[s];
     S.rho = cnt / (double)total;
     S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
     S.active = 1;
     S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
   }
+}
+
+__global__ __launch_bounds__(NT) void k_slice_init(Params P) {
+  __shared__ double red[NT / 64];
+  const int s = P.list[blockIdx.x];
+  init_slice(P.desc[s], P.desc[s].mask, P.state[s], red);
+}
+
+// Slot refills of a streamed batch, one workgroup per record: save the
+// stopped slice's final state, give the slot the new slice's inputs (the
+// slot's workspace pointers stay) and start the new slice's outer loop.
+__global__ __launch_bounds__(NT) void k_refill(RefillArgs A) {
+  __shared__ double red[NT / 64];
+  const RefillRec r = A.rec[blockIdx.x];
+  SliceDesc& D = A.desc[r.slot];
+  SliceState& S = A.state[r.slot];
+  if (threadIdx.x == 0) {
+    if (r.old >= 0) A.state[A.final_base + r.old] = S;
+    D.b = r.b;
+    D.mask = r.mask;
+    D.x = r.x;
+    D.lambda = r.lambda;
+    A.list[blockIdx.x] = r.slot;
+  }
+  init_slice(D, r.mask, S, red);
+}
+
+hipError_t launch_refill(const RefillArgs& A, hipStream_t st) {
+  const LaunchTiming& t = launch_timing();
+  launch_kernel(k_refill, dim3(A.count), dim3(NT), 0, st, t.start, t.stop, A);
+  return hipGetLastError();
 }
 
 // Objective of the current x and the outer stopping rule.  F_eps = data +

@@ -50,6 +50,10 @@ struct GemmKernels {
 };
 const GemmKernels* gemm_kernels(bool fp64);
 
+// Saves the final states of stopped slices, points their slots at new
+// slices and starts those (as k_slice_init does); one workgroup per record.
+hipError_t launch_refill(const RefillArgs& A, hipStream_t st);
+
 // nullptr if the size is not built for that precision.
 const SizeKernels* size_kernels(bool fp64, int n);
 const PrecKernels* prec_kernels(bool fp64);

@@ -97,6 +97,27 @@ struct SliceState {
                      // (folded into the next residual row pass)
 };
 
+// One slot refill of a streamed batch (a sub-batch whose slots take the
+// next queued slice as soon as theirs stops): the stopped slice ``old``
+// (>= 0) has its final state saved at state[final_base + old], and the slot
+// takes the inputs of the new slice.
+struct RefillRec {
+  const void* b;
+  const uint8_t* mask;
+  void* x;
+  double lambda;
+  int32_t slot;
+  int32_t old;
+};
+struct RefillArgs {
+  const RefillRec* rec;   // host-mapped, ``count`` records
+  int32_t count;
+  int32_t final_base;
+  SliceDesc* desc;
+  SliceState* state;
+  int32_t* list;          // out: the refilled slots, in record order
+};
+
 // Group map of one shape on the device (internal coefficient indices).
 constexpr int ELL_MAX = 8;        // widest padded group / membership list
 
