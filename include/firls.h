@@ -288,7 +288,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
  * once as a HIP graph and replayed (enable = 0 launches them directly).
  * Either way the host launches iteration k + 1 once the stop test of
  * iteration k has reported, through host-mapped memory, while the GPU runs
- * iteration k's PCG launches.  With the null stream the library works on its
+ * iteration k's PCG launches (the calling thread busy-waits for it).  With the null stream the library works on its
  * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
 

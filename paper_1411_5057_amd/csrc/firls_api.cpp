@@ -739,16 +739,20 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
   int next = slots;   // next queued slice
   for (int i = 0; i < slots; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
   auto read_active = [&](int j, bool& done) {
-    std::vector<int> cnt(nsh, 0);
-    int active = 0;
     done = true;
-    for (int i = 0; i < slots; ++i) {
+    for (int i = 0; i < slots && done; ++i) {
       const int32_t w = __atomic_load_n(h->h_flags + i, __ATOMIC_ACQUIRE);
       if ((w & 1) && (w >> 1) <= j - start_it[i]) done = false;
-      active += w & 1;
-      cnt[sl[slot_slice[i]].shape_id] += w & 1;
     }
-    if (done) act_pcg.push_back(cnt);
+    if (!done) return 0;
+    std::vector<int> cnt(nsh, 0);
+    int active = 0;
+    for (int i = 0; i < slots; ++i) {
+      const int32_t w = __atomic_load_n(h->h_flags + i, __ATOMIC_ACQUIRE) & 1;
+      active += w;
+      cnt[sl[slot_slice[i]].shape_id] += w;
+    }
+    act_pcg.push_back(cnt);
     return active;
   };
   // Polls until iteration j's outer checks have all reported.  The event
