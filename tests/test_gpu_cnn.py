@@ -125,6 +125,13 @@ def test_learned_solve_reaches_oracle_optimum():
         assert r["F_eps"] == q["F_eps"] and r["outer_iters"] == q["outer_iters"]
     for a, b in zip(items, items2):
         assert torch.equal(a["x"], b["x"])
+    # one streamed slot taking the three slices in turn: the same results
+    s.set_chunk(1)
+    items3 = [dict(it, x=torch.zeros_like(it["x"])) for it in items]
+    reps3, used3 = s.solve_batched_learned(net, items3)
+    assert list(used3) == list(used) and reps3 == reps
+    for a, b in zip(items, items3):
+        assert torch.equal(a["x"], b["x"])
 
 
 def test_bad_network_falls_back_to_zero_filled():

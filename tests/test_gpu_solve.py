@@ -163,6 +163,14 @@ def test_batched_uneven_mixed():
         fe = ops.objective(to_np(it["x"]))[0]
         assert abs(fe - ref.F_eps) <= 1e-5 * ref.F_eps
         assert rep["outer_iters"] == T
+    # a sub-batch size below the batch size: mixed shapes run in sub-batches
+    # one after the other, with the same results
+    s.set_chunk(2)
+    items2 = [dict(it, x=torch.zeros_like(it["x"])) for it in items]
+    reps2 = s.solve_batched(items2)
+    assert reps2 == reps
+    for a, b in zip(items, items2):
+        assert torch.equal(a["x"], b["x"])
 
 
 def test_deterministic():
