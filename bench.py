@@ -42,12 +42,17 @@ HBM_PEAK_GBS = 8000.0
 #   col    : read t, mask bits; write t
 #   rowinv : read t, p, d; write q
 #   update : read x, p, q, r, d; write x, r
-def bytes_per_px(cls: str, K: int, fused: bool = True) -> float:
+def bytes_per_px(cls: str, K: int, fused: bool = True, paired: bool = False) -> float:
     """Algorithmic HBM bytes per pixel of one launch of a kernel class.
     ``fused``: the paper's preconditioner, whose residual passes also carry
-    the last PCG step's x update and the first one's z0, p0 and row FFT."""
+    the last PCG step's x update and the first one's z0, p0 and row FFT.
+    ``paired``: the row inverse of iterations 0 .. K-2 rides in the step's
+    launch ("update": read t, p, x, r, d; write x, r, p, t, also 68 B), so
+    the row-inverse class is only the last iteration's launch."""
     if not fused and cls in ("r0_rowfwd", "r0_rowinv"):
         return {"r0_rowfwd": 20.0, "r0_rowinv": 28.0}[cls]
+    if fused and cls == "rowinv":
+        return 20.0 if paired else 28.0 - 8.0 / K    # the last iteration's q is not written
     return {
         "rowfwd": 28.0,        # first iteration: read r, d; write p, t
         "col": 16.125,         # read t, mask bits; write t
@@ -92,6 +97,8 @@ def parse():
                          "profiler runs pin the unprofiled choice, since the profiler skews the trials")
     ap.add_argument("--launch", choices=("graphs", "direct"), default=None,
                     help="launch mode instead of the autotuner's choice (with --sub-batch)")
+    ap.add_argument("--no-pair", action="store_true",
+                    help="run the PCG row-inverse pass and the step as two launches (A/B of the paired pass)")
     ap.add_argument("--workload", choices=("mri", "dense"), default="mri",
                     help="mri: the 256^2 CS-MRI benchmark (default); dense: 64^2 images measured by one "
                          "shared dense random projection (30%% of N rows), the MFMA path")
@@ -167,13 +174,14 @@ def roofline_of(prof, n, K, dt, slices, fused=True):
     ``slices`` solves of the instrumented step each start with one residual
     pass that has no x update to fold in."""
     npx = n * n
-    tot_bytes = sum(bytes_per_px(c, K, fused) * v["slice_launches"] * npx for c, v in prof.items())
+    paired = fused and 0 < prof.get("rowinv", {}).get("launches", 0) < prof.get("col", {}).get("launches", 0)
+    tot_bytes = sum(bytes_per_px(c, K, fused, paired) * v["slice_launches"] * npx for c, v in prof.items())
     if prof.get("r0_rowfwd", {}).get("launches", 0) and not prof.get("last_x", {}).get("launches", 0):
         tot_bytes -= 16.0 * npx * slices
     pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update", "last_x")}
     dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
     v = prof[dom]
-    per_launch_bytes = bytes_per_px(dom, K, fused) * npx * v["slice_launches"] / v["launches"]
+    per_launch_bytes = bytes_per_px(dom, K, fused, paired) * npx * v["slice_launches"] / v["launches"]
     avg_s = v["ms"] / v["launches"] / 1e3
     ach = per_launch_bytes / avg_s / 1e9
     tr = traffic_record()
@@ -297,6 +305,7 @@ def main():
                       outer_tol=a.tau, eps=1e-10, precond=pc)
     x = torch.zeros_like(b)
     items = [dict(b=b[i], mask=m[i], x=x[i], lam=lams[i]) for i in range(B)]
+    solver.set_paired(not a.no_pair)
     if a.sub_batch >= 0:
         chunk = a.sub_batch
         solver.set_chunk(chunk)

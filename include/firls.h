@@ -53,6 +53,8 @@ enum {
   FIRLS_E_HIP = -3,          /* a HIP runtime call failed */
   FIRLS_E_NOMEM = -4,        /* device allocation failed */
   FIRLS_E_NONFINITE = -5,    /* objective became NaN or Inf */
+  FIRLS_E_SYNC = -6,         /* workgroups of a slice did not meet at a barrier
+                                within its time limit (internal error) */
   FIRLS_W_MAXITER = 1        /* stopped at max_outer before the tolerance */
 };
 
@@ -291,6 +293,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
  * iteration k's PCG launches (the calling thread busy-waits for it).  With the null stream the library works on its
  * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
+
+/* Haar with the paper's preconditioner (FP32, image sides up to 256): the row
+ * inverse pass of PCG iteration k - 1 and the step of iteration k run in
+ * one launch, the workgroups of a slice meeting at a barrier in between,
+ * so q stays on chip (default).  enable = 0 runs them as two launches;
+ * results are bitwise the same. */
+int firls_set_paired(firls_handle* h, int32_t enable);
 
 /* Solve at most ``chunk`` slices at a time (0: the whole batch at once);
  * a smaller working set stays in the device's last-level cache.  A batch

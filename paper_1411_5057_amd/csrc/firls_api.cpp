@@ -123,6 +123,8 @@ struct firls_handle {
 
   // graph replay of one outer iteration's launches
   bool use_graphs = true;
+  // the paired PCG pass (row inverse of k - 1 and step of k in one launch)
+  bool use_pair = true;
   hipStream_t own = nullptr;          // work stream when the caller passes the null stream
   hipEvent_t ev_in = nullptr;
   struct GraphKey {
@@ -533,10 +535,13 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
   const bool fused = haar && h->cfg.precond == FIRLS_PC_PAPER;
   const dim3 rows(s.row_wgs(), c);
   const int K = h->cfg.pcg_iters;
+  // the row inverse of iteration k - 1 rides in the launch of step k
+  const bool pair = fused && !s.dense && s.sk->pcg_pair && h->use_pair;
   for (int k = 0; k < K; ++k) {
     P.k = k;
     if (fused) {
-      if (k > 0) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
+      if (k > 0 && pair) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->pcg_pair, P, rows, st);
+      else if (k > 0) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->rowfwd[RF_STEP_HAAR], P, rows, st);
       else if (!p0_in_prep(h, s)) KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
     } else if (haar) {
       KLAUNCH(h, FIRLS_PROF_ROWFWD, s.sk->rowfwd[RF_PCG_HAAR], P, rows, st);
@@ -549,7 +554,12 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     } else {
       KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.col_wgs(h->fp64), c), st);
     }
-    KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
+    // the fused step reads q of iterations 0 .. K-2 only
+    if (!pair || k == K - 1) {
+      P.q_dead = fused && k == K - 1 ? 1 : 0;
+      KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
+      P.q_dead = 0;
+    }
     if (haar && !fused) KLAUNCH(h, FIRLS_PROF_UPDATE, s.sk->update_haar, P, rows, st);
     if (!haar) KLAUNCH(h, FIRLS_PROF_UPDATE, pk->update_tv[UP_STEP], P, dim3(P.nrz, c), st);
   }
@@ -851,7 +861,8 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     if (S.status < 0 && (worst >= 0 || S.status < worst)) worst = S.status;
     else if (worst >= 0 && S.status > worst) worst = S.status;
   }
-  if (worst < 0) g_err = "a slice's objective became non-finite";
+  if (worst == FIRLS_E_SYNC) g_err = "workgroups of a slice missed a barrier (internal error)";
+  else if (worst < 0) g_err = "a slice's objective became non-finite";
   return worst;
 }
 
@@ -1556,6 +1567,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
 int firls_set_graphs(firls_handle* h, int32_t enable) {
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
   h->use_graphs = enable != 0;
+  drop_graphs(h);
+  return FIRLS_OK;
+}
+
+int firls_set_paired(firls_handle* h, int32_t enable) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  h->use_pair = enable != 0;
   drop_graphs(h);
   return FIRLS_OK;
 }

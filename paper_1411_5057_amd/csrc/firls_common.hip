@@ -10,6 +10,9 @@ namespace firls {
 // diag(A^H A) for the unitary F (Section 5.4), and a fresh outer-loop state.
 // One workgroup per slice; ``mask`` is the slice's mask (D.mask).
 __device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& S, double* red) {
+  // the paired PCG pass's barrier counters count from zero for each slice
+  uint32_t* sync = reinterpret_cast<uint32_t*>(slot_wptr(D, SLOT_SYNC));
+  for (int k = threadIdx.x; k < KMAX; k += NT) sync[k] = 0u;
   if (D.rho_fixed > 0.0) {
     // dense sensing matrix: rho = mean diag(A^T A), set by the host; no mask
     if (threadIdx.x == 0) {

@@ -593,6 +593,15 @@ __device__ __forceinline__ double slot_sum(const double* slot, int count) {
   return wave_sum(v);
 }
 
+// The same over partials that other workgroups of the running launch wrote
+// with device-coherent stores (loads that bypass non-coherent caches).
+__device__ __forceinline__ double slot_sum_coherent(const double* slot, int count) {
+  double v = 0.0;
+  for (int i = threadIdx.x & 63; i < count; i += 64)
+    v += __hip_atomic_load(slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return wave_sum(v);
+}
+
 __device__ __forceinline__ const double* slot_ptr(const SliceDesc& D, int s) { return D.parts + (size_t)s * PMAX; }
 __device__ __forceinline__ double* slot_wptr(const SliceDesc& D, int s) { return D.parts + (size_t)s * PMAX; }
 

@@ -45,6 +45,10 @@ hipError_t L_last_x(const Params& P, dim3 g, hipStream_t st) {
   return launch_dyn(k_last_x<T, N>, 0, P, g, st);
 }
 template <typename T, int N>
+hipError_t L_pcg_pair(const Params& P, dim3 g, hipStream_t st) {
+  return launch_dyn(k_pcg_pair<T, N>, lds_bytes<T, N>(), P, g, st);
+}
+template <typename T, int N>
 hipError_t L_psi_sq_haar(const Params& P, dim3 g, hipStream_t st) {
   return launch_dyn(k_psi_sq_haar<T, N>, 0, P, g, st);
 }
@@ -75,6 +79,10 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
   allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
+  // FP32 only: in FP64 the two phases' registers would not fit four
+  // workgroups per CU
+  constexpr bool pair = Units<N, band_rows(N)>::PER == 1 && sizeof(T) == 4;
+  if constexpr (pair) allow_lds(k_pcg_pair<T, N>, b);
   SizeKernels k{};
   k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;
   k.rowfwd[RF_PCG_HAAR] = L_rowfwd<T, N, RF_PCG_HAAR>;
@@ -96,6 +104,7 @@ SizeKernels make_size_kernels() {
   k.psi_sq_haar = L_psi_sq_haar<T, N>;
   k.last_x = L_last_x<T, N>;
   k.update_haar = L_update_haar<T, N>;
+  if constexpr (pair) k.pcg_pair = L_pcg_pair<T, N>;
   return k;
 }
 

@@ -656,10 +656,13 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
           w[s] = w[s] * (ld * sgn);
         }
         haar_col<true>(w, P.L, col);
+        // q of the fused step's last iteration is never read: the next
+        // residual pass needs only alpha (from the sums) and p
+        const bool keep = !(SP && P.q_dead);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const C o = lds[Lay::at(row + s, col)] + w[s];
-          out[(row + s) * N + col] = o;
+          if (keep) out[(row + s) * N + col] = o;
           w[s] = o;
         }
         // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
@@ -713,6 +716,170 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[blockIdx.x] = tot;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// The row-inverse pass of PCG iteration k - 1 and the fused step of
+// iteration k in one launch (Haar, the paper's preconditioner, FFT
+// operator; one row band per workgroup, one tile column per thread):
+//   A: q = S p_{k-1} (row inverse FFT of the column pass's output plus
+//      lambda Phi^T (d * Phi p)), the partials of <p, S p> and
+//      <q, P^{-1} q>;
+//   a barrier among the workgroups of the slice (their partials complete
+//      alpha and the beta recurrence);
+//   B: x += alpha p, r -= alpha q, z = P^{-1} r, <r, z>, p_k = z + beta p,
+//      and the row FFT of p_k.
+// q waits in the thread's own LDS cells across the barrier (where A^H A p
+// was), so it never goes through memory; B reads p again (the band was
+// just read, so it comes from cache).  The barrier counts arrivals in the
+// slice's counter k, which grows by one band count per outer iteration
+// (zeroed when the slice starts); the partials it publishes are the only
+// data that crosses workgroups, written and read device-coherently, so no
+// cache write-back or invalidation is needed.  Workgroups start in index
+// order and a slice's bands are consecutive, so the workgroups that wait
+// never hold back one that a slice still needs.  The wait is bounded: past
+// the limit the slice is marked FIRLS_E_SYNC and the workgroup goes on.
+// Three workgroups per CU: at four the two phases' registers spill, and
+// without the bound the compiler takes enough for only two.
+template <typename T, int N>
+__global__ __launch_bounds__(NT, 3) void k_pcg_pair(Params P) {
+  constexpr int ROWS = band_rows(N);
+  using C = cplx<T>;
+  using Lay = LdsLayout<N>;
+  using U = Units<N, ROWS>;
+  static_assert(U::PER == 1, "one tile column per thread");
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  __shared__ double red[NT / 64];
+  __shared__ int timed_out;
+  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  const int row0 = blockIdx.x * ROWS;
+  const size_t off = (size_t)row0 * N;
+  const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
+  const int k = P.k;
+  const bool mine = U::valid(0);
+  const int col = U::col(0), row = U::row(0);
+  const T* d = static_cast<const T*>(D.d) + off;
+  const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
+  C* p = static_cast<C*>(D.p) + off;
+  // A: the row inverse of iteration k - 1
+  {
+    const C* tin = static_cast<const C*>(D.t);
+    fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, [&](int l, int q) { return tin[t_index<T, N>(row0 + l, q)]; },
+                                        LdsIO<T, N>{lds});
+    // keep the loads below from being hoisted into the FFT, where their
+    // registers would push the kernel under four workgroups per CU
+    __builtin_amdgcn_sched_barrier(0);
+    double acc = 0.0, acc2 = 0.0;
+    if (mine) {
+      C w[16];
+      T dv[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        w[s] = p[(row + s) * N + col];
+        dv[s] = d[(row + s) * N + col];
+      }
+      haar_col<false>(w, P.L, col);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const T ld = lam * dv[s];
+        acc += (double)(ld * cabs2t(w[s]));
+        w[s] = w[s] * ld;
+      }
+      haar_col<true>(w, P.L, col);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const int a = Lay::at(row + s, col);
+        w[s] = lds[a] + w[s];
+        lds[a] = w[s];
+      }
+      precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
+    }
+    // the partials other workgroups read in B go out as device-coherent
+    // stores; nothing else crosses workgroups, so the barrier needs no
+    // cache write-back or invalidation
+    const double t2 = block_sum(acc2, red);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slot_wptr(D, SLOT_QQ0 + k - 1) + blockIdx.x, t2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slot_wptr(D, SLOT_PQ0 + k - 1) + blockIdx.x, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // barrier among the slice's workgroups: the partial stores complete, the
+  // arrival is counted, then the wait for the rest
+  if (threadIdx.x == 0) {
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(slot_wptr(D, SLOT_SYNC)) + k;
+    const uint32_t target = gridDim.x * (uint32_t)P.state[s_].outer;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int late = 0;
+    for (uint32_t spin = 0; __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spin) {
+      if (spin >= (1u << 20)) {
+        late = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    timed_out = late;
+  }
+  __syncthreads();
+  if (timed_out && threadIdx.x == 0) P.state[s_].status = -6;   // FIRLS_E_SYNC
+  // B: the step of iteration k (this launch's partials read device-coherently)
+  const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + k - 1), P.nrz);
+  const double pqo = slot_sum_coherent(slot_ptr(D, SLOT_PQ0 + k - 1), P.npq);
+  const double qqo = slot_sum_coherent(slot_ptr(D, SLOT_QQ0 + k - 1), P.nrz);
+  const double ald = pqo > 0.0 ? rzo / pqo : 0.0;
+  const double rzn = ald * ald * qqo - rzo;
+  const T al = (T)ald;
+  const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
+  double acc = 0.0;
+  if (mine) {
+    // the tile column's indices again, opaque to the compiler, so the
+    // addresses of A are not kept alive through the barrier for reuse here
+    int cb = col, rb = row;
+    asm volatile("" : "+v"(cb), "+v"(rb));
+    C* x = static_cast<C*>(D.x) + off;
+    C* r = static_cast<C*>(D.r[0]) + off;
+    C v[16];
+    // loads ahead of the stores, in chunks (the compiler cannot prove that
+    // x and r do not overlap)
+    constexpr int CH = 8;
+#pragma unroll
+    for (int s0 = 0; s0 < 16; s0 += CH) {
+      C xo[CH], po[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int g = (rb + s0 + u) * N + cb;
+        po[u] = p[g];
+        xo[u] = x[g];
+        v[s0 + u] = r[g];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int g = (rb + s0 + u) * N + cb;
+        const int a = Lay::at(rb + s0 + u, cb);
+        const C qo = lds[a];
+        lds[a] = po[u];   // p_{k-1} waits in the cell of q until beta p is added
+        x[g] = xo[u] + po[u] * al;
+        v[s0 + u] = v[s0 + u] - qo * al;
+        r[g] = v[s0 + u];
+      }
+    }
+    precond_tile_k<true, N, PC_PAPER>(v, d + rb * N + cb, P.L, cb, rho, lam, acc);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int a = Lay::at(rb + s, cb);
+      const C pn = v[s] + lds[a] * bs;
+      p[(rb + s) * N + cb] = pn;
+      lds[a] = pn;
+    }
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + k)[blockIdx.x] = tot;
+  C* t = static_cast<C*>(D.t);
+  fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
+                                       [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; });
 }
 
 // ---------------------------------------------------------------------------

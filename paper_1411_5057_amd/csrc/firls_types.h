@@ -30,7 +30,8 @@ enum Slot : int {
                       // then ||A p_k||^2 partials of the column pass)
   SLOT_RZ0 = 3 + KMAX,  // <r_k, z_k>, k = 0..KMAX
   SLOT_QQ0 = 4 + 2 * KMAX,  // <q_k, P^{-1} q_k>, k = 0..KMAX-1 (Haar)
-  SLOT_COUNT = 4 + 3 * KMAX
+  SLOT_SYNC = 4 + 3 * KMAX,  // uint32 barrier counters k = 0..KMAX-1 of the paired PCG pass
+  SLOT_COUNT = 5 + 3 * KMAX
 };
 
 enum Psi : int { PSI_HAAR = 0, PSI_TV = 1 };
@@ -90,7 +91,7 @@ struct SliceState {
   int32_t active;    // 1 while the slice still iterates
   int32_t outer;     // reweighted solves done
   int32_t pcg;       // PCG iterations done
-  int32_t status;    // 0, FIRLS_W_MAXITER, FIRLS_E_NONFINITE
+  int32_t status;    // 0, FIRLS_W_MAXITER, FIRLS_E_NONFINITE, FIRLS_E_SYNC
   int32_t converged;
   int32_t evals;     // objective evaluations done
   int32_t pend;      // x += alpha p of the last PCG iteration not yet applied
@@ -153,6 +154,7 @@ struct Params {
   int32_t L;             // Haar levels
   int32_t k;             // PCG iteration index
   int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
+  int32_t q_dead;        // PCG row inverse: nothing reads this q (the last iteration of the fused step)
   int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs
   int32_t check_r0;      // ... and its first workgroup runs the outer check (Haar)
   int32_t K;             // PCG iterations per outer iteration

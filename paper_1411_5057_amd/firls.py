@@ -41,7 +41,7 @@ EXPORTED = (
     "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
-    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_autotune",
+    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_autotune",
 )
 PROF_CLASSES = 15
 
@@ -158,6 +158,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_last_error": ([], ctypes.c_char_p),
         "firls_set_graphs": ([vp, i32], ctypes.c_int),
         "firls_set_chunk": ([vp, i32], ctypes.c_int),
+        "firls_set_paired": ([vp, i32], ctypes.c_int),
         "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
@@ -503,6 +504,9 @@ class Solver:
 
     def set_chunk(self, chunk: int):
         _check(load().firls_set_chunk(self.handle, int(chunk)), "firls_set_chunk")
+
+    def set_paired(self, enable: bool):
+        _check(load().firls_set_paired(self.handle, int(enable)), "firls_set_paired")
 
     def autotune(self, items: List[dict], stream=None) -> int:
         """Picks the sub-batch size (returned) and the launch mode (kept in
