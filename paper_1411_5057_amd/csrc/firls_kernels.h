@@ -739,10 +739,12 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 // order and a slice's bands are consecutive, so the workgroups that wait
 // never hold back one that a slice still needs.  The wait is bounded: past
 // the limit the slice is marked FIRLS_E_SYNC and the workgroup goes on.
-// Three workgroups per CU: at four the two phases' registers spill, and
-// without the bound the compiler takes enough for only two.
+// Four workgroups per CU, as the other row passes: the two phases then
+// spill a few registers (68 bytes per thread, cache resident), which
+// measured faster than three workgroups per CU without spills (without
+// the bound the compiler takes registers for only two).
 template <typename T, int N>
-__global__ __launch_bounds__(NT, 3) void k_pcg_pair(Params P) {
+__global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
@@ -844,7 +846,7 @@ __global__ __launch_bounds__(NT, 3) void k_pcg_pair(Params P) {
     C v[16];
     // loads ahead of the stores, in chunks (the compiler cannot prove that
     // x and r do not overlap)
-    constexpr int CH = 8;
+    constexpr int CH = 4;
 #pragma unroll
     for (int s0 = 0; s0 < 16; s0 += CH) {
       C xo[CH], po[CH];
