@@ -1467,9 +1467,9 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     off[i] = wneed;
     wneed += h->slice_bytes(h->shapes[slices[i].shape_id]);
   }
-  int rc = ensure_capacity(h, st, wneed, ns);
+  int rc = ensure_capacity(h, st, wneed, 2 * ns);   // room for two staged desc sets
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipStreamSynchronize(st));   // an earlier copy may still read the pinned staging
   const int nsh = (int)h->shapes.size();
   std::vector<std::vector<int>> by_shape(nsh);
   for (int i = 0; i < ns; ++i) by_shape[slices[i].shape_id].push_back(i);
@@ -1479,14 +1479,20 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     lo[s] = pos;
     for (int i : by_shape[s]) h->h_list[pos++] = i;
   }
-  auto upload = [&](char* xbuf) -> int {
-    HIPCHK(hipStreamSynchronize(st));   // an earlier upload may still read the pinned staging
+  // the descs of both candidate sets (x in the zero-filled or the network
+  // staging) sit in two regions of the pinned staging from the start, so
+  // switching the device descs between them is a plain ordered copy
+  SliceDesc* const staged[2] = {h->h_desc, h->h_desc + ns};
+  char* const xbuf[2] = {zf, x0};
+  for (int v = 0; v < 2; ++v)
     for (int i = 0; i < ns; ++i) {
-      tmp[i].x = xbuf + (size_t)i * np * 8;
-      fill_desc(h, h->h_desc[i], h->shapes[slices[i].shape_id], off[i], &tmp[i]);
+      tmp[i].x = xbuf[v] + (size_t)i * np * 8;
+      fill_desc(h, staged[v][i], h->shapes[slices[i].shape_id], off[i], &tmp[i]);
     }
-    HIPCHK(hipMemcpyAsync(h->d_desc, h->h_desc, sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_list, h->h_list, sizeof(int32_t) * pos, hipMemcpyHostToDevice, st));
+  enum { ZF = 0, X0 = 1 };
+  auto upload = [&](int v) -> int {
+    HIPCHK(hipMemcpyAsync(h->d_desc, staged[v], sizeof(SliceDesc) * ns, hipMemcpyHostToDevice, st));
     return FIRLS_OK;
   };
   auto evaluate = [&]() -> int {   // F_eps of every slice's x into the states
@@ -1512,7 +1518,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
   const bool prof = h->profiling;
   h->profiling = false;
   // 1. zero-filled starts A^H b
-  if ((rc = upload(zf))) return rc;
+  if ((rc = upload(ZF))) return rc;
   for (int s = 0; s < nsh; ++s) {
     const int c = (int)by_shape[s].size();
     if (!c) continue;
@@ -1529,7 +1535,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     if ((rc = cnn_forward(net, st, bn, zf + (size_t)b0 * np * 8, x0 + (size_t)b0 * np * 8))) return rc;
   }
   // 3. data consistency on the network starts: x0 <- F^H (m b + (1 - m) F x0)
-  if ((rc = upload(x0))) return rc;
+  if ((rc = upload(X0))) return rc;
   for (int s = 0; s < nsh; ++s) {
     const int c = (int)by_shape[s].size();
     if (!c) continue;
@@ -1539,13 +1545,11 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     LAUNCH(S.sk->col[COL_DC], P, dim3(S.col_wgs(false), c), st);
     LAUNCH(S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
   }
-  HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
-  if ((rc = upload(zf))) return rc;
+  if ((rc = upload(ZF))) return rc;
   // 4. objectives of both candidates, 5. keep the better one in each x
   if ((rc = evaluate())) return rc;
   HIPCHK(hipMemcpyAsync(st_zero, h->d_state, sizeof(SliceState) * ns, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));   // the staging descs are rewritten next
-  if ((rc = upload(x0))) return rc;
+  if ((rc = upload(X0))) return rc;
   if ((rc = evaluate())) return rc;
   std::vector<void*> hx(ns);
   for (int i = 0; i < ns; ++i) hx[i] = slices[i].x;
