@@ -301,6 +301,13 @@ int firls_set_graphs(firls_handle* h, int32_t enable);
  * results are bitwise the same. */
 int firls_set_paired(firls_handle* h, int32_t enable);
 
+/* Test hook for the paired pass's error path: while enabled, its barrier
+ * waits for one workgroup more than the slice has and gives up after a few
+ * polls, so every slice that runs a paired launch ends with FIRLS_E_SYNC
+ * (its results are then meaningless).  Every kernel still exits normally.
+ * For tests only; off by default. */
+int firls_test_sync_timeout(firls_handle* h, int32_t enable);
+
 /* Solve at most ``chunk`` slices at a time (0: the whole batch at once);
  * a smaller working set stays in the device's last-level cache.  A batch
  * of one masked-FFT shape is streamed: ``chunk`` slots start with the

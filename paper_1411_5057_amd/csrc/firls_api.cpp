@@ -125,6 +125,7 @@ struct firls_handle {
   bool use_graphs = true;
   // the paired PCG pass (row inverse of k - 1 and step of k in one launch)
   bool use_pair = true;
+  bool sync_test = false;   // firls_test_sync_timeout
   hipStream_t own = nullptr;          // work stream when the caller passes the null stream
   hipEvent_t ev_in = nullptr;
   struct GraphKey {
@@ -537,6 +538,7 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
   const int K = h->cfg.pcg_iters;
   // the row inverse of iteration k - 1 rides in the launch of step k
   const bool pair = fused && !s.dense && s.sk->pcg_pair && h->use_pair;
+  P.sync_test = h->sync_test ? 1 : 0;
   for (int k = 0; k < K; ++k) {
     P.k = k;
     if (fused) {
@@ -1578,6 +1580,13 @@ int firls_set_graphs(firls_handle* h, int32_t enable) {
 int firls_set_paired(firls_handle* h, int32_t enable) {
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
   h->use_pair = enable != 0;
+  drop_graphs(h);
+  return FIRLS_OK;
+}
+
+int firls_test_sync_timeout(firls_handle* h, int32_t enable) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  h->sync_test = enable != 0;
   drop_graphs(h);
   return FIRLS_OK;
 }

@@ -22,6 +22,7 @@ FIRLS_E_UNSUPPORTED = -2
 FIRLS_E_HIP = -3
 FIRLS_E_NOMEM = -4
 FIRLS_E_NONFINITE = -5
+FIRLS_E_SYNC = -6
 FIRLS_W_MAXITER = 1
 FIRLS_PSI_HAAR = 0
 FIRLS_PSI_TV = 1
@@ -41,7 +42,7 @@ EXPORTED = (
     "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
-    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_autotune",
+    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_autotune",
 )
 PROF_CLASSES = 15
 
@@ -159,6 +160,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_set_graphs": ([vp, i32], ctypes.c_int),
         "firls_set_chunk": ([vp, i32], ctypes.c_int),
         "firls_set_paired": ([vp, i32], ctypes.c_int),
+        "firls_test_sync_timeout": ([vp, i32], ctypes.c_int),
         "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
@@ -507,6 +509,10 @@ class Solver:
 
     def set_paired(self, enable: bool):
         _check(load().firls_set_paired(self.handle, int(enable)), "firls_set_paired")
+
+    def test_sync_timeout(self, enable: bool):
+        """Test hook: the paired pass's barrier times out at once (FIRLS_E_SYNC)."""
+        _check(load().firls_test_sync_timeout(self.handle, int(enable)), "firls_test_sync_timeout")
 
     def autotune(self, items: List[dict], stream=None) -> int:
         """Picks the sub-batch size (returned) and the launch mode (kept in

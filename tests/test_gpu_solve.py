@@ -356,3 +356,23 @@ def test_paired_pcg_pass_matches_two_launches(n):
     assert r1 == r0
     for a, b in zip(i0, i1):
         assert torch.equal(a["x"], b["x"])
+
+
+def test_paired_barrier_timeout_reports_an_error():
+    """The paired pass's in-kernel barrier is bounded: with the test hook
+    (one arrival more than can come, a short spin limit) every kernel still
+    exits, the solve reports FIRLS_E_SYNC, and after the hook is turned off
+    the same handle solves normally again."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 190 + i, psi="haar", levels=4, groups="quadtree", lam=0.035, sigma=0.01,
+                                frac=0.2) for i in range(3)]
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=3, max_outer=3, pcg_iters=4)
+    ref = s.solve_batched(_batch(torch, probs))
+    s.test_sync_timeout(True)
+    with pytest.raises(F.FirlsError) as e:
+        s.solve_batched(_batch(torch, probs))
+    assert e.value.code == F.FIRLS_E_SYNC
+    s.test_sync_timeout(False)
+    again = s.solve_batched(_batch(torch, probs))
+    assert again == ref
