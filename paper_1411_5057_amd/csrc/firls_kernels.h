@@ -771,8 +771,6 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     const C* tin = static_cast<const C*>(D.t);
     fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, [&](int l, int q) { return tin[t_index<T, N>(row0 + l, q)]; },
                                         LdsIO<T, N>{lds});
-    // keep the loads below out of the FFT's register-heavy stages
-    __builtin_amdgcn_sched_barrier(0);
     double acc = 0.0, acc2 = 0.0;
     if (mine) {
       C w[16];
