@@ -669,8 +669,9 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
         }
         // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
         if constexpr (SP) {
-          // only the fused step (paper's preconditioner) uses <q, P^{-1} q>
-          if (P.precond == PC_PAPER) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
+          // only the fused step (paper's preconditioner) uses <q, P^{-1} q>,
+          // and not after the last iteration
+          if (P.precond == PC_PAPER && !P.q_dead) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
         } else if (P.p0_prep) {
           // the first PCG iteration's start: z0 = P^{-1} r0, p0 = z0, whose
           // row FFTs follow from this thread's own LDS cells (already read)
@@ -685,8 +686,10 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
           precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
         }
       }
-      const double t2 = block_sum(acc2, red);
-      if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
+      if (!(SP && P.q_dead)) {
+        const double t2 = block_sum(acc2, red);
+        if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
+      }
       if (!SP && P.p0_prep) {
         __syncthreads();
         C* tout = static_cast<C*>(D.t);

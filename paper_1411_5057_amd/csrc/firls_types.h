@@ -154,7 +154,7 @@ struct Params {
   int32_t L;             // Haar levels
   int32_t k;             // PCG iteration index
   int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
-  int32_t q_dead;        // PCG row inverse: nothing reads this q (the last iteration of the fused step)
+  int32_t q_dead;        // PCG row inverse: nothing reads this q or <q, P^-1 q> (last iteration of the fused step)
   int32_t sync_test;     // test hook: the paired pass's barrier waits for one arrival too many, briefly
   int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs
   int32_t check_r0;      // ... and its first workgroup runs the outer check (Haar)
