@@ -661,13 +661,8 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
   h->ctx_phase = 0;
   h->ctx_it = 0;
   h->ctx_group = 0;
-  h->ctx_count = slots;
-  {
-    Params P = base_params(h, h->shapes[0], 0, h->d_list);
-    KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(slots), st);
-  }
   // x^1 = A^H b for slices without a warm start (Section 3.3); ``list``
-  // holds the c slots of shape s that need it
+  // holds the c descs of shape s that need it
   auto launch_ahb = [&](int s, const int32_t* list, int c) -> int {
     const Shape& S = h->shapes[s];
     Params P = base_params(h, S, s, list);
@@ -678,6 +673,45 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     KLAUNCH(h, FIRLS_PROF_AHB, S.sk->rowinv[RI_PLAIN], P, dim3(S.row_wgs(), c), st);
     return FIRLS_OK;
   };
+  // Streamed batches: A^H b of every queued zero-filled slice up front, in
+  // groups of ``slots`` that borrow the slots' workspaces before the loop
+  // starts (descs behind the slots' ones, the list behind the refill list),
+  // as a few full launches instead of a small pair at each refill; those
+  // slices then enter their slots with x already set.
+  std::vector<char> x_ready(ns, 0);
+  if (streamed) {
+    const int s0 = sl[0].shape_id;
+    const Shape& S = h->shapes[s0];
+    int32_t* hl = h->h_list + 3 * slots;
+    int nq = 0;
+    for (int i = slots; i < ns; ++i) {
+      if (sl[i].x_is_init) continue;
+      fill_desc(h, h->h_desc[i], S, off[nq % slots], &sl[i]);
+      h->h_desc[i].shape = s0;
+      hl[nq++] = i;
+      x_ready[i] = 1;
+    }
+    if (nq) {
+      HIPCHK(hipMemcpyAsync(h->d_desc + slots, h->h_desc + slots, sizeof(SliceDesc) * (ns - slots),
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(h->d_list + 3 * slots, hl, sizeof(int32_t) * nq, hipMemcpyHostToDevice, st));
+      for (int g0 = 0; g0 < nq; g0 += slots) {
+        const int c = std::min(slots, nq - g0);
+        const int32_t* list = h->d_list + 3 * slots + g0;
+        h->ctx_group = s0;
+        h->ctx_count = c;
+        Params P = base_params(h, S, s0, list);   // states of these descs: the final-state area, unused yet
+        KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(c), st);
+        if ((rc = launch_ahb(s0, list, c))) return rc;
+      }
+    }
+  }
+  h->ctx_group = 0;
+  h->ctx_count = slots;
+  {
+    Params P = base_params(h, h->shapes[0], 0, h->d_list);
+    KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(slots), st);
+  }
   for (int s = 0; s < nsh; ++s)
     if (!zf_by_shape[s].empty() && (rc = launch_ahb(s, h->d_list + zlo[s], (int)zf_by_shape[s].size()))) return rc;
   auto enqueue_prep = [&]() -> int {
@@ -802,7 +836,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
       }
       const firls_slice& q = sl[next];
       RefillRec r{q.b, q.mask, q.x, q.lambda, i, old};
-      (q.x_is_init ? given : zf).push_back(r);
+      (q.x_is_init || x_ready[next] ? given : zf).push_back(r);
       fin[old] = slots + old;
       slot_slice[i] = next++;
       start_it[i] = it;
