@@ -404,5 +404,6 @@ def stationarity(ops: Operators, x) -> float:
 
 def snr_db(x, truth) -> float:
     """SNR = 10 log10(var(x0) / MSE) (Section 5.4), magnitude image."""
-    mse = float(np.mean((np.abs(x) - truth) ** 2))
-    return 10.0 * np.log10(float(np.var(truth)) / mse)
+    mse = np.mean((np.abs(x) - truth) ** 2)
+    with np.errstate(divide="ignore"):
+        return float(10.0 * np.log10(np.var(truth) / mse))   # +inf for an exact magnitude

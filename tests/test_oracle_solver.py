@@ -262,3 +262,21 @@ def test_gradient_identity_used_by_lbfgs():
     h = 1e-6
     fd = (ops.objective(x + h * v)[0] - ops.objective(x - h * v)[0]) / (2 * h)
     assert abs(fd - inner(g, v)) < 1e-6 * max(1.0, abs(fd))
+
+
+# -- reconstruction quality (Section 5.4) -----------------------------------------
+
+def test_snr_db_closed_forms():
+    """SNR = 10 log10(var(truth) / MSE) on the magnitude image, pinned by
+    cases whose MSE is known in closed form: a constant offset c gives
+    MSE = c^2; scaling by 2 gives MSE = mean(truth^2); a pure phase or sign
+    change leaves the magnitude, so the SNR is infinite."""
+    from oracle.firls import snr_db
+    rs = np.random.default_rng(7)
+    truth = rs.uniform(0.0, 1.0, (16, 16))
+    var = float(np.mean((truth - truth.mean()) ** 2))
+    for c in (0.01, 0.25):
+        assert snr_db(truth + c, truth) == pytest.approx(10 * np.log10(var / c ** 2), rel=1e-12)
+    assert snr_db(2.0 * truth, truth) == pytest.approx(10 * np.log10(var / np.mean(truth ** 2)), rel=1e-12)
+    assert snr_db(truth * np.exp(0.7j), truth) > 250.0
+    assert snr_db(-truth.astype(np.complex128), truth) == np.inf
