@@ -55,8 +55,19 @@ enum {
   FIRLS_E_NONFINITE = -5,    /* objective became NaN or Inf */
   FIRLS_E_SYNC = -6,         /* workgroups of a slice did not meet at a barrier
                                 within its time limit (internal error) */
-  FIRLS_W_MAXITER = 1        /* stopped at max_outer before the tolerance */
+  FIRLS_E_BREAKDOWN = -7,    /* PCG: <p, S p> <= 0 with <r, z> > 0, impossible for
+                                the Hermitian positive definite S of eq. (15) /
+                                eq. (39) in exact arithmetic (Section 3.2) */
+  FIRLS_W_MAXITER = 1,       /* stopped at max_outer before the tolerance */
+  FIRLS_W_NONMONOTONE = 2    /* F_eps rose between outer iterations by more than
+                                rounding (1e-6 relative in FP32, 1e-12 in FP64),
+                                against Theorem 2 (Section 3.3) */
 };
+/* Per-slice statuses (firls_report.status) use the same codes; FIRLS_E_INVALID
+ * there means a TV slice whose mask leaves out the DC entry of some contrast:
+ * the difference operators annihilate constant images, so without that
+ * sample the minimiser is not unique.  Such a slice is not solved (its x is
+ * left as given). */
 
 /* Sparsifying transform Psi.  HAAR: orthonormal L-level 2D Haar (Section
  * 3, eq. 17).  TV: first-order differences with a periodic boundary,
@@ -307,6 +318,18 @@ int firls_set_paired(firls_handle* h, int32_t enable);
  * (its results are then meaningless).  Every kernel still exits normally.
  * For tests only; off by default. */
 int firls_test_sync_timeout(firls_handle* h, int32_t enable);
+
+/* Test hooks: conditions forced from the host so the error paths run with
+ * every kernel still exiting normally.  flags is a bit set (0 clears all):
+ *   FIRLS_TEST_SYNC_TIMEOUT  as firls_test_sync_timeout;
+ *   FIRLS_TEST_BREAKDOWN     every <p, S p> is taken as negative, so the first
+ *                            PCG step of each slice records FIRLS_E_BREAKDOWN;
+ *   FIRLS_TEST_NONMONOTONE   the monotonicity check's rounding slack becomes
+ *                            -100%, so every evaluation after the first counts
+ *                            as a rise and records FIRLS_W_NONMONOTONE.
+ * For tests only; off by default. */
+enum { FIRLS_TEST_SYNC_TIMEOUT = 1, FIRLS_TEST_BREAKDOWN = 2, FIRLS_TEST_NONMONOTONE = 4 };
+int firls_test_hooks(firls_handle* h, int32_t flags);
 
 /* Solve at most ``chunk`` slices at a time (0: the whole batch at once);
  * a smaller working set stays in the device's last-level cache.  A batch

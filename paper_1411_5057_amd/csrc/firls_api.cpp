@@ -125,7 +125,7 @@ struct firls_handle {
   bool use_graphs = true;
   // the paired PCG pass (row inverse of k - 1 and step of k in one launch)
   bool use_pair = true;
-  bool sync_test = false;   // firls_test_sync_timeout
+  int test_flags = 0;       // firls_test_hooks (TEST_*)
   hipStream_t own = nullptr;          // work stream when the caller passes the null stream
   hipEvent_t ev_in = nullptr;
   struct GraphKey {
@@ -289,6 +289,7 @@ void fill_desc(firls_handle* h, SliceDesc& D, const Shape& s, size_t off, const 
   D.n = s.n;
   D.C = s.C;
   D.shape = 0;
+  D.need_dc = sl && s.psi == PSI_TV && !s.dense ? 1 : 0;
   if (sl) {
     D.b = sl->b;
     D.mask = sl->mask;
@@ -328,6 +329,10 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.precond = h->cfg.precond;
   P.eps = h->cfg.eps;
   P.tau = h->cfg.outer_tol;
+  P.test_flags = h->test_flags;
+  // rounding slack of the monotone-objective check: F_eps is summed in FP64
+  // from FP32 (or FP64) terms
+  P.mono_slack = (h->test_flags & TEST_NONMONOTONE) ? -1.0 : (h->fp64 ? 1e-12 : 1e-6);
   const int R = band_rows(s.n);
   // partials per slot: one per workgroup, over the rows of every contrast
   P.npq = s.C * (s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0));
@@ -538,7 +543,6 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
   const int K = h->cfg.pcg_iters;
   // the row inverse of iteration k - 1 rides in the launch of step k
   const bool pair = fused && !s.dense && s.sk->pcg_pair && h->use_pair;
-  P.sync_test = h->sync_test ? 1 : 0;
   for (int k = 0; k < K; ++k) {
     P.k = k;
     if (fused) {
@@ -708,8 +712,13 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
   }
   h->ctx_group = 0;
   h->ctx_count = slots;
+  // Stop words start as active; a slice rejected at its start (a TV mask
+  // without DC) writes its word as stopped.  The host's own stores must
+  // come first, so they happen before the launch.
+  for (int i = 0; i < slots; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
   {
     Params P = base_params(h, h->shapes[0], 0, h->d_list);
+    P.stop_flags = h->d_flags;
     KLAUNCH(h, FIRLS_PROF_INIT, pk->slice_init, P, dim3(slots), st);
   }
   for (int s = 0; s < nsh; ++s)
@@ -783,7 +792,6 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
   std::vector<char> settled(slots, 0);   // stopped, queue empty: its slice's state stays in the slot
   for (int i = 0; i < slots; ++i) slot_slice[i] = i;
   int next = slots;   // next queued slice
-  for (int i = 0; i < slots; ++i) __atomic_store_n(h->h_flags + i, 1, __ATOMIC_RELAXED);
   auto read_active = [&](int j, bool& done) {
     done = true;
     for (int i = 0; i < slots && done; ++i) {
@@ -846,7 +854,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     if (!count) return FIRLS_OK;
     std::copy(zf.begin(), zf.end(), h->h_refill);
     std::copy(given.begin(), given.end(), h->h_refill + zf.size());
-    RefillArgs A{h->d_refill, count, slots, h->d_desc, h->d_state, d_refill_list};
+    RefillArgs A{h->d_refill, count, slots, h->d_desc, h->d_state, d_refill_list, h->d_flags};
     HIPCHK(launch_refill(A, st));
     h->ctx_phase = 0;
     int r2;
@@ -898,6 +906,9 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     else if (worst >= 0 && S.status > worst) worst = S.status;
   }
   if (worst == FIRLS_E_SYNC) g_err = "workgroups of a slice missed a barrier (internal error)";
+  else if (worst == FIRLS_E_BREAKDOWN) g_err = "PCG breakdown: <p, S p> <= 0 with a nonzero residual";
+  else if (worst == FIRLS_E_INVALID)
+    g_err = "a TV slice's mask does not sample the DC entry (its minimiser would not be unique)";
   else if (worst < 0) g_err = "a slice's objective became non-finite";
   return worst;
 }
@@ -1551,7 +1562,13 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
     }
     return FIRLS_OK;
   };
-  const bool prof = h->profiling;
+  // the prelude's launches are not profiled; the setting comes back on
+  // every return path
+  struct ProfilingOff {
+    firls_handle* h;
+    bool was;
+    ~ProfilingOff() { h->profiling = was; }
+  } prof_off{h, h->profiling};
   h->profiling = false;
   // 1. zero-filled starts A^H b
   if ((rc = upload(ZF))) return rc;
@@ -1598,7 +1615,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
   HIPCHK(hipStreamSynchronize(st));
   if (used_learned)
     for (int i = 0; i < ns; ++i) used_learned[i] = s1[i].Fe <= s0[i].Fe ? 1 : 0;
-  h->profiling = prof;
+  h->profiling = prof_off.was;
   // 6. FIRLS from the chosen starts
   for (int i = 0; i < ns; ++i) tmp[i] = slices[i], tmp[i].x_is_init = 1;
   return run_batch(h, st, ns, tmp.data(), reports, h->cfg.max_outer, h->cfg.outer_tol);
@@ -1620,7 +1637,16 @@ int firls_set_paired(firls_handle* h, int32_t enable) {
 
 int firls_test_sync_timeout(firls_handle* h, int32_t enable) {
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
-  h->sync_test = enable != 0;
+  h->test_flags = enable ? (h->test_flags | TEST_SYNC_TIMEOUT) : (h->test_flags & ~TEST_SYNC_TIMEOUT);
+  drop_graphs(h);
+  return FIRLS_OK;
+}
+
+int firls_test_hooks(firls_handle* h, int32_t flags) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  if (flags & ~(FIRLS_TEST_SYNC_TIMEOUT | FIRLS_TEST_BREAKDOWN | FIRLS_TEST_NONMONOTONE))
+    return fail(FIRLS_E_INVALID, "unknown test hook");
+  h->test_flags = flags;
   drop_graphs(h);
   return FIRLS_OK;
 }
@@ -1728,7 +1754,9 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     }
   }
   h->profiling = prof;
-  if (!rc) rc = copy_all(false);
+  // the caller's x comes back from the snapshot also when a trial failed
+  const int rc_restore = copy_all(false);
+  if (!rc) rc = rc_restore;
   (void)hipStreamSynchronize(st);
   (void)hipFree(snap);
   if (rc) {

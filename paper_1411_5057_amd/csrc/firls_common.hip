@@ -9,7 +9,11 @@ namespace firls {
 // rho = (number of sampled entries) / n^2, the mean (indeed every entry) of
 // diag(A^H A) for the unitary F (Section 5.4), and a fresh outer-loop state.
 // One workgroup per slice; ``mask`` is the slice's mask (D.mask).
-__device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& S, double* red) {
+// A TV solve needs the DC entry of every contrast's mask: the differences
+// annihilate constants, so without it A 1 = 0 and the minimiser is not
+// unique.  Such a slice is not started: status FIRLS_E_INVALID, and its
+// stop word (``flag``, host-mapped, if given) reads stopped at once.
+__device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& S, double* red, int32_t* flag) {
   // the paired PCG pass's barrier counters count from zero for each slice
   uint32_t* sync = reinterpret_cast<uint32_t*>(slot_wptr(D, SLOT_SYNC));
   for (int k = threadIdx.x; k < KMAX; k += NT) sync[k] = 0u;
@@ -44,13 +48,20 @@ __device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& 
     S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
     S.active = 1;
     S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
+    bool dc = true;
+    for (int c = 0; D.need_dc && c < D.C; ++c) dc = dc && mask[(size_t)c * n * n] != 0;
+    if (!dc) {
+      S.status = ST_E_INVALID;
+      S.active = 0;
+      if (flag) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
 __global__ __launch_bounds__(NT) void k_slice_init(Params P) {
   __shared__ double red[NT / 64];
   const int s = P.list[blockIdx.x];
-  init_slice(P.desc[s], P.desc[s].mask, P.state[s], red);
+  init_slice(P.desc[s], P.desc[s].mask, P.state[s], red, P.stop_flags ? P.stop_flags + s : nullptr);
 }
 
 // Slot refills of a streamed batch, one workgroup per record: save the
@@ -69,7 +80,7 @@ __global__ __launch_bounds__(NT) void k_refill(RefillArgs A) {
     D.lambda = r.lambda;
     A.list[blockIdx.x] = r.slot;
   }
-  init_slice(D, r.mask, S, red);
+  init_slice(D, r.mask, S, red, A.stop_flags ? A.stop_flags + r.slot : nullptr);
 }
 
 hipError_t launch_refill(const RefillArgs& A, hipStream_t st) {

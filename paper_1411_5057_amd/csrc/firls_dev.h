@@ -172,10 +172,11 @@ struct Stage {
   }
 
   template <class Src>
-  __device__ __forceinline__ static void load(cplx<T> (&v)[ITER][R], Src& src, const cplx<T>* tw) {
+  __device__ __forceinline__ static void load(cplx<T> (&v)[ITER][R], Src& src, const cplx<T>* tw,
+                                              int tid = threadIdx.x) {
 #pragma unroll
     for (int i = 0; i < ITER; ++i) {
-      const int b = threadIdx.x + i * NT;
+      const int b = tid + i * NT;
       if (TOT % NT != 0 && b >= TOT) continue;
       int line, j;
       decode(b, line, j);
@@ -195,10 +196,10 @@ struct Stage {
   }
 
   template <class Dst>
-  __device__ __forceinline__ static void store(cplx<T> (&v)[ITER][R], Dst& dst) {
+  __device__ __forceinline__ static void store(cplx<T> (&v)[ITER][R], Dst& dst, int tid = threadIdx.x) {
 #pragma unroll
     for (int i = 0; i < ITER; ++i) {
-      const int b = threadIdx.x + i * NT;
+      const int b = tid + i * NT;
       if (TOT % NT != 0 && b >= TOT) continue;
       int line, j;
       decode(b, line, j);
@@ -221,8 +222,12 @@ struct LdsIO {
 // The first stage reads src(line, pos), the last writes dst(line, pos, v);
 // intermediate stages go through ``lds`` (LINES x LdsLayout<N>::LS).
 // Barriers bracket every LDS phase, so src / dst may themselves be LDS.
+// ``tid`` is the work-item index the butterflies are assigned by; a kernel
+// with two FFTs far apart passes a copy the compiler cannot see through, so
+// the second one's addresses are recomputed instead of being kept live (and
+// spilled) from the first.
 template <typename T, int N, int LINES, int MAP, bool INV, class Src, class Dst>
-__device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src src, Dst dst) {
+__device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src src, Dst dst, int tid = threadIdx.x) {
   using P = Plan<N>;
   constexpr int A0 = INV ? (P::S == 3 ? P::R2 : (P::S == 2 ? P::R1 : P::R0)) : P::R0;
   constexpr int A1 = INV ? (P::S == 3 ? P::R1 : P::R0) : P::R1;
@@ -230,29 +235,29 @@ __device__ __forceinline__ void fft_lines(cplx<T>* lds, const cplx<T>* tw, Src s
   LdsIO<T, N> io{lds};
   using S0 = Stage<T, N, A0, 1, LINES, MAP, INV>;
   cplx<T> v0[S0::ITER][A0];
-  S0::load(v0, src, tw);
+  S0::load(v0, src, tw, tid);
   __syncthreads();
   if constexpr (P::S == 1) {
-    S0::store(v0, dst);
+    S0::store(v0, dst, tid);
     __syncthreads();
   } else {
-    S0::store(v0, io);
+    S0::store(v0, io, tid);
     __syncthreads();
     using S1 = Stage<T, N, A1, A0, LINES, MAP, INV>;
     cplx<T> v1[S1::ITER][A1];
-    S1::load(v1, io, tw);
+    S1::load(v1, io, tw, tid);
     __syncthreads();
     if constexpr (P::S == 2) {
-      S1::store(v1, dst);
+      S1::store(v1, dst, tid);
       __syncthreads();
     } else {
-      S1::store(v1, io);
+      S1::store(v1, io, tid);
       __syncthreads();
       using S2 = Stage<T, N, A2, A0 * A1, LINES, MAP, INV>;
       cplx<T> v2[S2::ITER][A2];
-      S2::load(v2, io, tw);
+      S2::load(v2, io, tw, tid);
       __syncthreads();
-      S2::store(v2, dst);
+      S2::store(v2, dst, tid);
       __syncthreads();
     }
   }

@@ -122,6 +122,20 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
   else precond_tile_k<NEED_Z, N, PC_NONE>(v, dg, L, col, rho, lam, acc);
 }
 
+// alpha = <r, z> / <p, S p> of a PCG step of slice s.  For HPD S, <p, S p>
+// is positive whenever the residual is not zero (then <r, z> > 0 and p != 0),
+// so a non-positive (or NaN) <p, S p> with <r, z> > 0 is a breakdown: the
+// first workgroup records FIRLS_E_BREAKDOWN, which stops the slice at its
+// next outer check, and the step is taken as zero.  A zero residual (both
+// zero) is the ordinary end of the iteration: a zero step.  The test hook
+// TEST_BREAKDOWN turns <p, S p> negative.
+__device__ __forceinline__ double pcg_alpha(const Params& P, int s, double rz, double pq) {
+  if (P.test_flags & TEST_BREAKDOWN) pq = -fabs(pq);
+  if (pq > 0.0) return rz / pq;
+  if (rz > 0.0 && blockIdx.x == 0 && threadIdx.x == 0 && P.state[s].status >= 0) P.state[s].status = ST_E_BREAKDOWN;
+  return 0.0;
+}
+
 // Objective of the current x and the outer stopping rule of slice s (one
 // workgroup; every thread takes part in the sums).  F_eps = data + lambda
 // sum sqrt(s_g + eps); stop when (F_eps^{prev} - F_eps) <= tau F_eps after
@@ -144,16 +158,21 @@ __device__ __forceinline__ void outer_check_wg(const Params& P, int s) {
   S.F = F;
   S.data = data;
   S.evals += 1;
+  // Theorem 2: with x^{k+1} from PCG started at x^k (any number of
+  // iterations, each lowering the majoriser) F_eps never rises; beyond the
+  // rounding slack a rise is reported (the stop rule then ends the slice
+  // when tau > 0)
+  if (!first && S.status == ST_OK && isfinite(Fe) && Fe > prev * (1.0 + P.mono_slack)) S.status = ST_W_NONMONOTONE;
   if (S.status < 0) {
-    S.active = 0;   // a PCG pass recorded an error (FIRLS_E_SYNC): stop, keep it
+    S.active = 0;   // a PCG pass recorded an error (sync time-out, breakdown): stop, keep it
   } else if (!isfinite(Fe)) {
-    S.status = -5;  // FIRLS_E_NONFINITE
+    S.status = ST_E_NONFINITE;
     S.active = 0;
   } else if (!first && P.tau > 0.0 && (prev - Fe) <= P.tau * Fe) {
     S.converged = 1;
     S.active = 0;
   } else if (S.outer >= P.Tmax) {
-    if (P.tau > 0.0) S.status = 1;  // FIRLS_W_MAXITER
+    if (P.tau > 0.0 && S.status == ST_OK) S.status = ST_W_MAXITER;
     S.active = 0;
   } else {
     S.outer += 1;
@@ -276,7 +295,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     if (pend) {
       const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
       const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-      al = (T)(pq > 0.0 ? rz / pq : 0.0);
+      al = (T)pcg_alpha(P, s_, rz, pq);
     }
     const C* p = static_cast<const C*>(D.p) + off;
     T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
@@ -408,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz);
       const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq);
       const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz);
-      const double ald = pqo > 0.0 ? rzo / pqo : 0.0;
+      const double ald = pcg_alpha(P, s_, rzo, pqo);
       const double rzn = ald * ald * qqo - rzo;
       const T al = (T)ald;
       const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -735,8 +754,8 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 //   B: x += alpha p, r -= alpha q, z = P^{-1} r, <r, z>, p_k = z + beta p,
 //      and the row FFT of p_k.
 // q waits in the thread's own LDS cells across the barrier (where A^H A p
-// was), so it never goes through memory; B reads p again (the band was
-// just read, so it comes from cache).  The barrier counts arrivals in the
+// was), so it never goes through memory, and d in registers; B reads p
+// again (keeping it in registers as well would spill).  The barrier counts arrivals in the
 // slice's counter k, which grows by one band count per outer iteration
 // (zeroed when the slice starts); the partials it publishes are the only
 // data that crosses workgroups, written and read device-coherently, so no
@@ -744,10 +763,11 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 // order and a slice's bands are consecutive, so the workgroups that wait
 // never hold back one that a slice still needs.  The wait is bounded: past
 // the limit the slice is marked FIRLS_E_SYNC and the workgroup goes on.
-// Four workgroups per CU, as the other row passes: the two phases then
-// spill a few registers (68 bytes per thread, cache resident), which
-// measured faster than three workgroups per CU without spills (without
-// the bound the compiler takes registers for only two).
+// Four workgroups per CU, as the other row passes (without the bound the
+// compiler takes registers for only two).  The closing row FFT is laid out
+// from a thread index the compiler cannot see through, so its addresses
+// are recomputed there rather than kept live from phase A, which would
+// not fit the 128 registers of that occupancy and spill.
 template <typename T, int N>
 __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   constexpr int ROWS = band_rows(N);
@@ -769,6 +789,8 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   const T* d = static_cast<const T*>(D.d) + off;
   const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
   C* p = static_cast<C*>(D.p) + off;
+  // d of the thread's tile column stays in registers from A to B
+  T dv[16];
   // A: the row inverse of iteration k - 1
   {
     const C* tin = static_cast<const C*>(D.t);
@@ -777,7 +799,6 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     double acc = 0.0, acc2 = 0.0;
     if (mine) {
       C w[16];
-      T dv[16];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         w[s] = p[(row + s) * N + col];
@@ -815,8 +836,9 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     uint32_t* cnt = reinterpret_cast<uint32_t*>(slot_wptr(D, SLOT_SYNC)) + k;
     // (the test hook asks for one arrival more than can come and gives up
     // after a few polls, so the time-out path runs without a long wait)
-    const uint32_t target = gridDim.x * (uint32_t)P.state[s_].outer + (P.sync_test ? 1u : 0u);
-    const uint32_t limit = P.sync_test ? 64u : (1u << 20);
+    const bool hook = (P.test_flags & TEST_SYNC_TIMEOUT) != 0;
+    const uint32_t target = gridDim.x * (uint32_t)P.state[s_].outer + (hook ? 1u : 0u);
+    const uint32_t limit = hook ? 64u : (1u << 20);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -831,12 +853,12 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     timed_out = late;
   }
   __syncthreads();
-  if (timed_out && threadIdx.x == 0) P.state[s_].status = -6;   // FIRLS_E_SYNC
+  if (timed_out && threadIdx.x == 0) P.state[s_].status = ST_E_SYNC;
   // B: the step of iteration k (this launch's partials read device-coherently)
   const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + k - 1), P.nrz);
   const double pqo = slot_sum_coherent(slot_ptr(D, SLOT_PQ0 + k - 1), P.npq);
   const double qqo = slot_sum_coherent(slot_ptr(D, SLOT_QQ0 + k - 1), P.nrz);
-  const double ald = pqo > 0.0 ? rzo / pqo : 0.0;
+  const double ald = pcg_alpha(P, s_, rzo, pqo);
   const double rzn = ald * ald * qqo - rzo;
   const T al = (T)ald;
   const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -873,7 +895,7 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
         r[g] = v[s0 + u];
       }
     }
-    precond_tile_k<true, N, PC_PAPER>(v, d + rb * N + cb, P.L, cb, rho, lam, acc);
+    precond_tile_paper<true>(v, dv, P.L, cb, rho, lam, acc);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int a = Lay::at(rb + s, cb);
@@ -885,8 +907,10 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + k)[blockIdx.x] = tot;
   C* t = static_cast<C*>(D.t);
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
-                                       [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; });
+                                       [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; }, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -928,7 +952,7 @@ __global__ __launch_bounds__(NT) void k_update_haar(Params P) {
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
+  const T al = (T)pcg_alpha(P, s_, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   C* r = static_cast<C*>(D.r[0]) + off;
   const C* p = static_cast<const C*>(D.p) + off;
@@ -976,7 +1000,7 @@ __global__ __launch_bounds__(NT) void k_last_x(Params P) {
   const size_t off = (size_t)blockIdx.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)(pq > 0.0 ? rz / pq : 0.0);
+  const T al = (T)pcg_alpha(P, s_, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
   // E elements per thread, CH at a time with their loads ahead of their
@@ -1105,7 +1129,7 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-    al = (T)(pq > 0.0 ? rz / pq : 0.0);
+    al = (T)pcg_alpha(P, s_, rz, pq);
   }
   const C* q = static_cast<const C*>(D.q) + cb;
   // coupling weights: slots that hold identity rows (tvb) couple nothing

@@ -35,6 +35,12 @@ enum Slot : int {
 };
 
 enum Psi : int { PSI_HAAR = 0, PSI_TV = 1 };
+
+// Per-slice status codes written on the device (the ABI's FIRLS_* values).
+enum SliceStatus : int { ST_OK = 0, ST_W_MAXITER = 1, ST_W_NONMONOTONE = 2, ST_E_INVALID = -1, ST_E_NONFINITE = -5,
+                         ST_E_SYNC = -6, ST_E_BREAKDOWN = -7 };
+// Test hooks (Params::test_flags), set only through firls_test_hooks.
+enum TestFlag : int { TEST_SYNC_TIMEOUT = 1, TEST_BREAKDOWN = 2, TEST_NONMONOTONE = 4 };
 enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
 
 // Kernel variants (template modes).
@@ -78,6 +84,7 @@ struct SliceDesc {
   int32_t n;
   int32_t shape;
   int32_t C;         // contrasts stacked as C blocks of n rows
+  int32_t need_dc;   // a solve of a TV slice: every contrast's mask must sample DC
 };
 
 // Per-slice device state of the outer loop (FP64 scalars on the device).
@@ -91,7 +98,7 @@ struct SliceState {
   int32_t active;    // 1 while the slice still iterates
   int32_t outer;     // reweighted solves done
   int32_t pcg;       // PCG iterations done
-  int32_t status;    // 0, FIRLS_W_MAXITER, FIRLS_E_NONFINITE, FIRLS_E_SYNC
+  int32_t status;    // SliceStatus
   int32_t converged;
   int32_t evals;     // objective evaluations done
   int32_t pend;      // x += alpha p of the last PCG iteration not yet applied
@@ -117,6 +124,7 @@ struct RefillArgs {
   SliceDesc* desc;
   SliceState* state;
   int32_t* list;          // out: the refilled slots, in record order
+  int32_t* stop_flags;    // host-mapped stop word per slot (a slice rejected at its start writes 0)
 };
 
 // Group map of one shape on the device (internal coefficient indices).
@@ -155,7 +163,7 @@ struct Params {
   int32_t k;             // PCG iteration index
   int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
   int32_t q_dead;        // PCG row inverse: nothing reads this q or <q, P^-1 q> (last iteration of the fused step)
-  int32_t sync_test;     // test hook: the paired pass's barrier waits for one arrival too many, briefly
+  int32_t test_flags;    // test hooks (TEST_*): conditions forced from the host so the error paths run
   int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs
   int32_t check_r0;      // ... and its first workgroup runs the outer check (Haar)
   int32_t K;             // PCG iterations per outer iteration
@@ -175,6 +183,7 @@ struct Params {
   void* gscr;            // GEMM split-K partial tiles
   double eps;
   double tau;
+  double mono_slack;     // outer check: F_eps may exceed its previous value by this fraction (rounding)
   void* out;             // op entry points: extra output
   int32_t* stop_flags;   // host-mapped word per slice, (evaluations << 1) | active,
                          // written by the outer check (null: not written)

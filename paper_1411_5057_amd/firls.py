@@ -23,7 +23,12 @@ FIRLS_E_HIP = -3
 FIRLS_E_NOMEM = -4
 FIRLS_E_NONFINITE = -5
 FIRLS_E_SYNC = -6
+FIRLS_E_BREAKDOWN = -7
 FIRLS_W_MAXITER = 1
+FIRLS_W_NONMONOTONE = 2
+FIRLS_TEST_SYNC_TIMEOUT = 1
+FIRLS_TEST_BREAKDOWN = 2
+FIRLS_TEST_NONMONOTONE = 4
 FIRLS_PSI_HAAR = 0
 FIRLS_PSI_TV = 1
 FIRLS_PSI_TV_PAPER = 2
@@ -42,7 +47,7 @@ EXPORTED = (
     "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
-    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_autotune",
+    "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_test_hooks", "firls_autotune",
 )
 PROF_CLASSES = 15
 
@@ -91,9 +96,58 @@ for _dt, _st in ((SLICE_DTYPE, firls_slice), (REPORT_DTYPE, firls_report)):
     assert all(_dt.fields[f][1] == getattr(_st, f).offset for f, _ in _st._fields_)
 
 
-def slice_array(items, init: Optional[bool] = None) -> np.ndarray:
+def check_tensor(t, what: str, dtype, numel: int, allow_none: bool = False, device: bool = True) -> None:
+    """Rejects a buffer the kernels would misread: it must be a contiguous
+    torch tensor of ``dtype`` with ``numel`` elements on the GPU (None only
+    where ``allow_none``; ``device=False`` skips the device check).  The
+    device is checked last, so every other check can be exercised with host
+    tensors."""
+    if t is None:
+        if allow_none:
+            return
+        raise ValueError(f"{what} is required")
+    if not hasattr(t, "data_ptr") or not hasattr(t, "is_contiguous"):
+        raise TypeError(f"{what} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    if device and t.device.type != "cuda":
+        raise ValueError(f"{what} must be on the GPU, got device {t.device}")
+
+
+def _dtypes(prec: str):
+    import torch
+    return (torch.complex64, torch.float32) if prec == "fp32" else (torch.complex128, torch.float64)
+
+
+def check_slice_item(it: dict, shapes, prec: str) -> None:
+    """b, mask and x of one batch item against its shape: b holds n^2 C
+    complex values (m for a dense sensing matrix), mask n^2 C bytes (may be
+    None for a dense matrix), x n^2 C complex values."""
+    import torch
+    sid = int(it.get("shape_id", 0))
+    if not 0 <= sid < len(shapes):
+        raise ValueError(f"shape_id {sid} out of range")
+    sh = shapes[sid]
+    cplx, _ = _dtypes(prec)
+    npx = sh.n * sh.n * sh.channels
+    dense = sh.A is not None
+    for dev in (False, True):    # every buffer's layout first, then where they live
+        check_tensor(it["b"], "b", cplx, sh.A.shape[0] if dense else npx, device=dev)
+        check_tensor(it["mask"], "mask", torch.uint8, npx, allow_none=dense, device=dev)
+        check_tensor(it["x"], "x", cplx, npx, device=dev)
+
+
+def slice_array(items, init: Optional[bool] = None, shapes=None, prec: Optional[str] = None) -> np.ndarray:
     """items (dicts with b, mask, x, lam, shape_id, x_is_init) -> firls_slice
-    records; ``init`` overrides every x_is_init."""
+    records; ``init`` overrides every x_is_init.  With ``shapes`` and
+    ``prec`` every item's tensors are checked first (check_slice_item)."""
+    if shapes is not None:
+        for it in items:
+            check_slice_item(it, shapes, prec)
     a = np.empty(len(items), SLICE_DTYPE)
     a["shape_id"] = [it.get("shape_id", 0) for it in items]
     a["x_is_init"] = ([bool(it.get("x_is_init", False)) for it in items] if init is None else bool(init))
@@ -120,9 +174,9 @@ class Batch:
     numpy structured array with the fields of firls_report (one record per
     slice, in item order)."""
 
-    def __init__(self, items: List[dict], init: Optional[bool] = None):
+    def __init__(self, items: List[dict], init: Optional[bool] = None, shapes=None, prec: Optional[str] = None):
         self.items = list(items)
-        self.slices = slice_array(self.items, init)
+        self.slices = slice_array(self.items, init, shapes, prec)
         self.reports = np.zeros(len(self.items), REPORT_DTYPE)
         self.used = np.zeros(len(self.items), np.int32)
 
@@ -161,6 +215,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_set_chunk": ([vp, i32], ctypes.c_int),
         "firls_set_paired": ([vp, i32], ctypes.c_int),
         "firls_test_sync_timeout": ([vp, i32], ctypes.c_int),
+        "firls_test_hooks": ([vp, i32], ctypes.c_int),
         "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
@@ -365,14 +420,24 @@ class Net:
     def get_params(self) -> np.ndarray:
         return firls_cnn_get_params(self.handle)
 
+    def _batch(self, *ts) -> int:
+        """Checks complex64 [batch, n, n] buffers of one batch size."""
+        import torch
+        batch = int(ts[0].shape[0]) if hasattr(ts[0], "shape") and len(ts[0].shape) else 0
+        if not 1 <= batch <= self.max_batch:
+            raise ValueError(f"batch must be in 1..{self.max_batch}, got {batch}")
+        for i, t in enumerate(ts):
+            check_tensor(t, f"network buffer {i}", torch.complex64, batch * self.n * self.n)
+        return batch
+
     def forward(self, zf, x0, stream=None):
-        firls_cnn_forward(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(x0))
+        firls_cnn_forward(self.handle, _stream(stream), self._batch(zf, x0), _ptr(zf), _ptr(x0))
 
     def gradients(self, zf, label, stream=None):
-        return firls_cnn_gradients(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(label))
+        return firls_cnn_gradients(self.handle, _stream(stream), self._batch(zf, label), _ptr(zf), _ptr(label))
 
     def train_step(self, zf, label, lr, stream=None) -> float:
-        return firls_cnn_train_step(self.handle, _stream(stream), zf.shape[0], _ptr(zf), _ptr(label), lr)
+        return firls_cnn_train_step(self.handle, _stream(stream), self._batch(zf, label), _ptr(zf), _ptr(label), lr)
 
 
 # ---------------------------------------------------------------------------
@@ -444,7 +509,24 @@ class Solver:
         except Exception:
             pass
 
+    def _check(self, it: dict) -> None:
+        check_slice_item(it, self.shapes, self.prec)
+
+    def _npx(self, shape_id: int) -> int:
+        if not 0 <= shape_id < len(self.shapes):
+            raise ValueError(f"shape_id {shape_id} out of range")
+        sh = self.shapes[shape_id]
+        return sh.n * sh.n * sh.channels
+
+    def _vec(self, t, what: str, shape_id: int) -> None:
+        check_tensor(t, what, _dtypes(self.prec)[0], self._npx(shape_id))
+
+    def _mask(self, m, shape_id: int) -> None:
+        import torch
+        check_tensor(m, "mask", torch.uint8, self._npx(shape_id), allow_none=self.shapes[shape_id].A is not None)
+
     def solve(self, b, mask, x, lam: float, shape_id: int = 0, x_is_init: bool = False, stream=None) -> dict:
+        self._check(dict(b=b, mask=mask, x=x, shape_id=shape_id))
         sl = firls_slice(shape_id, int(x_is_init), float(lam), _ptr(b), _ptr(mask), _ptr(x))
         rep = firls_report()
         firls_solve(self.handle, _stream(stream), sl, rep)
@@ -453,7 +535,7 @@ class Solver:
     def prepare(self, items: List[dict], learned: bool = False) -> Batch:
         """Marshal a batch once (``learned``: for solve_batched_learned, whose
         slices all count as initialised)."""
-        return Batch(items, True if learned else None)
+        return Batch(items, True if learned else None, self.shapes, self.prec)
 
     def solve_batched(self, items, stream=None):
         """items: dicts with b, mask, x, lam, shape_id (0), x_is_init (False),
@@ -463,25 +545,36 @@ class Solver:
             firls_solve_batched(self.handle, _stream(stream), len(items), _as(items.slices, firls_slice),
                                 _as(items.reports, firls_report))
             return items.reports.copy()
-        arr = slice_array(items)
+        arr = slice_array(items, None, self.shapes, self.prec)
         reps = np.zeros(len(items), REPORT_DTYPE)
         firls_solve_batched(self.handle, _stream(stream), len(items), _as(arr, firls_slice), _as(reps, firls_report))
         return report_dicts(reps)
 
     # single-operator entry points
     def adjoint(self, b, mask, x, shape_id=0, stream=None):
+        self._check(dict(b=b, mask=mask, x=x, shape_id=shape_id))
         firls_op_adjoint(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), _ptr(x))
 
     def weights(self, x, d_out, shape_id=0, stream=None):
+        self._vec(x, "x", shape_id)
+        ncoef = self._npx(shape_id) * (1 if self.shapes[shape_id].psi == "haar" else 2)
+        check_tensor(d_out, "d_out", _dtypes(self.prec)[1], ncoef)
         firls_op_weights(self.handle, _stream(stream), shape_id, _ptr(x), _ptr(d_out))
 
     def system(self, mask, lam, x_w, p, q, shape_id=0, stream=None):
+        self._mask(mask, shape_id)
+        for t, w in ((x_w, "x_w"), (p, "p"), (q, "q")):
+            self._vec(t, w, shape_id)
         firls_op_system(self.handle, _stream(stream), shape_id, _ptr(mask), float(lam), _ptr(x_w), _ptr(p), _ptr(q))
 
     def precond(self, mask, lam, x_w, r, z, shape_id=0, stream=None):
+        self._mask(mask, shape_id)
+        for t, w in ((x_w, "x_w"), (r, "r"), (z, "z")):
+            self._vec(t, w, shape_id)
         firls_op_precond(self.handle, _stream(stream), shape_id, _ptr(mask), float(lam), _ptr(x_w), _ptr(r), _ptr(z))
 
     def objective(self, b, mask, lam, x, shape_id=0, stream=None):
+        self._check(dict(b=b, mask=mask, x=x, shape_id=shape_id))
         return firls_op_objective(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))
 
     def solve_batched_learned(self, net: "Net", items, stream=None):
@@ -493,7 +586,7 @@ class Solver:
                                         _as(items.slices, firls_slice), _as(items.reports, firls_report),
                                         _as(items.used, ctypes.c_int32))
             return items.reports.copy(), items.used.copy()
-        arr = slice_array(items, True)
+        arr = slice_array(items, True, self.shapes, self.prec)
         reps = np.zeros(len(items), REPORT_DTYPE)
         used = np.zeros(len(items), np.int32)
         firls_solve_batched_learned(self.handle, net.handle, _stream(stream), len(items), _as(arr, firls_slice),
@@ -514,10 +607,15 @@ class Solver:
         """Test hook: the paired pass's barrier times out at once (FIRLS_E_SYNC)."""
         _check(load().firls_test_sync_timeout(self.handle, int(enable)), "firls_test_sync_timeout")
 
+    def test_hooks(self, flags: int):
+        """Test hooks (FIRLS_TEST_* bits; 0 clears them): forced conditions
+        that make the error paths run."""
+        _check(load().firls_test_hooks(self.handle, int(flags)), "firls_test_hooks")
+
     def autotune(self, items: List[dict], stream=None) -> int:
         """Picks the sub-batch size (returned) and the launch mode (kept in
         ``self.graphs``: True for graph replay) for these slices."""
-        arr = slice_array(items)
+        arr = slice_array(items, None, self.shapes, self.prec)
         chosen, graphs = ctypes.c_int32(), ctypes.c_int32()
         _check(load().firls_autotune(self.handle, _stream(stream), len(items), _as(arr, firls_slice),
                                      ctypes.byref(chosen), ctypes.byref(graphs)),
@@ -532,4 +630,5 @@ class Solver:
         return firls_profile_read(self.handle)
 
     def outer_step(self, b, mask, lam, x, shape_id=0, stream=None):
+        self._check(dict(b=b, mask=mask, x=x, shape_id=shape_id))
         firls_op_outer_step(self.handle, _stream(stream), shape_id, _ptr(b), _ptr(mask), float(lam), _ptr(x))

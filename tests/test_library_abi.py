@@ -63,3 +63,36 @@ def test_batch_records_match_the_abi_structures():
     assert F.report_dicts(arr) == [r.as_dict() for r in reps]
     batch = F.Batch(items)
     assert len(batch) == 3 and batch.slices.tobytes() == bytes(want)
+
+
+def test_binding_rejects_buffers_the_kernels_would_misread():
+    """Host-side checks of the binding (no GPU needed): wrong dtype, a
+    strided view, a wrong element count and a tensor in host memory are
+    refused before any pointer reaches the library."""
+    import numpy as np
+    import torch
+    from paper_1411_5057_amd import firls as F
+    n = 16
+    shapes = [F.Shape(n, "haar", 2), F.Shape(n, "tv", 0, channels=2)]
+    ok = dict(b=torch.zeros(n, n, dtype=torch.complex64), mask=torch.ones(n, n, dtype=torch.uint8),
+              x=torch.zeros(n, n, dtype=torch.complex64), lam=0.01)
+
+    def bad(**kw):
+        it = dict(ok, **kw)
+        with pytest.raises((ValueError, TypeError)) as e:
+            F.slice_array([it], shapes=shapes, prec="fp32")
+        return str(e.value)
+
+    assert "complex64" in bad(b=torch.zeros(n, n, dtype=torch.complex128))
+    assert "uint8" in bad(mask=torch.ones(n, n, dtype=torch.bool))
+    assert "contiguous" in bad(x=torch.zeros(n, 2 * n, dtype=torch.complex64)[:, ::2])
+    assert "elements" in bad(x=torch.zeros(n, n - 1, dtype=torch.complex64))
+    assert "elements" in bad(shape_id=1)          # two contrasts need 2 n^2 values
+    assert "out of range" in bad(shape_id=2)
+    assert "required" in bad(mask=None)           # only a dense sensing matrix may omit it
+    assert "torch tensor" in bad(b=np.zeros((n, n), np.complex64))
+    assert "GPU" in bad()                          # everything else right, but in host memory
+    with pytest.raises(ValueError, match="complex128"):
+        F.check_tensor(torch.zeros(4, dtype=torch.complex64), "x", torch.complex128, 4)
+    # without shapes the marshalling alone runs (host pointers are fine there)
+    assert len(F.slice_array([ok])) == 1
