@@ -16,19 +16,26 @@ template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { return c
 template <typename T> __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename T> __device__ __forceinline__ cplx<T> operator*(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+// Sums of two products are written as one explicit fused multiply-add and
+// one product.  Left to contraction, the compiler picks which product to
+// fuse per kernel, so the same formula could round differently in two
+// kernels that must agree bitwise (the FFT passes of the paired and the
+// separate PCG launches, say).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  return {fmat(a.x, b.x, -(a.y * b.y)), fmat(a.x, b.y, a.y * b.x)};
 }
 template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {  // a * conj(b)
-  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+  return {fmat(a.x, b.x, a.y * b.y), fmat(a.y, b.x, -(a.x * b.y))};
 }
 template <typename T> __device__ __forceinline__ double cabs2(cplx<T> a) {
-  return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  return fmat((double)a.x, (double)a.x, (double)a.y * (double)a.y);
 }
 template <typename T> __device__ __forceinline__ double cdot(cplx<T> a, cplx<T> b) {  // Re(conj(a) b)
-  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+  return fmat((double)a.x, (double)b.x, (double)a.y * (double)b.y);
 }
-template <typename T> __device__ __forceinline__ T cabs2t(cplx<T> a) { return a.x * a.x + a.y * a.y; }
+template <typename T> __device__ __forceinline__ T cabs2t(cplx<T> a) { return fmat(a.x, a.x, a.y * a.y); }
 
 // 1 / (rho + lambda d) of the pseudo-diagonal preconditioner (eq. 17).  Every
 // kernel that applies P^{-1} or sums <v, P^{-1} v> takes it from here, so
@@ -37,6 +44,11 @@ template <typename T> __device__ __forceinline__ T cabs2t(cplx<T> a) { return a.
 // symmetric positive definite and the same everywhere).
 __device__ __forceinline__ float pc_inv(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double pc_inv(double v) { return 1.0 / v; }
+// 1 / (rho + lambda d) with the denominator as one fused multiply-add, so
+// it rounds the same wherever it is formed (a separate lambda d product,
+// shared with the regulariser, would round it differently).
+__device__ __forceinline__ float pc_inv(float rho, float lam, float d) { return pc_inv(__builtin_fmaf(lam, d, rho)); }
+__device__ __forceinline__ double pc_inv(double rho, double lam, double d) { return pc_inv(__builtin_fma(lam, d, rho)); }
 
 // cos(2 pi e / 16) and sin(2 pi e / 16), e = 0..15.
 __device__ constexpr double kC16[16] = {

@@ -77,7 +77,7 @@ __device__ __forceinline__ void precond_tile_paper(cplx<T> (&v)[16], const T (&d
   haar_col<false>(v, L, col);
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const T iv = pc_inv(rho + lam * dv[s]);
+    const T iv = pc_inv(rho, lam, dv[s]);
     acc += (double)(cabs2t(v[s]) * iv);
     if (NEED_Z) v[s] = v[s] * iv;
   }
@@ -91,7 +91,7 @@ __device__ __forceinline__ void precond_tile_k(cplx<T> (&v)[16], const T* dg, in
     haar_col<false>(v, L, col);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const T iv = pc_inv(rho + lam * dg[s * N]);
+      const T iv = pc_inv(rho, lam, dg[s * N]);
       acc += (double)(cabs2t(v[s]) * iv);
       if (NEED_Z) v[s] = v[s] * iv;
     }
@@ -103,7 +103,7 @@ __device__ __forceinline__ void precond_tile_k(cplx<T> (&v)[16], const T* dg, in
     haar_diag_col(e, L, col);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const T iv = pc_inv(rho + lam * e[s]);
+      const T iv = pc_inv(rho, lam, e[s]);
       acc += (double)(cabs2t(v[s]) * iv);
       if (NEED_Z) v[s] = v[s] * iv;
     }
