@@ -215,6 +215,25 @@ int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_r
 int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices,
                         const firls_slice* slices, firls_report* reports);
 
+/* For callers that cannot allocate device memory during a solve: code
+ * running under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same as firls_solve_batched (same kernels, bitwise the
+ * same reports and x), but it allocates nothing: the slice tables, states
+ * and per-slice workspace live in a fixed array of
+ * FIRLS_NOALLOC_SCRATCH_BYTES (64 MiB) of device memory per GPU, which the
+ * library holds from its load until the process ends (the host-side slice
+ * tables were reserved for max_slices by firls_create).  All slices run at
+ * once with direct launches (the firls_set_chunk and firls_set_graphs
+ * settings do not apply); masked-FFT shapes only.  A batch whose tables and
+ * workspace do not fit (about 3.6 MB per 256^2 FP32 Haar slice, 17 such
+ * slices) is rejected with FIRLS_E_INVALID before any work.  Every call on
+ * a GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (from several threads, handles or streams) race and must not be made;
+ * each call initialises what it reads, so nothing carries over. */
+#define FIRLS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int firls_solve_batched_noalloc(firls_handle* h, void* stream, int32_t n_slices,
+                                const firls_slice* slices, firls_report* reports);
+
 /* ---- single-operator entry points (one slice; each blocks until done) -- */
 
 /* x = A^H b = F^H (mask * b)  (the zero-filled start, Section 3.3). */

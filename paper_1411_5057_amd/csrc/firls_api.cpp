@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <cmath>
 #include <cstring>
@@ -84,6 +85,37 @@ int32_t haar_internal_index(int n, int L, int gr, int gc) {
   return ((I << L) + s) * n + (J << L) + c;
 }
 
+// Device memory of firls_solve_batched_noalloc: one array per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in): the device address comes
+// from hipGetSymbolAddress, taken once per device at handle creation with
+// that device current.
+constexpr size_t kNoallocBytes = FIRLS_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char g_noalloc_scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The array's address on ``device`` (the current device), looked up once.
+int noalloc_scratch(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(FIRLS_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(FIRLS_E_HIP, std::string("hipGetSymbolAddress of the allocation-free scratch: ") +
+                                   hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return FIRLS_OK;
+}
+
 }  // namespace
 
 namespace firls {
@@ -142,6 +174,10 @@ struct firls_handle {
   hipGraphExec_t g_iter = nullptr;
   // sub-batch size chosen by firls_autotune (0: the whole batch at once)
   int chunk = 0;
+  // set while firls_solve_batched_noalloc runs: buffers must already fit
+  bool noalloc = false;
+  void* scratch = nullptr;   // this device's g_noalloc_scratch (null if the lookup failed)
+  std::string scratch_err;
 
   // learned-start staging: zero-filled and network starts [S, n, n] complex,
   // per-slice output pointers and a copy of the slice states
@@ -212,6 +248,8 @@ void free_batch(firls_handle* h) {
 }
 
 int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
+  if (h->noalloc && (bytes > h->ws_cap || std::max(slices, 2) > h->cap_slices))
+    return fail(FIRLS_E_INVALID, "internal: the allocation-free solve needs more memory than it checked for");
   if (bytes > h->ws_cap || std::max(slices, 2) > h->cap_slices) drop_graphs(h);
   if (bytes > h->ws_cap) {
     HIPCHK(hipStreamSynchronize(st));
@@ -1249,6 +1287,16 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
     delete h;
     return fail(FIRLS_E_HIP, "event creation failed");
   }
+  // slice tables and pinned staging for max_slices up front (the
+  // allocation-free solve relies on them), and this device's scratch
+  int rc = ensure_capacity(h, nullptr, 0, cfg->max_slices);
+  if (rc) {
+    const std::string msg = g_err;
+    firls_destroy(h);
+    return fail(rc, msg);
+  }
+  if (noalloc_scratch(h->device, &h->scratch)) h->scratch_err = g_err;
+  g_err.clear();
   *out = h;
   return FIRLS_OK;
 }
@@ -1283,6 +1331,72 @@ int firls_solve_batched(firls_handle* h, void* stream, int32_t n_slices, const f
   if (n_slices <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
   if (!slices || !reports) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
   g_err.clear();
+  return run_batch(h, (hipStream_t)stream, n_slices, slices, reports, h->cfg.max_outer, h->cfg.outer_tol);
+}
+
+int firls_solve_batched_noalloc(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices,
+                                firls_report* reports) {
+  if (!h) return fail(FIRLS_E_INVALID, "null handle");
+  if (n_slices <= 0) return fail(FIRLS_E_INVALID, "n_slices must be positive");
+  if (n_slices > h->cfg.max_slices) return fail(FIRLS_E_INVALID, "n_slices exceeds max_slices");
+  if (!slices || !reports) return fail(FIRLS_E_INVALID, "slices and reports must be non-null");
+  g_err.clear();
+  if (!h->scratch) return fail(FIRLS_E_HIP, "no allocation-free scratch on this device: " + h->scratch_err);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != h->device) return fail(FIRLS_E_INVALID, "the handle belongs to another device");
+  for (int i = 0; i < n_slices; ++i) {
+    int rc = check_slice(h, slices[i]);
+    if (rc) return rc;
+    if (h->shapes[slices[i].shape_id].dense)
+      return fail(FIRLS_E_UNSUPPORTED, "the allocation-free solve is for masked-FFT shapes");
+  }
+  // scratch layout: slice descs, slice states, the two slice lists, then
+  // each slice's workspace in call order (as run_chunk carves it)
+  const size_t ns = (size_t)n_slices;
+  const size_t o_state = align256(ns * sizeof(SliceDesc));
+  const size_t o_list = o_state + align256(ns * sizeof(SliceState));
+  const size_t o_ws = o_list + align256(2 * ns * sizeof(int32_t));
+  size_t need = 0;
+  for (int i = 0; i < n_slices; ++i) need += h->slice_bytes(h->shapes[slices[i].shape_id]);
+  if (o_ws + need > kNoallocBytes)
+    return fail(FIRLS_E_INVALID, "the batch needs " + std::to_string(o_ws + need) + " bytes of scratch; the "
+                "allocation-free solve has " + std::to_string(kNoallocBytes) + " (FIRLS_NOALLOC_SCRATCH_BYTES)");
+  if (std::max(n_slices, 2) > h->cap_slices) return fail(FIRLS_E_INVALID, "slice tables smaller than max_slices");
+  // Run the ordinary batched loop on the scratch: direct launches (no graph
+  // is captured or instantiated), all slices at once, no profiling events.
+  // The handle's own buffers and settings come back on every return path.
+  struct Swap {
+    firls_handle* h;
+    void* ws;
+    size_t ws_cap;
+    SliceDesc* desc;
+    SliceState* state;
+    int32_t* list;
+    bool graphs, prof;
+    int chunk;
+    ~Swap() {
+      h->ws = ws;
+      h->ws_cap = ws_cap;
+      h->d_desc = desc;
+      h->d_state = state;
+      h->d_list = list;
+      h->use_graphs = graphs;
+      h->profiling = prof;
+      h->chunk = chunk;
+      h->noalloc = false;
+    }
+  } keep{h, h->ws, h->ws_cap, h->d_desc, h->d_state, h->d_list, h->use_graphs, h->profiling, h->chunk};
+  char* base = static_cast<char*>(h->scratch);
+  h->d_desc = reinterpret_cast<SliceDesc*>(base);
+  h->d_state = reinterpret_cast<SliceState*>(base + o_state);
+  h->d_list = reinterpret_cast<int32_t*>(base + o_list);
+  h->ws = base + o_ws;
+  h->ws_cap = kNoallocBytes - o_ws;
+  h->use_graphs = false;
+  h->profiling = false;
+  h->chunk = 0;
+  h->noalloc = true;
   return run_batch(h, (hipStream_t)stream, n_slices, slices, reports, h->cfg.max_outer, h->cfg.outer_tol);
 }
 

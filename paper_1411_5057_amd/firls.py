@@ -42,7 +42,7 @@ FIRLS_PC_NONE = 2
 
 EXPORTED = (
     "firls_create", "firls_destroy", "firls_workspace_bytes", "firls_solve",
-    "firls_solve_batched", "firls_op_adjoint", "firls_op_weights",
+    "firls_solve_batched", "firls_solve_batched_noalloc", "firls_op_adjoint", "firls_op_weights",
     "firls_op_system", "firls_op_precond", "firls_op_objective",
     "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
@@ -202,6 +202,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_workspace_bytes": ([vp, i32, i32], ctypes.c_size_t),
         "firls_solve": ([vp, vp, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
         "firls_solve_batched": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
+        "firls_solve_batched_noalloc": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)],
+                                        ctypes.c_int),
         "firls_op_adjoint": ([vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "firls_op_weights": ([vp, vp, i32, vp, vp], ctypes.c_int),
         "firls_op_system": ([vp, vp, i32, vp, dbl, vp, vp, vp], ctypes.c_int),
@@ -283,6 +285,10 @@ def firls_solve(h, stream, sl: firls_slice, rep: firls_report) -> int:
 
 def firls_solve_batched(h, stream, n: int, slices, reports) -> int:
     return _check(load().firls_solve_batched(h, stream, n, slices, reports), "firls_solve_batched")
+
+
+def firls_solve_batched_noalloc(h, stream, n: int, slices, reports) -> int:
+    return _check(load().firls_solve_batched_noalloc(h, stream, n, slices, reports), "firls_solve_batched_noalloc")
 
 
 def firls_op_adjoint(h, stream, shape_id, b, mask, x) -> int:
@@ -548,6 +554,20 @@ class Solver:
         arr = slice_array(items, None, self.shapes, self.prec)
         reps = np.zeros(len(items), REPORT_DTYPE)
         firls_solve_batched(self.handle, _stream(stream), len(items), _as(arr, firls_slice), _as(reps, firls_report))
+        return report_dicts(reps)
+
+    def solve_batched_noalloc(self, items, stream=None):
+        """firls_solve_batched_noalloc: as solve_batched, with every device
+        buffer of the solve in the library's fixed per-GPU scratch (nothing
+        is allocated); items as for solve_batched."""
+        if isinstance(items, Batch):
+            firls_solve_batched_noalloc(self.handle, _stream(stream), len(items), _as(items.slices, firls_slice),
+                                        _as(items.reports, firls_report))
+            return items.reports.copy()
+        arr = slice_array(items, None, self.shapes, self.prec)
+        reps = np.zeros(len(items), REPORT_DTYPE)
+        firls_solve_batched_noalloc(self.handle, _stream(stream), len(items), _as(arr, firls_slice),
+                                    _as(reps, firls_report))
         return report_dicts(reps)
 
     # single-operator entry points
