@@ -76,11 +76,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--slices", type=int, default=256)
+    ap.add_argument("--slices", type=int, default=None,
+                    help="slices per step (default: 500 for mri, 32 for tv512, 1024 for fp64_64, 64 for uneven)")
+    ap.add_argument("--seed0", type=int, default=None,
+                    help="first seed of the batch (mri default: the 500 fresh evaluation seeds 20000-20499 of "
+                         "the learned-start workload, disjoint from the network's training seeds; else 0)")
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--pcg", type=int, default=4)
-    ap.add_argument("--max-outer", type=int, default=50)
-    ap.add_argument("--tau", type=float, default=8e-6)
+    ap.add_argument("--pcg", type=int, default=None, help="PCG iterations per outer iteration (workload default)")
+    ap.add_argument("--max-outer", type=int, default=None)
+    ap.add_argument("--tau", type=float, default=None)
+    ap.add_argument("--prec", choices=("fp32", "fp64"), default=None,
+                    help="working precision (tv512: fp32 by default, with the FP64 run of the same slices "
+                         "reported beside it)")
+    ap.add_argument("--no-fp64-ref", action="store_true", help="tv512: skip the FP64 comparison run")
     ap.add_argument("--ref-outer", type=int, default=300,
                     help="outer iterations of the reference solve that estimates the optimum")
     ap.add_argument("--no-profile", action="store_true")
@@ -99,18 +107,40 @@ def parse():
                     help="launch mode instead of the autotuner's choice (with --sub-batch)")
     ap.add_argument("--no-pair", action="store_true",
                     help="run the PCG row-inverse pass and the step as two launches (A/B of the paired pass)")
-    ap.add_argument("--workload", choices=("mri", "dense"), default="mri",
-                    help="mri: the 256^2 CS-MRI benchmark (default); dense: 64^2 images measured by one "
-                         "shared dense random projection (30%% of N rows), the MFMA path")
+    ap.add_argument("--workload", choices=("mri", "dense", "tv512", "fp64_64", "uneven"), default="mri",
+                    help="mri: the 256^2 tree-group CS-MRI benchmark (default); tv512: FIRLS_TV at 512^2; "
+                         "fp64_64: plain l1 FIRLS in FP64 at 64^2; uneven: 64 slices of mixed sizes and "
+                         "regularisers in one call; dense: 64^2 images measured by one shared dense random "
+                         "projection (30%% of N rows), the MFMA path")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    d = WORKLOAD_DEFAULTS[a.workload]
+    for k in ("slices", "pcg", "max_outer", "tau", "prec", "seed0"):
+        if getattr(a, k) is None:
+            setattr(a, k, d[k])
+    return a
 
 
-def make_inputs(B, n, torch):
+# Per workload: slices per step, PCG iterations per outer iteration, outer
+# cap, stop tolerance tau (relative F_eps decrease) and precision.  tau is
+# calibrated so that every slice ends within 1e-4 of its optimum.
+WORKLOAD_DEFAULTS = {
+    "mri": dict(seed0=20000, slices=500, pcg=4, max_outer=50, tau=8e-6, prec="fp32"),
+    "dense": dict(seed0=0, slices=256, pcg=10, max_outer=50, tau=1e-5, prec="fp32"),
+    # TV: the paper's run length for FIRLS_TV (29 outer iterations, Section
+    # 5.5.2); its MM iteration approaches the optimum slowly on
+    # piecewise-constant images with eps = 1e-10, so the gap is reported
+    "tv512": dict(seed0=0, slices=32, pcg=10, max_outer=30, tau=0.0, prec="fp32"),
+    "fp64_64": dict(seed0=0, slices=1024, pcg=20, max_outer=30, tau=0.0, prec="fp64"),
+    "uneven": dict(seed0=0, slices=64, pcg=4, max_outer=50, tau=8e-6, prec="fp32"),
+}
+
+
+def make_inputs(seeds, n, torch):
     import synth
     bs, ms, lams = [], [], []
-    for s in range(B):
+    for s in seeds:
         p = synth.cfg1(s, n=n)
         bs.append(p.b)
         ms.append(p.mask)
@@ -120,23 +150,55 @@ def make_inputs(B, n, torch):
     return p, b, m, lams
 
 
-def cpu_baseline(n, tau, max_outer, K, budget_s=12.0, max_slices=64):
-    """The FP64 oracle, untouched, on the first slices (seeds 0, 1, ...) of
-    the same workload, one after another until about ``budget_s`` seconds
-    of solving have passed."""
+def oracle_optima():
+    """F_eps* per seed written by tests/golden/make_golden.py (FP64 oracle,
+    300 outer x 20 PCG iterations), or {} if absent."""
+    path = os.path.join(ROOT, "tests", "golden", "optima_256.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return {int(r["seed"]): float(r["F_eps"]) for r in json.load(f)["optima"]}
+
+
+def cpu_baseline(n, tau, max_outer, K, seeds, gpu_x, gpu_fe, budget_s=12.0, max_slices=64):
+    """The FP64 oracle, untouched, on the first slices of the same workload
+    (the first seeds of the timed batch), one after another until about
+    ``budget_s`` seconds of solving have passed.  Each oracle result is also
+    the reference of the GPU's result for the same slice (plain start, same
+    K, tau and cap): the per-result error against the FP64 oracle."""
     import synth
     from oracle.firls import Operators, firls
     solved, outer, dt = 0, 0, 0.0
-    while solved < max_slices and dt < budget_s:
-        ops = Operators.from_problem(synth.cfg1(solved, n=n))
+    errs = []
+    while solved < min(max_slices, len(seeds)) and dt < budget_s:
+        ops = Operators.from_problem(synth.cfg1(seeds[solved], n=n))
         t0 = time.perf_counter()
         rep = firls(ops, max_outer, K, tau=tau)
         dt += time.perf_counter() - t0
+        x = gpu_x[solved].astype(np.complex128)
+        fe = ops.objective(x)[0]
+        errs.append({"seed": seeds[solved], "outer_gpu": int(gpu_fe[solved][1]), "outer_oracle": rep.outer_iters,
+                     "F_eps_rel_diff": abs(fe - rep.F_eps) / rep.F_eps,
+                     "F_eps_reported_vs_fp64": abs(gpu_fe[solved][0] - fe) / fe,
+                     "x_rel_l2": float(np.linalg.norm(x - rep.x) / np.linalg.norm(rep.x)),
+                     "x_max_rel": float(np.max(np.abs(x - rep.x)) / np.max(np.abs(rep.x)))})
         solved += 1
         outer += rep.outer_iters
+    same = [e for e in errs if e["outer_gpu"] == e["outer_oracle"]]
+    per_result = {
+        "slices": len(errs), "same_outer_count": len(same),
+        "F_eps_rel_diff_max": max(e["F_eps_rel_diff"] for e in errs),
+        "F_eps_rel_diff_max_same_count": max([e["F_eps_rel_diff"] for e in same], default=None),
+        "x_rel_l2_max_same_count": max([e["x_rel_l2"] for e in same], default=None),
+        "x_max_rel_max_same_count": max([e["x_max_rel"] for e in same], default=None),
+        "reported_F_eps_vs_fp64_max": max(e["F_eps_reported_vs_fp64"] for e in errs),
+        "note": "GPU plain-start results against the FP64 oracle run from the same start with the same K, tau and "
+                "cap; x compared where both took the same number of outer iterations",
+        "per_slice": errs}
     return {"value": solved / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solved} slices (seeds 0-{solved - 1}) of the same workload, {outer / solved:.1f} outer x "
-                      f"{K} PCG on average, numpy FP64, single process; {dt:.1f} s of solving"}
+            "sample": f"{solved} slices (seeds {seeds[0]}-{seeds[solved - 1]}) of the same workload, "
+                      f"{outer / solved:.1f} outer x {K} PCG on average, numpy FP64, single process; "
+                      f"{dt:.1f} s of solving"}, per_result
 
 
 def timed(solver, run, steps, warmup, profile, torch):
@@ -277,6 +339,144 @@ def run_dense(a, torch, F):
     solver.close()
 
 
+def psi_bytes_per_px(cls: str, psi: str, K: int, prec: str, paired: bool) -> float:
+    """Algorithmic HBM bytes per pixel of one launch of a kernel class for
+    one shape kind (the paper's preconditioner).  FP64 doubles every vector
+    and real array (the mask bits stay 1 bit per pixel).  TV, per PCG
+    iteration: rowfwd reads z and p, writes p and t (32; 24 at k = 0); col
+    reads t and the mask bits, writes t; rowinv reads t, p, both weights,
+    writes q (32); update reads x, p, q, r, both weights, writes x, r, z
+    (64).  Per outer iteration: |D x|^2 (read x, write 2 reals: 16), W (read
+    2 reals, write 1: 12), d (16), the residual passes (16, 25, 32) and z0
+    (read r and both weights, write z: 24)."""
+    sc = 2.0 if prec == "fp64" else 1.0
+    if psi == "haar":
+        b = bytes_per_px(cls, K, True, paired)
+        return (b - 0.125) * sc + 0.125 if cls == "col" else b * sc
+    tv = {"rowfwd": 32.0 - 8.0 / K, "col": 16.125, "rowinv": 32.0, "update": 64.0, "psi_sq": 16.0,
+          "group_w": 12.0, "group_d": 16.0, "r0_rowfwd": 16.0, "r0_col": 25.0, "r0_rowinv": 32.0,
+          "r0_update": 24.0, "adjoint": 33.0}.get(cls, 0.0)
+    return (tv - 0.125) * sc + 0.125 if cls == "col" else tv * sc
+
+
+def workload_problems(a):
+    import synth
+    if a.workload == "tv512":
+        return [synth.cfg2(s) for s in range(a.seed0, a.seed0 + a.slices)], "FIRLS_TV, 512x512, 40 ellipses + ramp, " \
+            "15% radial mask, sigma 0.005, periodic isotropic TV, lambda 0.01, eps 1e-10"
+    if a.workload == "fp64_64":
+        return [synth.cfg0(s) for s in range(a.seed0, a.seed0 + a.slices)], "plain l1 FIRLS_OG, 64x64, 25% VD mask, " \
+            "sigma 0.01, 3-level Haar, singleton groups, lambda 0.035, eps 1e-10"
+    return synth.cfg3_set(a.seed0, count=a.slices), \
+        "uneven batch: sizes from {128,192,256,384,512}^2, 15-30% VD masks, sigma and lambda U[0.005,0.05], " \
+        "tree-group Haar (L=4) and isotropic TV mixed 50/50, one call"
+
+
+def run_workload(a, torch, F):
+    """TV 512^2, FP64 64^2 and the uneven batch: one step = one batched
+    solve of the workload's slices."""
+    probs, desc = workload_problems(a)
+    prec, K, B = a.prec, a.pcg, len(probs)
+    keys = []
+    for p in probs:
+        k = (p.n, p.psi, p.levels)
+        if k not in keys:
+            keys.append(k)
+    shapes = []
+    for (n, psi, L) in keys:
+        ref = next(p for p in probs if (p.n, p.psi, p.levels) == (n, psi, L))
+        shapes.append(F.Shape(n, psi, L, ref.group_ptr, ref.group_idx))
+    sid = [keys.index((p.n, p.psi, p.levels)) for p in probs]
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+
+    def items_for(dt):
+        out = []
+        for p, k in zip(probs, sid):
+            b = torch.from_numpy(p.b).to(dt).cuda()
+            out.append(dict(b=b, mask=torch.from_numpy(p.mask).cuda(), x=torch.zeros_like(b), lam=p.lam, shape_id=k))
+        return out
+
+    solver = F.Solver(shapes, prec=prec, max_slices=B, max_outer=a.max_outer, pcg_iters=K, outer_tol=a.tau,
+                      eps=1e-10)
+    items = items_for(cdt)
+    if a.sub_batch >= 0:
+        solver.set_chunk(a.sub_batch)
+        solver.set_graphs(a.launch != "direct")
+        chunk = a.sub_batch
+    else:
+        chunk = solver.autotune(items) if not a.no_tune else 0
+    batch = solver.prepare(items)
+    run = lambda: (solver.solve_batched(batch), None)
+    dt, (reps, _), _ = timed(solver, run, a.steps, a.warmup, False, torch)
+    prof = {}
+    if not a.no_profile:
+        _, _, prof = timed(solver, run, 1, 0, True, torch)
+        per_shape = [solver.profile_read(i) for i in range(len(shapes))]
+    outer = np.array([r["outer_iters"] for r in reps])
+    pcg = np.array([r["pcg_iters"] for r in reps])
+    fe = np.array([r["F_eps"] for r in reps])
+    out = {"metric": f"solves/s ({a.workload})", "value": B * a.steps / dt, "unit": "solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "f64",
+           "data": "synthetic (seeded ellipse phantoms, VD or radial masks, complex Gaussian noise)",
+           "config": {"workload": f"{desc}; {B} slices per step, {K} PCG per outer, stop at rel. F_eps decrease "
+                                  f"{a.tau:g} (max {a.max_outer})", "slices": B, "pcg_iters": K, "tau": a.tau,
+                      "max_outer": a.max_outer, "prec": prec, "sub_batch": chunk,
+                      "launch": "graphs" if solver.graphs else "direct",
+                      "shapes": [f"{n}x{n} {psi}" for (n, psi, _) in keys]},
+           "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
+           "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
+           "converged_frac": float(np.mean([r["converged"] for r in reps]))}
+    if prof:
+        pcg_cls = ("rowfwd", "col", "rowinv", "update", "last_x")
+        paired = prec == "fp32"
+        tot_bytes, cls_bytes = 0.0, {}
+        for i, (n, psi, _) in enumerate(keys):
+            ps = per_shape[i]
+            pr = paired and 0 < ps.get("rowinv", {}).get("launches", 0) < ps.get("col", {}).get("launches", 0)
+            for c, v in ps.items():
+                bb = psi_bytes_per_px(c, "haar" if psi == "haar" else "tv", K, prec, pr) * n * n * v["slice_launches"]
+                tot_bytes += bb
+                cls_bytes[c] = cls_bytes.get(c, 0.0) + bb
+        dom = max((c for c in prof if c in pcg_cls and prof[c]["launches"]), key=lambda c: prof[c]["ms"])
+        v = prof[dom]
+        ach = cls_bytes[dom] / (v["ms"] / 1e3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": v["ms"] / v["launches"] * 1e3,
+                           "bytes_per_launch": cls_bytes[dom] / v["launches"]}
+        out["hbm_gbs_algorithmic"] = tot_bytes / (dt / a.steps) / 1e9
+        out["kernel_ms"] = {c: round(u["ms"], 3) for c, u in prof.items() if u["launches"]}
+        out["launches_per_step"] = int(sum(u["launches"] for u in prof.values()))
+    if not a.no_gap:
+        ref = F.Solver(shapes, prec=prec, max_slices=B, max_outer=a.ref_outer, pcg_iters=K, outer_tol=0.0, eps=1e-10)
+        rit = items_for(cdt)
+        rr = ref.solve_batched(rit)
+        out["gap_to_optimum"] = gap_stats(fe, np.array([r["F_eps"] for r in rr]))
+        out["gap_to_optimum"]["reference"] = f"same slices, {a.ref_outer} outer iterations, tau = 0"
+        by = {}
+        for (n, psi, _), r, f0 in zip([keys[k] for k in sid], rr, fe):
+            by.setdefault(psi, []).append((f0 - r["F_eps"]) / r["F_eps"])
+        out["gap_to_optimum"]["max_by_kind"] = {k: float(np.max(v)) for k, v in by.items()}
+        ref.close()
+    if a.workload == "tv512" and prec == "fp32" and not a.no_fp64_ref:
+        # the same slices in FP64 with the same K, tau and cap
+        s64 = F.Solver(shapes, prec="fp64", max_slices=B, max_outer=a.max_outer, pcg_iters=K, outer_tol=a.tau,
+                       eps=1e-10)
+        it64 = items_for(torch.complex128)
+        r64 = s64.solve_batched(it64)
+        dx = [float(torch.linalg.vector_norm(u["x"].to(torch.complex128) - w["x"]) / torch.linalg.vector_norm(w["x"]))
+              for u, w in zip(items, it64)]
+        f64 = np.array([r["F_eps"] for r in r64])
+        o64 = np.array([r["outer_iters"] for r in r64])
+        out["fp32_vs_fp64"] = {"F_eps_rel_diff_max": float(np.max(np.abs(fe - f64) / f64)),
+                               "x_rel_l2_max": max(dx), "same_outer_count_frac": float(np.mean(o64 == outer)),
+                               "fp64_outer_iters_mean": float(o64.mean())}
+        s64.close()
+    print(json.dumps(out))
+    solver.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -291,6 +491,8 @@ def main():
     torch.cuda.set_device(dev)
     if a.workload == "dense":
         return run_dense(a, torch, F)
+    if a.workload in ("tv512", "fp64_64", "uneven"):
+        return run_workload(a, torch, F)
     B, n, K = a.slices, a.n, a.pcg
     if a.copy_calib_mb:
         src = torch.ones(a.copy_calib_mb << 18, dtype=torch.float32, device=dev)
@@ -298,7 +500,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p0, b, m, lams = make_inputs(B, n, torch)
+    seeds = list(range(a.seed0, a.seed0 + B))
+    p0, b, m, lams = make_inputs(seeds, n, torch)
     shape = F.Shape(n, "haar", 4, p0.group_ptr, p0.group_idx)
     pc = {"paper": F.FIRLS_PC_PAPER, "jacobi": F.FIRLS_PC_JACOBI, "none": F.FIRLS_PC_NONE}[a.precond]
     solver = F.Solver([shape], prec="fp32", max_slices=B, max_outer=a.max_outer, pcg_iters=K,
@@ -342,7 +545,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded ellipse phantoms, VD masks, complex Gaussian noise)",
         "config": {"workload": f"tree-group FIRLS_OG, {n}x{n}, 20% VD mask, sigma 0.01, 4-level Haar, "
-                               f"quadtree-pair groups, lambda 0.035, eps 1e-10, {B} slices per step, "
+                               f"quadtree-pair groups, lambda 0.035, eps 1e-10, {B} slices per step "
+                               f"(seeds {seeds[0]}-{seeds[-1]}), "
                                f"{K} PCG per outer, stop at rel. F_eps decrease {a.tau:g} (max {a.max_outer}), "
                                f"start: {'learned warm start (network + data consistency, A^H b fallback)' if use_learned else 'A^H b'}",
                    "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer,
@@ -379,12 +583,32 @@ def main():
         if plain is not None:
             plain["gap_to_optimum"] = gap_stats(plain["fe"], fstar)
         ref.close()
+    # the oracle's optima where they are stored (golden seeds of this batch)
+    fstar_or = oracle_optima()
+    gold = [(i, sd) for i, sd in enumerate(seeds) if sd in fstar_or]
+    if gold and n == 256:
+        fs = np.array([fstar_or[sd] for _, sd in gold])
+        g = {"seeds": f"{len(gold)} slices with a stored oracle optimum "
+                      f"(tests/golden/optima_256.json: FP64 oracle, 300 outer x 20 PCG)",
+             "gap": gap_stats(np.array([fe[i] for i, _ in gold]), fs)}
+        if plain is not None:
+            g["gap_plain"] = gap_stats(np.array([plain["fe"][i] for i, _ in gold]), fs)
+        out["gap_to_oracle_optimum"] = g
     if plain is not None:
+        out["outer_iters_saved"] = {"mean": plain["outer_iters_mean"] - out["outer_iters_mean"],
+                                    "frac": 1.0 - out["outer_iters_mean"] / plain["outer_iters_mean"]}
         plain.pop("fe")
         out["plain"] = plain
         out["learned_speedup_vs_plain"] = value / plain["value"]
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, a.tau, a.max_outer, K)
+        # the x buffers hold the last timed call's results, which are from
+        # the plain start (A^H b) whether or not the learned leg ran first
+        xs = x.cpu().numpy()
+        last = reps_p if use_learned else reps
+        cb, per = cpu_baseline(n, a.tau, a.max_outer, K, seeds, xs,
+                               [(r["F_eps"], r["outer_iters"]) for r in last])
+        out["cpu_baseline"] = cb
+        out["error_vs_fp64_oracle"] = per
     print(json.dumps(out))
     if net is not None:
         net.close()

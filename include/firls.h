@@ -149,7 +149,15 @@ typedef struct {
  *               reports 10 to 30 sufficient).
  *   outer_tol   tau: stop once (F_eps^{k-1} - F_eps^k) <= tau F_eps^k; 0
  *               runs max_outer solves.
- *   precond     FIRLS_PC_*. */
+ *   precond     FIRLS_PC_*.
+ *   workspace   optional caller-owned device buffer (256-byte aligned) of
+ *               workspace_bytes >= firls_workspace_bytes(cfg) bytes for the
+ *               per-slice vectors, weights and partial sums of every solve
+ *               (a torch tensor, say); NULL lets the library allocate and
+ *               grow its own on demand.  It must stay valid until
+ *               firls_destroy and is used by one call at a time.  The
+ *               learned start's staging and the split-K scratch of dense
+ *               sensing matrices are still the library's. */
 typedef struct {
   int32_t n_shapes;
   const firls_shape* shapes;
@@ -160,6 +168,8 @@ typedef struct {
   int32_t pcg_iters;
   double outer_tol;
   int32_t precond;
+  void* workspace;
+  size_t workspace_bytes;
 } firls_config;
 
 /* One image to reconstruct.  b, mask and x are device pointers of the
@@ -198,9 +208,17 @@ int firls_create(const firls_config* cfg, firls_handle** out);
 /* Release the handle and all device memory it owns (NULL is a no-op). */
 int firls_destroy(firls_handle* h);
 
-/* Device bytes the per-slice workspace needs for ``n`` slices of shape
- * ``shape_id`` (for budgeting; allocation stays internal). */
-size_t firls_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n);
+/* Device bytes of the workspace a handle for this configuration needs to
+ * solve any batch of up to max_slices slices of its shapes at once:
+ * max_slices times the largest per-slice workspace (about 3.6 MB for a
+ * 256^2 FP32 Haar slice).  0 for an invalid configuration.  Computed from
+ * the configuration alone (no device calls), so a caller can allocate the
+ * buffer before firls_create. */
+size_t firls_workspace_bytes(const firls_config* cfg);
+
+/* Device bytes of the workspace of ``n`` slices of shape ``shape_id`` (a
+ * streamed batch needs only its slots' worth). */
+size_t firls_slice_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n);
 
 /* FIRLS_OG (Algorithm 2) or FIRLS_TV (Algorithm 3) on one slice.  Blocks
  * until the report is written. */
@@ -408,6 +426,10 @@ int firls_profile(firls_handle* h, int32_t enable);
 
 /* Copy up to n class totals into out; returns the number written. */
 int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out);
+
+/* The same totals restricted to the launches of one shape (a batch mixing
+ * shapes launches every kernel once per shape present). */
+int firls_profile_read_shape(const firls_handle* h, int32_t shape_id, int32_t n, firls_kernel_stat* out);
 
 /* Thread-local text of the last error (empty string if none). */
 const char* firls_last_error(void);

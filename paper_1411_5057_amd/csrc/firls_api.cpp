@@ -199,14 +199,25 @@ struct firls_handle {
   double prof_ms[FIRLS_PROF_CLASSES] = {};
   int64_t prof_launches[FIRLS_PROF_CLASSES] = {};
   int64_t prof_units[FIRLS_PROF_CLASSES] = {};
+  // the same per shape (index shape * FIRLS_PROF_CLASSES + class)
+  std::vector<double> prof_ms_shape;
+  std::vector<int64_t> prof_launches_shape, prof_units_shape;
 
   size_t slice_bytes(const Shape& s) const {
-    const size_t vec = align256(s.pixels() * elt);
-    const size_t nvec = s.psi == PSI_TV ? 6 : 4;
-    return nvec * vec + 2 * align256((size_t)s.n_coef * relt) + align256((size_t)s.n_groups * relt) +
-           align256(s.pixels() / 8) + align256((size_t)SLOT_COUNT * PMAX * sizeof(double)) +
-           (s.dense ? align256((size_t)s.Mp * elt) : 0);
+    return slice_bytes_of(s.pixels(), s.psi == PSI_TV, (size_t)s.n_coef, (size_t)s.n_groups, s.dense ? s.Mp : 0,
+                          elt, relt);
   }
+  // Workspace of one slice (fill_desc carves it in this order): r, p, q, t
+  // (and for TV a second r and z), d and |Psi x|^2 per coefficient, W per
+  // group, the packed mask, the partial sums, and A v for a dense matrix.
+  static size_t slice_bytes_of(size_t pixels, bool tv, size_t n_coef, size_t n_groups, int Mp, size_t elt,
+                               size_t relt) {
+    const size_t vec = align256(pixels * elt);
+    const size_t nvec = tv ? 6 : 4;
+    return nvec * vec + 2 * align256(n_coef * relt) + align256(n_groups * relt) + align256(pixels / 8) +
+           align256((size_t)SLOT_COUNT * PMAX * sizeof(double)) + (Mp ? align256((size_t)Mp * elt) : 0);
+  }
+  bool ws_owned = true;   // false: the workspace is the caller's (firls_config.workspace)
 };
 
 namespace {
@@ -225,7 +236,7 @@ void free_batch(firls_handle* h) {
   if (h->gscr) (void)hipFree(h->gscr);
   h->gscr = nullptr;
   h->gscr_cap = 0;
-  if (h->ws) (void)hipFree(h->ws);
+  if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   if (h->d_desc) (void)hipFree(h->d_desc);
   if (h->d_state) (void)hipFree(h->d_state);
   if (h->d_list) (void)hipFree(h->d_list);
@@ -234,8 +245,10 @@ void free_batch(firls_handle* h) {
   if (h->h_list) (void)hipHostFree(h->h_list);
   if (h->h_flags) (void)hipHostFree(h->h_flags);
   if (h->h_refill) (void)hipHostFree(h->h_refill);
-  h->ws = nullptr;
-  h->ws_cap = 0;
+  if (h->ws_owned) {
+    h->ws = nullptr;
+    h->ws_cap = 0;
+  }
   h->d_desc = nullptr;
   h->d_state = nullptr;
   h->d_list = nullptr;
@@ -250,6 +263,9 @@ void free_batch(firls_handle* h) {
 int ensure_capacity(firls_handle* h, hipStream_t st, size_t bytes, int slices) {
   if (h->noalloc && (bytes > h->ws_cap || std::max(slices, 2) > h->cap_slices))
     return fail(FIRLS_E_INVALID, "internal: the allocation-free solve needs more memory than it checked for");
+  if (!h->ws_owned && bytes > h->ws_cap)
+    return fail(FIRLS_E_INVALID, "the caller's workspace holds " + std::to_string(h->ws_cap) + " bytes; this call needs " +
+                                     std::to_string(bytes));
   if (bytes > h->ws_cap || std::max(slices, 2) > h->cap_slices) drop_graphs(h);
   if (bytes > h->ws_cap) {
     HIPCHK(hipStreamSynchronize(st));
@@ -630,6 +646,12 @@ int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg,
     h->prof_ms[r.cls] += ms;
     h->prof_launches[r.cls] += 1;
     h->prof_units[r.cls] += units;
+    const size_t k = (size_t)r.group * FIRLS_PROF_CLASSES + r.cls;
+    if (r.group >= 0 && k < h->prof_ms_shape.size()) {
+      h->prof_ms_shape[k] += ms;
+      h->prof_launches_shape[k] += 1;
+      h->prof_units_shape[k] += units;
+    }
   }
   h->recs.clear();
   h->ev_used = 0;
@@ -1262,9 +1284,19 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
   if (!(cfg->outer_tol >= 0.0)) return fail(FIRLS_E_INVALID, "outer_tol must be >= 0");
   if (cfg->precond != FIRLS_PC_PAPER && cfg->precond != FIRLS_PC_JACOBI && cfg->precond != FIRLS_PC_NONE)
     return fail(FIRLS_E_INVALID, "precond must be FIRLS_PC_PAPER, FIRLS_PC_JACOBI or FIRLS_PC_NONE");
+  if (cfg->workspace && (reinterpret_cast<uintptr_t>(cfg->workspace) & 255))
+    return fail(FIRLS_E_INVALID, "workspace must be 256-byte aligned");
+  if (cfg->workspace && cfg->workspace_bytes < firls_workspace_bytes(cfg))
+    return fail(FIRLS_E_INVALID, "workspace_bytes is smaller than firls_workspace_bytes(cfg) = " +
+                                     std::to_string(firls_workspace_bytes(cfg)));
   firls_handle* h = new firls_handle();
   h->cfg = *cfg;
   h->cfg.shapes = nullptr;
+  if (cfg->workspace) {
+    h->ws = cfg->workspace;
+    h->ws_cap = cfg->workspace_bytes;
+    h->ws_owned = false;
+  }
   h->fp64 = cfg->prec == FIRLS_FP64;
   h->elt = h->fp64 ? 16 : 8;
   h->relt = h->fp64 ? 8 : 4;
@@ -1314,9 +1346,27 @@ int firls_destroy(firls_handle* h) {
   return FIRLS_OK;
 }
 
-size_t firls_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n) {
+size_t firls_slice_workspace_bytes(const firls_handle* h, int32_t shape_id, int32_t n) {
   if (!h || shape_id < 0 || shape_id >= (int)h->shapes.size() || n < 0) return 0;
   return (size_t)n * h->slice_bytes(h->shapes[shape_id]);
+}
+
+size_t firls_workspace_bytes(const firls_config* cfg) {
+  if (!cfg || cfg->n_shapes <= 0 || !cfg->shapes || cfg->max_slices <= 0) return 0;
+  const bool fp64 = cfg->prec == FIRLS_FP64;
+  const size_t elt = fp64 ? 16 : 8, relt = fp64 ? 8 : 4;
+  size_t most = 0;
+  for (int i = 0; i < cfg->n_shapes; ++i) {
+    const firls_shape& in = cfg->shapes[i];
+    const bool tv = in.psi == FIRLS_PSI_TV || in.psi == FIRLS_PSI_TV_PAPER;
+    const size_t C = in.channels <= 0 ? 1 : (size_t)in.channels;
+    const size_t pixels = C * (size_t)in.n * (size_t)in.n;
+    const size_t n_coef = tv ? 2 * pixels : pixels;
+    const size_t n_groups = in.n_groups > 0 ? (size_t)in.n_groups : (size_t)in.n * (size_t)in.n;
+    const int Mp = in.op == FIRLS_OP_DENSE ? (in.m + GEMM_BM - 1) / GEMM_BM * GEMM_BM : 0;
+    most = std::max(most, firls_handle::slice_bytes_of(pixels, tv, n_coef, n_groups, Mp, elt, relt));
+  }
+  return most * (size_t)cfg->max_slices;
 }
 
 int firls_solve(firls_handle* h, void* stream, const firls_slice* slice, firls_report* report) {
@@ -1408,23 +1458,47 @@ int firls_profile(firls_handle* h, int32_t enable) {
     h->prof_launches[c] = 0;
     h->prof_units[c] = 0;
   }
+  const size_t ks = h->shapes.size() * FIRLS_PROF_CLASSES;
+  h->prof_ms_shape.assign(ks, 0.0);
+  h->prof_launches_shape.assign(ks, 0);
+  h->prof_units_shape.assign(ks, 0);
   h->recs.clear();
   h->ev_used = 0;
   return FIRLS_OK;
 }
 
+namespace {
+const char* const kProfNames[FIRLS_PROF_CLASSES] = {
+    "init", "adjoint", "psi_sq", "group_w", "group_d", "r0_rowfwd", "r0_col", "r0_rowinv",
+    "r0_update", "check", "rowfwd", "col", "rowinv", "update", "last_x"};
+}  // namespace
+
 int firls_profile_read(const firls_handle* h, int32_t n, firls_kernel_stat* out) {
   if (!h || !out || n < 0) return fail(FIRLS_E_INVALID, "null argument");
-  static const char* names[FIRLS_PROF_CLASSES] = {
-      "init", "adjoint", "psi_sq", "group_w", "group_d", "r0_rowfwd", "r0_col", "r0_rowinv",
-      "r0_update", "check", "rowfwd", "col", "rowinv", "update", "last_x"};
   const int m = std::min<int>(n, FIRLS_PROF_CLASSES);
   for (int c = 0; c < m; ++c) {
     std::memset(&out[c], 0, sizeof(out[c]));
-    std::strncpy(out[c].name, names[c], sizeof(out[c].name) - 1);
+    std::strncpy(out[c].name, kProfNames[c], sizeof(out[c].name) - 1);
     out[c].launches = h->prof_launches[c];
     out[c].slice_launches = h->prof_units[c];
     out[c].ms = h->prof_ms[c];
+  }
+  return m;
+}
+
+int firls_profile_read_shape(const firls_handle* h, int32_t shape_id, int32_t n, firls_kernel_stat* out) {
+  if (!h || !out || n < 0) return fail(FIRLS_E_INVALID, "null argument");
+  if (shape_id < 0 || shape_id >= (int)h->shapes.size()) return fail(FIRLS_E_INVALID, "shape_id out of range");
+  const int m = std::min<int>(n, FIRLS_PROF_CLASSES);
+  for (int c = 0; c < m; ++c) {
+    const size_t k = (size_t)shape_id * FIRLS_PROF_CLASSES + c;
+    std::memset(&out[c], 0, sizeof(out[c]));
+    std::strncpy(out[c].name, kProfNames[c], sizeof(out[c].name) - 1);
+    if (k < h->prof_ms_shape.size()) {
+      out[c].launches = h->prof_launches_shape[k];
+      out[c].slice_launches = h->prof_units_shape[k];
+      out[c].ms = h->prof_ms_shape[k];
+    }
   }
   return m;
 }

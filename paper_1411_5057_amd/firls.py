@@ -41,10 +41,10 @@ FIRLS_PC_JACOBI = 1
 FIRLS_PC_NONE = 2
 
 EXPORTED = (
-    "firls_create", "firls_destroy", "firls_workspace_bytes", "firls_solve",
+    "firls_create", "firls_destroy", "firls_workspace_bytes", "firls_slice_workspace_bytes", "firls_solve",
     "firls_solve_batched", "firls_solve_batched_noalloc", "firls_op_adjoint", "firls_op_weights",
     "firls_op_system", "firls_op_precond", "firls_op_objective",
-    "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_last_error",
+    "firls_op_outer_step", "firls_profile", "firls_profile_read", "firls_profile_read_shape", "firls_last_error",
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
     "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_test_hooks", "firls_autotune",
@@ -63,7 +63,8 @@ class firls_config(ctypes.Structure):
     _fields_ = [("n_shapes", ctypes.c_int32), ("shapes", ctypes.POINTER(firls_shape)),
                 ("max_slices", ctypes.c_int32), ("prec", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
-                ("outer_tol", ctypes.c_double), ("precond", ctypes.c_int32)]
+                ("outer_tol", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class firls_slice(ctypes.Structure):
@@ -199,7 +200,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "firls_create": ([ctypes.POINTER(firls_config), ctypes.POINTER(vp)], ctypes.c_int),
         "firls_destroy": ([vp], ctypes.c_int),
-        "firls_workspace_bytes": ([vp, i32, i32], ctypes.c_size_t),
+        "firls_workspace_bytes": ([ctypes.POINTER(firls_config)], ctypes.c_size_t),
+        "firls_slice_workspace_bytes": ([vp, i32, i32], ctypes.c_size_t),
         "firls_solve": ([vp, vp, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
         "firls_solve_batched": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)], ctypes.c_int),
         "firls_solve_batched_noalloc": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(firls_report)],
@@ -212,6 +214,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_op_outer_step": ([vp, vp, i32, vp, vp, dbl, vp], ctypes.c_int),
         "firls_profile": ([vp, i32], ctypes.c_int),
         "firls_profile_read": ([vp, i32, ctypes.POINTER(firls_kernel_stat)], ctypes.c_int),
+        "firls_profile_read_shape": ([vp, i32, i32, ctypes.POINTER(firls_kernel_stat)], ctypes.c_int),
         "firls_last_error": ([], ctypes.c_char_p),
         "firls_set_graphs": ([vp, i32], ctypes.c_int),
         "firls_set_chunk": ([vp, i32], ctypes.c_int),
@@ -275,8 +278,12 @@ def firls_destroy(h) -> int:
     return load().firls_destroy(h)
 
 
-def firls_workspace_bytes(h, shape_id: int, n: int) -> int:
-    return int(load().firls_workspace_bytes(h, shape_id, n))
+def firls_workspace_bytes(cfg: firls_config) -> int:
+    return int(load().firls_workspace_bytes(ctypes.byref(cfg)))
+
+
+def firls_slice_workspace_bytes(h, shape_id: int, n: int) -> int:
+    return int(load().firls_slice_workspace_bytes(h, shape_id, n))
 
 
 def firls_solve(h, stream, sl: firls_slice, rep: firls_report) -> int:
@@ -324,6 +331,13 @@ def firls_profile(h, enable: bool) -> int:
 def firls_profile_read(h) -> dict:
     arr = (firls_kernel_stat * PROF_CLASSES)()
     m = _check(load().firls_profile_read(h, PROF_CLASSES, arr), "firls_profile_read")
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "slice_launches": arr[i].slice_launches,
+                                   "ms": arr[i].ms} for i in range(m)}
+
+
+def firls_profile_read_shape(h, shape_id: int) -> dict:
+    arr = (firls_kernel_stat * PROF_CLASSES)()
+    m = _check(load().firls_profile_read_shape(h, shape_id, PROF_CLASSES, arr), "firls_profile_read_shape")
     return {arr[i].name.decode(): {"launches": arr[i].launches, "slice_launches": arr[i].slice_launches,
                                    "ms": arr[i].ms} for i in range(m)}
 
@@ -486,7 +500,11 @@ class Solver:
 
     def __init__(self, shapes: Sequence[Shape], *, prec: str = "fp32", max_slices: int = 1,
                  eps: float = 1e-10, max_outer: int = 50, pcg_iters: int = 20,
-                 outer_tol: float = 0.0, precond: int = FIRLS_PC_PAPER):
+                 outer_tol: float = 0.0, precond: int = FIRLS_PC_PAPER, workspace=None):
+        """workspace: None (the library allocates its own), True (a torch
+        buffer of firls_workspace_bytes(cfg) is allocated here and handed
+        over), or a contiguous uint8 torch tensor on the GPU of at least
+        that size; it is kept alive as long as the solver."""
         self.shapes = list(shapes)
         self._cshapes = (firls_shape * len(self.shapes))(*[s.c() for s in self.shapes])
         cfg = firls_config()
@@ -499,6 +517,16 @@ class Solver:
         cfg.pcg_iters = pcg_iters
         cfg.outer_tol = outer_tol
         cfg.precond = precond
+        self.workspace = None
+        if workspace is not None and workspace is not False:
+            import torch
+            need = firls_workspace_bytes(cfg)
+            if workspace is True:
+                workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+            check_tensor(workspace, "workspace", torch.uint8, workspace.numel())
+            cfg.workspace = int(workspace.data_ptr())
+            cfg.workspace_bytes = int(workspace.numel())
+            self.workspace = workspace
         self.cfg = cfg
         self.prec = prec
         self.handle = firls_create(cfg)
@@ -646,8 +674,11 @@ class Solver:
     def profile(self, enable: bool):
         firls_profile(self.handle, enable)
 
-    def profile_read(self) -> dict:
-        return firls_profile_read(self.handle)
+    def profile_read(self, shape_id: Optional[int] = None) -> dict:
+        """Per-class kernel totals, of every launch or of one shape's."""
+        if shape_id is None:
+            return firls_profile_read(self.handle)
+        return firls_profile_read_shape(self.handle, shape_id)
 
     def outer_step(self, b, mask, lam, x, shape_id=0, stream=None):
         self._check(dict(b=b, mask=mask, x=x, shape_id=shape_id))

@@ -35,3 +35,10 @@ def shape_of(prob):
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def max_err(a, b):
+    """max |a - b| over elements, relative to max |b| (every element is held
+    to the bar, not only the norm)."""
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -2,10 +2,11 @@
 
 Each operator entry point of the C ABI (A^H, the weights d, S, P^{-1}, the
 objective) is compared element by element with the oracle on the same
-seeded inputs, at every built image size in both precisions.  FP64 must
-agree to rounding (1e-12 relative); FP32 to 1e-5 relative (the FP32
-tolerance the whole solve is held to), which bounds a few ulps of the
-FFT / Haar / difference arithmetic.
+seeded inputs, at every built image size in both precisions: in norm and at
+every element (|g - r| against max |r|).  FP64 must agree to rounding
+(1e-12 relative); FP32 to 1e-5 relative (the FP32 tolerance the whole solve
+is held to), which bounds a few ulps of the FFT / Haar / difference
+arithmetic.
 """
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ import pytest
 import synth
 from oracle import fourier
 from oracle.firls import Operators
-from tests.gpu_util import dev_complex, dev_mask, rel, shape_of, to_np, torch_cuda
+from tests.gpu_util import dev_complex, dev_mask, max_err, rel, shape_of, to_np, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +52,7 @@ def test_adjoint(n, prec):
     s.adjoint(b, m, x)
     ref = fourier.AH(p.b * p.mask, p.mask)
     assert rel(to_np(x), ref) < TOL[prec]
+    assert max_err(to_np(x), ref) < TOL[prec]
 
 
 @pytest.mark.parametrize("prec,psi,L,groups", [
@@ -85,6 +87,7 @@ def test_system(n, psi, prec):
     q = torch.empty((n, n), dtype=torch.complex64 if prec == "fp32" else torch.complex128, device="cuda")
     s.system(dev_mask(p.mask), p.lam, dev_complex(xw, prec), dev_complex(pv, prec), q)
     assert rel(to_np(q), ref) < TOL[prec]
+    assert max_err(to_np(q), ref) < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -101,6 +104,7 @@ def test_precond(n, psi, prec):
     z = torch.empty((n, n), dtype=torch.complex64 if prec == "fp32" else torch.complex128, device="cuda")
     s.precond(dev_mask(p.mask), p.lam, dev_complex(xw, prec), dev_complex(r, prec), z)
     assert rel(to_np(z), ref) < TOL[prec]
+    assert max_err(to_np(z), ref) < TOL[prec]
 
 
 @pytest.mark.parametrize("kind", ["jacobi", "none"])
@@ -120,6 +124,7 @@ def test_precond_ablation_variants(n, psi, prec, kind):
     z = torch.empty((n, n), dtype=torch.complex64 if prec == "fp32" else torch.complex128, device="cuda")
     s.precond(dev_mask(p.mask), p.lam, dev_complex(xw, prec), dev_complex(r, prec), z)
     assert rel(to_np(z), ref) < TOL[prec]
+    assert max_err(to_np(z), ref) < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

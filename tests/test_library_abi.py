@@ -96,3 +96,24 @@ def test_binding_rejects_buffers_the_kernels_would_misread():
         F.check_tensor(torch.zeros(4, dtype=torch.complex64), "x", torch.complex128, 4)
     # without shapes the marshalling alone runs (host pointers are fine there)
     assert len(F.slice_array([ok])) == 1
+
+
+def test_workspace_bytes_from_the_configuration():
+    """firls_workspace_bytes(cfg) needs no device: max_slices times the
+    largest per-slice workspace.  For a 256^2 FP32 Haar slice with 65536
+    groups: r, p, q, t (4 x 512 KiB), d and |Psi x|^2 (2 x 256 KiB), W
+    (256 KiB), the packed mask (8 KiB) and 197 x 512 FP64 partial sums."""
+    from paper_1411_5057_amd import firls as F
+    import synth
+    p = synth.make_problem(256, 0, psi="haar", levels=4, groups="quadtree", lam=0.035, sigma=0.01, frac=0.2)
+    shapes = [F.Shape(64, "tv", 0), F.Shape(256, "haar", 4, p.group_ptr, p.group_idx)]
+    cs = (F.firls_shape * 2)(*[s.c() for s in shapes])
+    cfg = F.firls_config()
+    cfg.n_shapes, cfg.shapes, cfg.max_slices, cfg.prec = 2, cs, 3, F.FIRLS_FP32
+    per = 4 * 524288 + 2 * 262144 + 4 * 65536 + 8192 + 197 * 512 * 8
+    assert len(p.group_ptr) - 1 == 65536
+    assert F.firls_workspace_bytes(cfg) == 3 * per
+    cfg.prec = F.FIRLS_FP64
+    assert F.firls_workspace_bytes(cfg) == 3 * (4 * 2 * 524288 + 2 * 524288 + 8 * 65536 + 8192 + 197 * 512 * 8)
+    cfg.max_slices = 0
+    assert F.firls_workspace_bytes(cfg) == 0
