@@ -105,6 +105,8 @@ def parse():
                          "profiler runs pin the unprofiled choice, since the profiler skews the trials")
     ap.add_argument("--launch", choices=("graphs", "direct"), default=None,
                     help="launch mode instead of the autotuner's choice (with --sub-batch)")
+    ap.add_argument("--schedule", choices=("per_shape", "across", "largest_first"), default=None,
+                    help="launches of a mixed-shape batch (with --sub-batch; default: the autotuner's choice)")
     ap.add_argument("--no-pair", action="store_true",
                     help="run the PCG row-inverse pass and the step as two launches (A/B of the paired pass)")
     ap.add_argument("--workload", choices=("mri", "dense", "tv512", "fp64_64", "uneven"), default="mri",
@@ -133,7 +135,7 @@ WORKLOAD_DEFAULTS = {
     # piecewise-constant images with eps = 1e-10, so the gap is reported
     "tv512": dict(seed0=0, slices=32, pcg=10, max_outer=30, tau=0.0, prec="fp32"),
     "fp64_64": dict(seed0=0, slices=1024, pcg=20, max_outer=30, tau=0.0, prec="fp64"),
-    "uneven": dict(seed0=0, slices=64, pcg=4, max_outer=50, tau=8e-6, prec="fp32"),
+    "uneven": dict(seed0=0, slices=64, pcg=4, max_outer=100, tau=8e-6, prec="fp32"),
 }
 
 
@@ -402,6 +404,9 @@ def run_workload(a, torch, F):
     if a.sub_batch >= 0:
         solver.set_chunk(a.sub_batch)
         solver.set_graphs(a.launch != "direct")
+        if a.schedule:
+            solver.set_schedule({"per_shape": F.FIRLS_SCHED_PER_SHAPE, "across": F.FIRLS_SCHED_ACROSS,
+                                 "largest_first": F.FIRLS_SCHED_ACROSS_LARGEST_FIRST}[a.schedule])
         chunk = a.sub_batch
     else:
         chunk = solver.autotune(items) if not a.no_tune else 0
@@ -423,6 +428,7 @@ def run_workload(a, torch, F):
                                   f"{a.tau:g} (max {a.max_outer})", "slices": B, "pcg_iters": K, "tau": a.tau,
                       "max_outer": a.max_outer, "prec": prec, "sub_batch": chunk,
                       "launch": "graphs" if solver.graphs else "direct",
+                      "schedule": ["per_shape", "across", "largest_first"][solver.schedule],
                       "shapes": [f"{n}x{n} {psi}" for (n, psi, _) in keys]},
            "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
            "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
@@ -433,7 +439,8 @@ def run_workload(a, torch, F):
         tot_bytes, cls_bytes = 0.0, {}
         for i, (n, psi, _) in enumerate(keys):
             ps = per_shape[i]
-            pr = paired and 0 < ps.get("rowinv", {}).get("launches", 0) < ps.get("col", {}).get("launches", 0)
+            # the paired PCG pass runs for FP32 Haar up to 256 x 256
+            pr = paired and psi == "haar" and n <= 256
             for c, v in ps.items():
                 bb = psi_bytes_per_px(c, "haar" if psi == "haar" else "tv", K, prec, pr) * n * n * v["slice_launches"]
                 tot_bytes += bb

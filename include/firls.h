@@ -356,6 +356,21 @@ int firls_set_paired(firls_handle* h, int32_t enable);
  * For tests only; off by default. */
 int firls_test_sync_timeout(firls_handle* h, int32_t enable);
 
+/* How a batch of several shapes is launched.  PER_SHAPE: every kernel of an
+ * outer iteration once per shape.  ACROSS, ACROSS_LARGEST_FIRST: the k-th
+ * launch of every shape's sequence becomes one launch per kernel class and
+ * mode covering all shapes (a work table gives each workgroup its slice,
+ * block and parameters), with the shapes' workgroups in shape order or
+ * largest images first.  Batches
+ * of one shape, streamed batches, dense sensing matrices and the
+ * allocation-free solve always launch per shape.  firls_autotune chooses it
+ * together with the sub-batch size and launch mode.  Each shape's kernels
+ * are the same code either way; results agree to rounding (the compiler
+ * may fuse multiply-adds differently in the two kernels). */
+enum { FIRLS_SCHED_PER_SHAPE = 0, FIRLS_SCHED_ACROSS = 1, FIRLS_SCHED_ACROSS_LARGEST_FIRST = 2 };
+int firls_set_schedule(firls_handle* h, int32_t schedule);
+int firls_get_schedule(const firls_handle* h);
+
 /* Test hooks: conditions forced from the host so the error paths run with
  * every kernel still exiting normally.  flags is a bit set (0 clears all):
  *   FIRLS_TEST_SYNC_TIMEOUT  as firls_test_sync_timeout;
@@ -379,10 +394,12 @@ int firls_set_chunk(firls_handle* h, int32_t chunk);
 
 /* Time a few outer iterations of these slices for candidate sub-batch sizes
  * (whole batch, 256, 128, 64, 32), each with graph replay and with direct
- * launches, and keep the fastest pair: the sub-batch size is written to
+ * launches and, for a batch of several masked-FFT shapes, each schedule
+ * (FIRLS_SCHED_*), and keep the fastest: the sub-batch size is written to
  * *chosen and the launch mode (1 graphs, 0 direct) to *graphs (either may
- * be NULL), and both stay set on the handle as firls_set_chunk and
- * firls_set_graphs would set them.  Every x is restored afterwards; on an
+ * be NULL), and all three stay set on the handle as firls_set_chunk,
+ * firls_set_graphs and firls_set_schedule would set them
+ * (firls_get_schedule reads the schedule).  Every x is restored afterwards; on an
  * error the handle keeps its earlier settings.  With the environment
  * variable FIRLS_TUNE_CACHE naming a file, a previous choice for the same
  * shape mix and batch size is reused, and new choices are appended. */

@@ -167,8 +167,10 @@ struct firls_handle {
     void* ws = nullptr;
     void* desc = nullptr;
     hipStream_t stream = nullptr;
+    int multi = 0;   // schedule of launches across shapes (0: per shape)
     bool operator==(const GraphKey& o) const {
-      return counts == o.counts && Tmax == o.Tmax && tau == o.tau && ws == o.ws && desc == o.desc && stream == o.stream;
+      return counts == o.counts && Tmax == o.Tmax && tau == o.tau && ws == o.ws && desc == o.desc &&
+             stream == o.stream && multi == o.multi;
     }
   } gkey;
   hipGraphExec_t g_iter = nullptr;
@@ -176,6 +178,23 @@ struct firls_handle {
   int chunk = 0;
   // set while firls_solve_batched_noalloc runs: buffers must already fit
   bool noalloc = false;
+  // how a batch of several shapes is launched: FIRLS_SCHED_PER_SHAPE, or
+  // one launch per kernel class and position across shapes
+  // (FIRLS_SCHED_ACROSS in batch order, FIRLS_SCHED_ACROSS_LARGEST_FIRST)
+  int schedule = FIRLS_SCHED_PER_SHAPE;
+  // while set, launch_prep / launch_pcg record their launches here
+  struct LaunchRec {
+    Launcher fn;
+    Params P;
+    dim3 grid;
+    int cls;
+  };
+  std::vector<LaunchRec>* rec_seq = nullptr;
+  // device work tables of the launches across shapes
+  Params* d_mparams = nullptr;
+  size_t mparams_cap = 0;
+  MultiItem* d_mitems = nullptr;
+  size_t mitems_cap = 0;
   void* scratch = nullptr;   // this device's g_noalloc_scratch (null if the lookup failed)
   std::string scratch_err;
 
@@ -230,6 +249,11 @@ void drop_graphs(firls_handle* h) {
 
 void free_batch(firls_handle* h) {
   drop_graphs(h);
+  if (h->d_mparams) (void)hipFree(h->d_mparams);
+  if (h->d_mitems) (void)hipFree(h->d_mitems);
+  h->d_mparams = nullptr;
+  h->d_mitems = nullptr;
+  h->mparams_cap = h->mitems_cap = 0;
   if (h->ws_learn) (void)hipFree(h->ws_learn);
   h->ws_learn = nullptr;
   h->ws_learn_cap = 0;
@@ -427,6 +451,10 @@ struct TimingScope {   // launch_timing() set for one launcher call
 // ``cls`` is a FIRLS_PROF_* class.
 #define KLAUNCH(h, cls, fn, P, grid, st)                                                \
   do {                                                                                  \
+    if ((h)->rec_seq) {                                                                 \
+      (h)->rec_seq->push_back({(fn), (P), (grid), (cls)});                              \
+      break;                                                                            \
+    }                                                                                   \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                              \
     if ((h)->profiling) {                                                               \
       a_ = prof_event(h);                                                               \
@@ -638,18 +666,21 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
 int prof_collect(firls_handle* h, const std::vector<std::vector<int>>& act_pcg,
                  const std::vector<std::vector<int>>& act_prep) {
   for (const auto& r : h->recs) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    float ms = 0.f;   // records without events: the other shapes of a launch across shapes
+    if (r.a && r.b) HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
     int units = r.count;
     if (r.phase == 1 && r.it > 0) units = act_prep[r.it][r.group];
     if (r.phase == 2) units = act_pcg[r.it][r.group];
+    // a launch across shapes has one record per shape; the first carries
+    // its time and counts the launch
+    const int launches = r.a ? 1 : 0;
     h->prof_ms[r.cls] += ms;
-    h->prof_launches[r.cls] += 1;
+    h->prof_launches[r.cls] += launches;
     h->prof_units[r.cls] += units;
     const size_t k = (size_t)r.group * FIRLS_PROF_CLASSES + r.cls;
     if (r.group >= 0 && k < h->prof_ms_shape.size()) {
       h->prof_ms_shape[k] += ms;
-      h->prof_launches_shape[k] += 1;
+      h->prof_launches_shape[k] += launches;
       h->prof_units_shape[k] += units;
     }
   }
@@ -663,6 +694,174 @@ int check_slice(const firls_handle* h, const firls_slice& sl) {
   if (!(sl.lambda > 0.0) || !std::isfinite(sl.lambda)) return fail(FIRLS_E_INVALID, "lambda must be positive and finite");
   if (!sl.b || !sl.x) return fail(FIRLS_E_INVALID, "b and x must be device pointers");
   if (!sl.mask && !h->shapes[sl.shape_id].dense) return fail(FIRLS_E_INVALID, "mask must be a device pointer");
+  return FIRLS_OK;
+}
+
+// ---- launches across shapes ------------------------------------------------
+// A batch of several shapes runs each position of its outer iteration (the
+// k-th launch of the weights and residual passes, the k-th launch of the
+// PCG iterations) as one launch per kernel class and mode covering every
+// shape: the per-shape launch sequences are recorded, then merged position
+// by position.  Within a shape the order is unchanged, and shapes never
+// depend on each other, so only the launch count changes (a batch of ten
+// shapes needs about a tenth of the launches).
+
+// Which kernel class and mode a recorded per-shape launcher is.
+bool multi_class_of(const firls_handle* h, const Shape& S, Launcher fn, int& cls, int& mode) {
+  const SizeKernels* sk = S.sk;
+  const PrecKernels* pk = prec_kernels(h->fp64);
+  auto hit = [&](Launcher cand, int c, int m) {
+    if (!cand || cand != fn) return false;
+    cls = c;
+    mode = m;
+    return true;
+  };
+  for (int m = 0; m < 7; ++m)
+    if (hit(sk->rowfwd[m], MC_ROWFWD, m)) return true;
+  for (int m = 0; m < 5; ++m)
+    if (hit(sk->col[m], MC_COL, m) || hit(sk->rowinv[m], MC_ROWINV, m)) return true;
+  return hit(sk->pcg_pair, MC_PAIR, 0) || hit(sk->psi_sq_haar, MC_PSI_SQ_HAAR, 0) ||
+         hit(sk->update_haar, MC_UPDATE_HAAR, 0) || hit(sk->last_x, MC_LAST_X, 0) ||
+         hit(pk->psi_sq_tv, MC_PSI_SQ_TV, 0) || hit(pk->group_w, MC_GROUP_W, 0) || hit(pk->group_d, MC_GROUP_D, 0) ||
+         hit(pk->update_tv[UP_INIT], MC_UPDATE_TV, UP_INIT) || hit(pk->update_tv[UP_STEP], MC_UPDATE_TV, UP_STEP) ||
+         hit(pk->outer_check, MC_OUTER_CHECK, 0);
+}
+
+struct MultiLaunch {
+  int cls, mode, prof_cls;
+  int item0, items;
+  size_t lds;
+  std::vector<std::pair<int, int>> groups;   // (shape, slices) it covers
+};
+struct MultiPlan {
+  std::vector<MultiLaunch> prep, pcg;
+};
+
+// Records the per-shape sequences of one outer iteration, merges them
+// position by position and uploads the Params table and the work items.
+// Returns 1 (plan built), 0 (some launch has no cross-shape kernel: the
+// caller launches per shape) or an error.
+int build_multi_plan(firls_handle* h, hipStream_t st, const std::vector<std::vector<int>>& by_shape,
+                     const std::vector<int>& lo, int Tmax, double tau, MultiPlan& plan) {
+  const int nsh = (int)h->shapes.size();
+  std::vector<std::vector<firls_handle::LaunchRec>> seq[2];
+  seq[0].resize(nsh);
+  seq[1].resize(nsh);
+  for (int sh = 0; sh < nsh; ++sh) {
+    const int c = (int)by_shape[sh].size();
+    if (!c) continue;
+    const Shape& S = h->shapes[sh];
+    Params P = base_params(h, S, sh, h->d_list + lo[sh]);
+    P.Tmax = Tmax;
+    P.tau = tau;
+    P.stop_flags = h->d_flags;
+    h->rec_seq = &seq[0][sh];
+    int rc = launch_prep(h, S, P, c, st);
+    if (!rc) {
+      h->rec_seq = &seq[1][sh];
+      rc = launch_pcg(h, S, base_params(h, S, sh, h->d_list + lo[sh]), c, st);
+    }
+    h->rec_seq = nullptr;
+    if (rc) return rc;
+  }
+  // the order of the shapes' items within every launch
+  std::vector<int> order;
+  for (int sh = 0; sh < nsh; ++sh)
+    if (!by_shape[sh].empty()) order.push_back(sh);
+  if (h->schedule == FIRLS_SCHED_ACROSS_LARGEST_FIRST)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return h->shapes[a].pixels() > h->shapes[b].pixels(); });
+  const MultiKernels* mk = multi_kernels(h->fp64);
+  std::vector<Params> params;
+  std::vector<MultiItem> items;
+  for (int ph = 0; ph < 2; ++ph) {
+    std::vector<MultiLaunch>& out = ph == 0 ? plan.prep : plan.pcg;
+    out.clear();
+    size_t len = 0;
+    for (int sh : order) len = std::max(len, seq[ph][sh].size());
+    for (size_t pos = 0; pos < len; ++pos) {
+      std::vector<MultiLaunch> bucket;
+      std::vector<std::vector<MultiItem>> bucket_items;
+      for (int sh : order) {
+        if (pos >= seq[ph][sh].size()) continue;
+        const firls_handle::LaunchRec& r = seq[ph][sh][pos];
+        int cls = 0, mode = 0;
+        if (!multi_class_of(h, h->shapes[sh], r.fn, cls, mode) || !mk->fn[cls][mode]) return 0;
+        size_t b = 0;
+        while (b < bucket.size() && !(bucket[b].cls == cls && bucket[b].mode == mode)) ++b;
+        if (b == bucket.size()) {
+          bucket.push_back(MultiLaunch{cls, mode, r.cls, 0, 0, 0, {}});
+          bucket_items.emplace_back();
+        }
+        const int pidx = (int)params.size();
+        params.push_back(r.P);
+        const int32_t* list = h->h_list + lo[sh];
+        std::vector<MultiItem>& mine = bucket_items[b];
+        if (cls == MC_OUTER_CHECK) {   // one workgroup per slice, indexed by x
+          for (unsigned x = 0; x < r.grid.x; ++x) mine.push_back(MultiItem{list[x], 0, pidx});
+        } else {                       // grid (blocks of a slice, slices)
+          for (unsigned y = 0; y < r.grid.y; ++y)
+            for (unsigned x = 0; x < r.grid.x; ++x) mine.push_back(MultiItem{list[y], (int32_t)x, pidx});
+        }
+        bucket[b].groups.push_back({sh, (int)by_shape[sh].size()});
+        bucket[b].lds = std::max(bucket[b].lds, multi_lds_bytes(h->fp64, cls, h->shapes[sh].n));
+      }
+      for (size_t b = 0; b < bucket.size(); ++b) {
+        bucket[b].item0 = (int)items.size();
+        bucket[b].items = (int)bucket_items[b].size();
+        items.insert(items.end(), bucket_items[b].begin(), bucket_items[b].end());
+        out.push_back(bucket[b]);
+      }
+    }
+  }
+  // device copies (grown as needed; a graph captured on the old ones is dropped)
+  auto grow = [&](void** ptr, size_t& cap, size_t bytes) -> int {
+    if (bytes <= cap) return FIRLS_OK;
+    drop_graphs(h);
+    HIPCHK(hipStreamSynchronize(st));
+    if (*ptr) HIPCHK(hipFree(*ptr));
+    *ptr = nullptr;
+    cap = 0;
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FIRLS_E_NOMEM, "work table allocation failed");
+    }
+    cap = bytes;
+    return FIRLS_OK;
+  };
+  int rc = grow(reinterpret_cast<void**>(&h->d_mparams), h->mparams_cap, params.size() * sizeof(Params));
+  if (!rc) rc = grow(reinterpret_cast<void**>(&h->d_mitems), h->mitems_cap, items.size() * sizeof(MultiItem));
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(h->d_mparams, params.data(), params.size() * sizeof(Params), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->d_mitems, items.data(), items.size() * sizeof(MultiItem), hipMemcpyHostToDevice, st));
+  // the copies come from host vectors that end here
+  HIPCHK(hipStreamSynchronize(st));
+  return 1;
+}
+
+// One merged launch list (timed per launch like KLAUNCH; the time goes to
+// the first shape it covers, the others get their slice counts).
+int launch_multi_list(firls_handle* h, const std::vector<MultiLaunch>& L, hipStream_t st) {
+  const MultiKernels* mk = multi_kernels(h->fp64);
+  for (const MultiLaunch& m : L) {
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    if (h->profiling) {
+      a_ = prof_event(h);
+      b_ = prof_event(h);
+      if (!a_ || !b_) a_ = b_ = nullptr;
+    }
+    const MultiArgs A{h->d_mparams, h->d_mitems + m.item0};
+    {
+      TimingScope ts_(a_, b_);
+      const hipError_t e = mk->fn[m.cls][m.mode](A, m.items, m.lds, st);
+      if (e != hipSuccess) return fail(FIRLS_E_HIP, std::string("launch across shapes: ") + hipGetErrorString(e));
+    }
+    if (a_ && b_) {
+      for (size_t g = 0; g < m.groups.size(); ++g)
+        h->recs.push_back({m.prof_cls, m.groups[g].first, h->ctx_it, h->ctx_phase, m.groups[g].second,
+                           g == 0 ? a_ : nullptr, g == 0 ? b_ : nullptr});
+    }
+  }
   return FIRLS_OK;
 }
 
@@ -783,7 +982,27 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
   }
   for (int s = 0; s < nsh; ++s)
     if (!zf_by_shape[s].empty() && (rc = launch_ahb(s, h->d_list + zlo[s], (int)zf_by_shape[s].size()))) return rc;
+  // several masked-FFT shapes at once: one launch per class and position
+  // across the shapes (the schedule chosen by firls_set_schedule or the
+  // autotuner)
+  MultiPlan mplan;
+  bool multi = false;
+  {
+    int present = 0;
+    bool dense = false;
+    for (int s = 0; s < nsh; ++s)
+      if (!by_shape[s].empty()) {
+        ++present;
+        dense = dense || h->shapes[s].dense;
+      }
+    if (h->schedule != FIRLS_SCHED_PER_SHAPE && present >= 2 && !dense && !streamed && !h->noalloc) {
+      rc = build_multi_plan(h, st, by_shape, lo, Tmax, tau, mplan);
+      if (rc < 0) return rc;
+      multi = rc == 1;
+    }
+  }
   auto enqueue_prep = [&]() -> int {
+    if (multi) return launch_multi_list(h, mplan.prep, st);
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
@@ -800,6 +1019,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     return FIRLS_OK;
   };
   auto enqueue_pcg = [&]() -> int {
+    if (multi) return launch_multi_list(h, mplan.pcg, st);
     for (int s = 0; s < nsh; ++s) {
       const int c = (int)by_shape[s].size();
       if (!c) continue;
@@ -823,6 +1043,7 @@ int run_chunk(firls_handle* h, hipStream_t st, int slots, int ns, const firls_sl
     key.ws = h->ws;
     key.desc = h->d_desc;
     key.stream = st;
+    key.multi = multi ? h->schedule : 0;
     if (!(key == h->gkey) || !h->g_iter) {
       drop_graphs(h);
       hipGraph_t g = nullptr;
@@ -1453,6 +1674,9 @@ int firls_solve_batched_noalloc(firls_handle* h, void* stream, int32_t n_slices,
 int firls_profile(firls_handle* h, int32_t enable) {
   if (!h) return fail(FIRLS_E_INVALID, "null handle");
   h->profiling = enable != 0;
+  h->recs.clear();
+  h->ev_used = 0;
+  if (!enable) return FIRLS_OK;   // the totals stay readable until the next enable
   for (int c = 0; c < FIRLS_PROF_CLASSES; ++c) {
     h->prof_ms[c] = 0.0;
     h->prof_launches[c] = 0;
@@ -1462,8 +1686,6 @@ int firls_profile(firls_handle* h, int32_t enable) {
   h->prof_ms_shape.assign(ks, 0.0);
   h->prof_launches_shape.assign(ks, 0);
   h->prof_units_shape.assign(ks, 0);
-  h->recs.clear();
-  h->ev_used = 0;
   return FIRLS_OK;
 }
 
@@ -1839,6 +2061,16 @@ int firls_test_hooks(firls_handle* h, int32_t flags) {
   return FIRLS_OK;
 }
 
+int firls_set_schedule(firls_handle* h, int32_t schedule) {
+  if (!h || schedule < FIRLS_SCHED_PER_SHAPE || schedule > FIRLS_SCHED_ACROSS_LARGEST_FIRST)
+    return fail(FIRLS_E_INVALID, "bad argument");
+  h->schedule = schedule;
+  drop_graphs(h);
+  return FIRLS_OK;
+}
+
+int firls_get_schedule(const firls_handle* h) { return h ? h->schedule : FIRLS_E_INVALID; }
+
 int firls_set_chunk(firls_handle* h, int32_t chunk) {
   if (!h || chunk < 0) return fail(FIRLS_E_INVALID, "bad argument");
   h->chunk = chunk;
@@ -1870,11 +2102,15 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     std::ifstream in(cache);
     std::string line;
     while (std::getline(in, line)) {
-      const size_t bar = line.rfind('|');
-      const size_t bar2 = bar == std::string::npos ? bar : line.rfind('|', bar - 1);
-      if (bar2 != std::string::npos && line.substr(0, bar2) == key) {
-        h->chunk = std::atoi(line.c_str() + bar2 + 1);
-        h->use_graphs = std::atoi(line.c_str() + bar + 1) != 0;
+      // key|chunk|graphs|schedule
+      const size_t b3 = line.rfind('|');
+      const size_t b2 = b3 == std::string::npos || b3 == 0 ? std::string::npos : line.rfind('|', b3 - 1);
+      const size_t b1 = b2 == std::string::npos || b2 == 0 ? std::string::npos : line.rfind('|', b2 - 1);
+      if (b1 != std::string::npos && line.substr(0, b1) == key) {
+        h->chunk = std::atoi(line.c_str() + b1 + 1);
+        h->use_graphs = std::atoi(line.c_str() + b2 + 1) != 0;
+        h->schedule = std::atoi(line.c_str() + b3 + 1);
+        drop_graphs(h);
         if (chosen) *chosen = h->chunk;
         if (graphs) *graphs = h->use_graphs ? 1 : 0;
         return FIRLS_OK;
@@ -1907,24 +2143,42 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     return FIRLS_OK;
   };
   int rc = copy_all(true);
+  // schedules of batches that mix masked-FFT shapes
+  std::vector<int> scheds = {FIRLS_SCHED_PER_SHAPE};
+  {
+    std::vector<int> seen(h->shapes.size(), 0);
+    int present = 0;
+    bool dense = false;
+    for (int i = 0; i < n_slices; ++i) {
+      present += seen[slices[i].shape_id]++ == 0;
+      dense = dense || h->shapes[slices[i].shape_id].dense;
+    }
+    if (present >= 2 && !dense) scheds = {FIRLS_SCHED_PER_SHAPE, FIRLS_SCHED_ACROSS, FIRLS_SCHED_ACROSS_LARGEST_FIRST};
+  }
   std::vector<int> cands = {0};
   for (int c : {256, 128, 64, 32})
     if (c < n_slices) cands.push_back(c);
   std::vector<firls_report> rep(n_slices);
   const int T = std::max(1, std::min(3, h->cfg.max_outer));
   double best = 1e300;
-  int best_c = 0;
+  int best_c = 0, best_s = FIRLS_SCHED_PER_SHAPE;
   bool best_g = true;
-  const int chunk0 = h->chunk;
+  const int chunk0 = h->chunk, sched0 = h->schedule;
   const bool graphs0 = h->use_graphs;
   const bool prof = h->profiling;
   h->profiling = false;
-  for (int trial = 0; trial < 2 * (int)cands.size(); ++trial) {
+  const int per_c = 2 * (int)scheds.size();
+  for (int trial = 0; trial < per_c * (int)cands.size(); ++trial) {
     if (rc) break;
-    const int c = cands[trial / 2];
+    const int c = cands[trial / per_c];
     const bool g = trial % 2 == 0;
+    const int sc = scheds[(trial % per_c) / 2];
     h->chunk = c;
     h->use_graphs = g;
+    if (h->schedule != sc) {
+      h->schedule = sc;
+      drop_graphs(h);
+    }
     double t = 0.0;
     for (int rep_i = 0; rep_i < 2 && !rc; ++rep_i) {
       if ((rc = copy_all(false))) break;
@@ -1939,6 +2193,7 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
       best = t;
       best_c = c;
       best_g = g;
+      best_s = sc;
     }
   }
   h->profiling = prof;
@@ -1950,15 +2205,21 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
   if (rc) {
     h->chunk = chunk0;
     h->use_graphs = graphs0;
+    h->schedule = sched0;
+    drop_graphs(h);
     return rc;
   }
   h->chunk = best_c;
   h->use_graphs = best_g;
+  if (h->schedule != best_s) {
+    h->schedule = best_s;
+    drop_graphs(h);
+  }
   if (chosen) *chosen = best_c;
   if (graphs) *graphs = best_g ? 1 : 0;
   if (cache) {
     std::ofstream out(cache, std::ios::app);
-    out << key << "|" << best_c << "|" << (best_g ? 1 : 0) << "\n";
+    out << key << "|" << best_c << "|" << (best_g ? 1 : 0) << "|" << best_s << "\n";
   }
   return FIRLS_OK;
 }

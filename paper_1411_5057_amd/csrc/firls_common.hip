@@ -144,7 +144,6 @@ PrecKernels make_prec() {
   return k;
 }
 
-#define FIRLS_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 #define FIRLS_DECL(N) SizeKernels make_size_f32_##N(); SizeKernels make_size_f64_##N();
 FIRLS_SIZES(FIRLS_DECL)
 #undef FIRLS_DECL

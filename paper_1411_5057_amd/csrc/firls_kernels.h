@@ -59,8 +59,17 @@ __device__ __forceinline__ size_t t_index(int row, int col) {
   return (size_t)ch * N * N + (size_t)(col / TS) * (N * TS) + (size_t)lr * TS + (col % TS);
 }
 
-#define FIRLS_SLICE_PROLOGUE(idx)                 \
-  const int s_ = P.list[idx];                    \
+// The workgroup's place: slice (index into the desc and state arrays) and
+// its block within the slice (row band, column strip or tile).  A kernel
+// launched per shape takes them from its grid and the slice list; a launch
+// across shapes reads them from its work table.
+struct Blk {
+  int x;   // block within the slice
+  int s;   // slice
+};
+
+#define FIRLS_SLICE_PROLOGUE_S(sidx)              \
+  const int s_ = (sidx);                         \
   if (!P.state[s_].active) return;               \
   const SliceDesc& D = P.desc[s_];
 
@@ -129,10 +138,10 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
 // next outer check, and the step is taken as zero.  A zero residual (both
 // zero) is the ordinary end of the iteration: a zero step.  The test hook
 // TEST_BREAKDOWN turns <p, S p> negative.
-__device__ __forceinline__ double pcg_alpha(const Params& P, int s, double rz, double pq) {
+__device__ __forceinline__ double pcg_alpha(const Params& P, Blk B, double rz, double pq) {
   if (P.test_flags & TEST_BREAKDOWN) pq = -fabs(pq);
   if (pq > 0.0) return rz / pq;
-  if (rz > 0.0 && blockIdx.x == 0 && threadIdx.x == 0 && P.state[s].status >= 0) P.state[s].status = ST_E_BREAKDOWN;
+  if (rz > 0.0 && B.x == 0 && threadIdx.x == 0 && P.state[B.s].status >= 0) P.state[B.s].status = ST_E_BREAKDOWN;
   return 0.0;
 }
 
@@ -261,7 +270,7 @@ __device__ __forceinline__ void band_d(const uint16_t* tell, const T* WL, T* d) 
 }
 
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
+__device__ __forceinline__ void rowfwd_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
@@ -269,11 +278,11 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[2 * NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const size_t off = (size_t)B.x * ROWS * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
   C* t = static_cast<C*>(D.t);
-  const int row0 = blockIdx.x * ROWS;
+  const int row0 = B.x * ROWS;
   auto gdst = [&](int l, int q, C v) { t[t_index<T, N>(row0 + l, q)] = v; };
   if constexpr (MODE == RF_PLAIN) {
     const C* x = static_cast<const C*>(D.x) + off;
@@ -295,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     if (pend) {
       const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
       const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-      al = (T)pcg_alpha(P, s_, rz, pq);
+      al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
     }
     const C* p = static_cast<const C*>(D.p) + off;
     T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
@@ -325,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       for (int s = 0; s < 16; ++s) sqL[(row + s) * N + col] = (T)cabs2(v[s]);
     }
     __syncthreads();
-    const int g0 = P.shape.bgptr[blockIdx.x], g1 = P.shape.bgptr[blockIdx.x + 1];
+    const int g0 = P.shape.bgptr[B.x], g1 = P.shape.bgptr[B.x + 1];
     const ShapeDev& G = P.shape;
     double ae = 0.0, a0 = 0.0;
     T* d = static_cast<T*>(D.d) + off;
@@ -376,8 +385,8 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     }
     block_sum2(ae, a0, red);       // also orders the LDS reads above before the FFT
     if (threadIdx.x == 0) {
-      slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
-      slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
+      slot_wptr(D, SLOT_REG_EPS)[B.x] = ae;
+      slot_wptr(D, SLOT_REG0)[B.x] = a0;
     }
     if constexpr (!PEN) {
 #pragma unroll
@@ -427,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
       const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz);
       const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq);
       const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz);
-      const double ald = pcg_alpha(P, s_, rzo, pqo);
+      const double ald = pcg_alpha(P, Blk{B.x, s_}, rzo, pqo);
       const double rzn = ald * ald * qqo - rzo;
       const T al = (T)ald;
       const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -477,7 +486,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
         }
       }
       const double tot = block_sum(acc, red);
-      if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k)[blockIdx.x] = tot;
+      if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k)[B.x] = tot;
     } else if constexpr (MODE == RF_PCG_HAAR) {
       // z = P^{-1} r in registers (precond_tile), p = z + beta p
       const C* r = static_cast<const C*>(D.r[0]) + off;
@@ -516,19 +525,24 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
     }
   }
 }
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
+  rowfwd_body<T, N, MODE>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_col(Params P) {
+__device__ __forceinline__ void col_body(const Params& P, const Blk B) {
   constexpr int COLS = Geo<T>::COLS;
   using C = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  FIRLS_SLICE_PROLOGUE_S(B.s)
   // workgroup = (contrast ch, strip): strips of all contrasts in turn
   constexpr int STRIPS = N / COLS;
-  const int ch = blockIdx.x / STRIPS, strip = blockIdx.x - ch * STRIPS;
+  const int ch = B.x / STRIPS, strip = B.x - ch * STRIPS;
   const int col0 = strip * COLS;
   const C* tw = lds_twiddles<T, N, COLS>(lds, P.tw);
   C* t = static_cast<C*>(D.t) + (size_t)ch * N * N + (size_t)strip * N * COLS;   // this strip's block
@@ -574,7 +588,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
       return u;
     }, gdst);
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[P.C * (N / band_rows(N)) + blockIdx.x] = tot;
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[P.C * (N / band_rows(N)) + B.x] = tot;
   } else if constexpr (MODE == COL_R0) {
     // k = (F x) at the sampled entries; keep m (b - k) / n for the inverse
     // and accumulate 1/2 ||m F x - b||^2.
@@ -591,7 +605,7 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
       return u;
     }, gdst);
     const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) slot_wptr(D, SLOT_DATA)[blockIdx.x] = 0.5 * tot;
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_DATA)[B.x] = 0.5 * tot;
   } else if constexpr (MODE == COL_DC) {
     // data consistency: keep F x where unsampled, put b where sampled
     // (k = m b + (1 - m) F x), then the column inverse with 1/n
@@ -608,10 +622,15 @@ __global__ __launch_bounds__(NT) void k_col(Params P) {
     }, gdst);
   }
 }
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_col(Params P) {
+  col_body<T, N, MODE>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(NT) void k_rowinv(Params P) {
+__device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
@@ -619,8 +638,8 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const int row0 = blockIdx.x * ROWS;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const int row0 = B.x * ROWS;
   const size_t off = (size_t)row0 * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
   const C* tin = static_cast<const C*>(D.t);
@@ -641,7 +660,7 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
     // the objective and stop test of this outer iteration (every partial it
     // needs is complete before this pass): the slice's first workgroup runs
     // it; a stopped slice's workgroups that start later just exit
-    if (!SP && P.check_r0 && blockIdx.x == 0) outer_check_wg(P, s_);
+    if (!SP && P.check_r0 && B.x == 0) outer_check_wg(P, s_);
     if constexpr (HAAR) {
       // A^H A part into LDS (row inverse FFT, or with a dense sensing matrix
       // the product A^T A v in t, row-major), then lambda Phi^T (d * Phi v)
@@ -707,7 +726,7 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
       }
       if (!(SP && P.q_dead)) {
         const double t2 = block_sum(acc2, red);
-        if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[blockIdx.x] = t2;
+        if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[B.x] = t2;
       }
       if (!SP && P.p0_prep) {
         __syncthreads();
@@ -737,10 +756,15 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
     }
     if constexpr (SP) {
       const double tot = block_sum(acc, red);
-      if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[blockIdx.x] = tot;
+      if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + P.k)[B.x] = tot;
     }
   }
 }
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(NT) void k_rowinv(Params P) {
+  rowinv_body<T, N, MODE>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // ---------------------------------------------------------------------------
 // The row-inverse pass of PCG iteration k - 1 and the fused step of
@@ -769,7 +793,7 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 // are recomputed there rather than kept live from phase A, which would
 // not fit the 128 registers of that occupancy and spill.
 template <typename T, int N>
-__global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
+__device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
@@ -779,8 +803,8 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
   __shared__ int timed_out;
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const int row0 = blockIdx.x * ROWS;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const int row0 = B.x * ROWS;
   const size_t off = (size_t)row0 * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
   const int k = P.k;
@@ -825,10 +849,10 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     // cache write-back or invalidation
     const double t2 = block_sum(acc2, red);
     if (threadIdx.x == 0)
-      __hip_atomic_store(slot_wptr(D, SLOT_QQ0 + k - 1) + blockIdx.x, t2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot_wptr(D, SLOT_QQ0 + k - 1) + B.x, t2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0)
-      __hip_atomic_store(slot_wptr(D, SLOT_PQ0 + k - 1) + blockIdx.x, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot_wptr(D, SLOT_PQ0 + k - 1) + B.x, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // barrier among the slice's workgroups: the partial stores complete, the
   // arrival is counted, then the wait for the rest
@@ -837,7 +861,8 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     // (the test hook asks for one arrival more than can come and gives up
     // after a few polls, so the time-out path runs without a long wait)
     const bool hook = (P.test_flags & TEST_SYNC_TIMEOUT) != 0;
-    const uint32_t target = gridDim.x * (uint32_t)P.state[s_].outer + (hook ? 1u : 0u);
+    const uint32_t bands = (uint32_t)(P.C * (N / ROWS));   // the slice's workgroups
+    const uint32_t target = bands * (uint32_t)P.state[s_].outer + (hook ? 1u : 0u);
     const uint32_t limit = hook ? 64u : (1u << 20);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
@@ -858,7 +883,7 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
   const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + k - 1), P.nrz);
   const double pqo = slot_sum_coherent(slot_ptr(D, SLOT_PQ0 + k - 1), P.npq);
   const double qqo = slot_sum_coherent(slot_ptr(D, SLOT_QQ0 + k - 1), P.nrz);
-  const double ald = pcg_alpha(P, s_, rzo, pqo);
+  const double ald = pcg_alpha(P, Blk{B.x, s_}, rzo, pqo);
   const double rzn = ald * ald * qqo - rzo;
   const T al = (T)ald;
   const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -905,23 +930,28 @@ __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
     }
   }
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + k)[blockIdx.x] = tot;
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + k)[B.x] = tot;
   C* t = static_cast<C*>(D.t);
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
                                        [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; }, tid);
 }
+template <typename T, int N>
+__global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
+  pcg_pair_body<T, N>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // ---------------------------------------------------------------------------
 // |Phi x|^2 per coefficient (Haar, in-place coefficient layout).
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
+__device__ __forceinline__ void psi_sq_haar_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using U = Units<N, ROWS>;
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const size_t off = (size_t)B.x * ROWS * N;
   const C* x = static_cast<const C*>(D.x) + off;
   T* sq = static_cast<T*>(D.sq) + off;
 #pragma unroll
@@ -936,6 +966,11 @@ __global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
     for (int s = 0; s < 16; ++s) sq[(row + s) * N + col] = (T)cabs2(v[s]);
   }
 }
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
+  psi_sq_haar_body<T, N>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // Haar PCG update in the textbook order, for the Jacobi and identity
 // preconditioners (whose slower inner convergence makes the beta
@@ -943,16 +978,16 @@ __global__ __launch_bounds__(NT) void k_psi_sq_haar(Params P) {
 // alpha = <r,z>/<p,q>, x += alpha p, r -= alpha q, and the partials of the
 // new <r, P^{-1} r>.  The next k_rowfwd (mode 1) forms z, beta and p.
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_update_haar(Params P) {
+__device__ __forceinline__ void update_haar_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   using U = Units<N, ROWS>;
   __shared__ double red[NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)pcg_alpha(P, s_, rz, pq);
+  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   C* r = static_cast<C*>(D.r[0]) + off;
   const C* p = static_cast<const C*>(D.p) + off;
@@ -988,19 +1023,24 @@ __global__ __launch_bounds__(NT) void k_update_haar(Params P) {
     precond_tile<false, N>(v, d + row * N + col, P.L, col, rho, lam, P.precond, acc);
   }
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k + 1)[blockIdx.x] = tot;
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + P.k + 1)[B.x] = tot;
 }
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_update_haar(Params P) {
+  update_haar_body<T, N>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // After the last PCG iteration (Haar): alpha = <r, z> / <p, q>, x += alpha p.
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_last_x(Params P) {
+__device__ __forceinline__ void last_x_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
-  const size_t off = (size_t)blockIdx.x * ROWS * N;
+  FIRLS_SLICE_PROLOGUE_S(B.s)
+  const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)pcg_alpha(P, s_, rz, pq);
+  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
   // E elements per thread, CH at a time with their loads ahead of their
@@ -1021,6 +1061,11 @@ __global__ __launch_bounds__(NT) void k_last_x(Params P) {
     for (int u = 0; u < CH; ++u) x[threadIdx.x + (e0 + u) * NT] = xv[u] + pv[u] * al;
   }
 }
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_last_x(Params P) {
+  last_x_body<T, N>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // ---------------------------------------------------------------------------
 // Precision-only kernels (no FFT size).
@@ -1028,14 +1073,14 @@ __global__ __launch_bounds__(NT) void k_last_x(Params P) {
 
 // |D1 x|^2 and |D2 x|^2 per pixel (TV).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
+__device__ __forceinline__ void psi_sq_tv_body(const Params& P, const Blk B) {
   using C = cplx<T>;
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  FIRLS_SLICE_PROLOGUE_S(B.s)
   const int n = P.n;
   const C* x = static_cast<const C*>(D.x);
   T* sq = static_cast<T*>(D.sq);
   const int total = P.C * n * n;        // D1 rows of every contrast, then D2 rows
-  for (int i = blockIdx.x * NT * 4 + threadIdx.x, e = 0; e < 4 && i < total; ++e, i += NT) {
+  for (int i = B.x * NT * 4 + threadIdx.x, e = 0; e < 4 && i < total; ++e, i += NT) {
     const int r = i / n, c = i - r * n;          // r counts rows of all contrasts
     const int lr = r % n;                         // row within the contrast
     const int rp = lr + 1 == n ? r - lr : r + 1, cp = c + 1 == n ? 0 : c + 1;
@@ -1044,20 +1089,25 @@ __global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
     sq[total + i] = (T)cabs2(x[r * n + cp] - (tv_cut(P.tvb, c, n) ? z : v));
   }
 }
+template <typename T>
+__global__ __launch_bounds__(NT) void k_psi_sq_tv(Params P) {
+  psi_sq_tv_body<T>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // W_g = (sum_{j in g} |z_j|^2 + eps)^{-1/2} (eq. 12 / eq. 37) and the
 // penalty partials sum sqrt(s_g + eps), sum sqrt(s_g).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_group_w(Params P) {
+__device__ __forceinline__ void group_w_body(const Params& P, const Blk B) {
   __shared__ double red[2 * NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  FIRLS_SLICE_PROLOGUE_S(B.s)
   const T* sq = static_cast<const T*>(D.sq);
   T* W = static_cast<T*>(D.W);
   const int ng = P.shape.n_groups;
   double ae = 0.0, a0 = 0.0;
 #pragma unroll
   for (int e = 0; e < GROUPS_PER_WG / NT; ++e) {
-    const int g = blockIdx.x * GROUPS_PER_WG + e * NT + threadIdx.x;
+    const int g = B.x * GROUPS_PER_WG + e * NT + threadIdx.x;
     if (g < ng) {
       double s = 0.0;
       for (int j = P.shape.gptr[g]; j < P.shape.gptr[g + 1]; ++j) s += (double)sq[P.shape.gidx[j]];
@@ -1069,21 +1119,26 @@ __global__ __launch_bounds__(NT) void k_group_w(Params P) {
   }
   block_sum2(ae, a0, red);
   if (threadIdx.x == 0) {
-    slot_wptr(D, SLOT_REG_EPS)[blockIdx.x] = ae;
-    slot_wptr(D, SLOT_REG0)[blockIdx.x] = a0;
+    slot_wptr(D, SLOT_REG_EPS)[B.x] = ae;
+    slot_wptr(D, SLOT_REG0)[B.x] = a0;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(NT) void k_group_w(Params P) {
+  group_w_body<T>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // d_j = sum over groups containing j of W_g (diag(G^T W G), eq. 13).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_group_d(Params P) {
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+__device__ __forceinline__ void group_d_body(const Params& P, const Blk B) {
+  FIRLS_SLICE_PROLOGUE_S(B.s)
   const T* W = static_cast<const T*>(D.W);
   T* d = static_cast<T*>(D.d);
   const int nc = P.shape.n_coef;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int j = blockIdx.x * NT * 4 + e * NT + threadIdx.x;
+    const int j = B.x * NT * 4 + e * NT + threadIdx.x;
     if (j < nc) {
       double s = 0.0;
       for (int t = P.shape.tptr[j]; t < P.shape.tptr[j + 1]; ++t) s += (double)W[P.shape.tidx[t]];
@@ -1091,6 +1146,11 @@ __global__ __launch_bounds__(NT) void k_group_d(Params P) {
     }
   }
 }
+template <typename T>
+__global__ __launch_bounds__(NT) void k_group_d(Params P) {
+  group_d_body<T>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 // TV preconditioner z = M^{-1} r with M = (D + L) D^{-1} (D + U) the
 // symmetric Gauss-Seidel factors of P = rho I + lambda (D1^T W1 D1 +
@@ -1103,7 +1163,7 @@ __global__ __launch_bounds__(NT) void k_group_d(Params P) {
 // the residual is read from r[k & 1] and written to r[(k + 1) & 1], so a
 // halo never sees a neighbour's update.
 template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_update_tv(Params P) {
+__device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   using C = cplx<T>;
   constexpr int H = 2, RR = TV_TR + 2 * H, RC = TV_TC + 2 * H, WR = RR + 1, WC = RC + 1;
   __shared__ C rn[RR * RC];
@@ -1112,10 +1172,10 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   __shared__ T w1[WR * WC];
   __shared__ T w2[WR * WC];
   __shared__ double red[NT / 64];
-  FIRLS_SLICE_PROLOGUE(blockIdx.y)
+  FIRLS_SLICE_PROLOGUE_S(B.s)
   const int n = P.n;
   const int tiles_x = n / TV_TC;
-  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int ty = B.x / tiles_x, tx = B.x - ty * tiles_x;
   // tiles run over the rows of all contrasts; a tile lies in one contrast,
   // whose image (and D1, D2 weights) the pointers below select
   const int ch = (ty * TV_TR) / n;
@@ -1129,7 +1189,7 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
   if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-    al = (T)pcg_alpha(P, s_, rz, pq);
+    al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
   }
   const C* q = static_cast<const C*>(D.q) + cb;
   // coupling weights: slots that hold identity rows (tvb) couple nothing
@@ -1208,7 +1268,12 @@ __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
 #undef W2P
 #undef W2M
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[blockIdx.x] = tot;
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[B.x] = tot;
 }
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_update_tv(Params P) {
+  update_tv_body<T, MODE>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+}
+
 
 }  // namespace firls

@@ -55,6 +55,15 @@ const GemmKernels* gemm_kernels(bool fp64);
 // slices and starts those (as k_slice_init does); one workgroup per record.
 hipError_t launch_refill(const RefillArgs& A, hipStream_t st);
 
+// Launches across shapes (MultiClass x mode); null where not built.
+using MultiLauncher = hipError_t (*)(const MultiArgs&, int items, size_t lds, hipStream_t);
+struct MultiKernels {
+  MultiLauncher fn[MC_COUNT][MC_MODES];
+};
+const MultiKernels* multi_kernels(bool fp64);
+// Dynamic LDS a kernel of class cls needs for image side n (0: none).
+size_t multi_lds_bytes(bool fp64, int cls, int n);
+
 // nullptr if the size is not built for that precision.
 const SizeKernels* size_kernels(bool fp64, int n);
 const PrecKernels* prec_kernels(bool fp64);

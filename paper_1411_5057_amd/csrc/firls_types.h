@@ -151,6 +151,24 @@ struct ShapeDev {
   int32_t Mp;            // M rounded up to the GEMM row tile
 };
 
+// Launches across shapes: one workgroup per item; the item names the slice,
+// the block within it and the parameters (an entry of a device table of
+// Params, one per shape and launch position) its shape's kernel runs with.
+struct MultiItem {
+  int32_t s;   // slice
+  int32_t x;   // block within the slice
+  int32_t p;   // Params entry
+};
+struct MultiArgs;   // below Params
+
+// Kernel classes of launches across shapes (the mode is the kernel's
+// template mode where it has one).
+enum MultiClass : int { MC_ROWFWD = 0, MC_COL, MC_ROWINV, MC_PAIR, MC_PSI_SQ_HAAR, MC_UPDATE_HAAR, MC_LAST_X,
+                        MC_PSI_SQ_TV, MC_GROUP_W, MC_GROUP_D, MC_UPDATE_TV, MC_OUTER_CHECK, MC_COUNT };
+constexpr int MC_MODES = 7;
+
+#define FIRLS_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
 // Kernel parameters (passed by value).
 struct Params {
   const SliceDesc* desc;
@@ -187,6 +205,11 @@ struct Params {
   void* out;             // op entry points: extra output
   int32_t* stop_flags;   // host-mapped word per slice, (evaluations << 1) | active,
                          // written by the outer check (null: not written)
+};
+
+struct MultiArgs {
+  const Params* __restrict__ table;
+  const MultiItem* __restrict__ items;
 };
 
 }  // namespace firls

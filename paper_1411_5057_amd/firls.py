@@ -26,6 +26,9 @@ FIRLS_E_SYNC = -6
 FIRLS_E_BREAKDOWN = -7
 FIRLS_W_MAXITER = 1
 FIRLS_W_NONMONOTONE = 2
+FIRLS_SCHED_PER_SHAPE = 0
+FIRLS_SCHED_ACROSS = 1
+FIRLS_SCHED_ACROSS_LARGEST_FIRST = 2
 FIRLS_TEST_SYNC_TIMEOUT = 1
 FIRLS_TEST_BREAKDOWN = 2
 FIRLS_TEST_NONMONOTONE = 4
@@ -48,6 +51,7 @@ EXPORTED = (
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
     "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_test_hooks", "firls_autotune",
+    "firls_set_schedule", "firls_get_schedule",
 )
 PROF_CLASSES = 15
 
@@ -221,6 +225,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_set_paired": ([vp, i32], ctypes.c_int),
         "firls_test_sync_timeout": ([vp, i32], ctypes.c_int),
         "firls_test_hooks": ([vp, i32], ctypes.c_int),
+        "firls_set_schedule": ([vp, i32], ctypes.c_int),
+        "firls_get_schedule": ([vp], ctypes.c_int),
         "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
@@ -654,6 +660,15 @@ class Solver:
     def test_sync_timeout(self, enable: bool):
         """Test hook: the paired pass's barrier times out at once (FIRLS_E_SYNC)."""
         _check(load().firls_test_sync_timeout(self.handle, int(enable)), "firls_test_sync_timeout")
+
+    def set_schedule(self, schedule: int):
+        """FIRLS_SCHED_*: per-shape launches or one launch per kernel class
+        and position across the shapes of a mixed batch."""
+        _check(load().firls_set_schedule(self.handle, int(schedule)), "firls_set_schedule")
+
+    @property
+    def schedule(self) -> int:
+        return _check(load().firls_get_schedule(self.handle), "firls_get_schedule")
 
     def test_hooks(self, flags: int):
         """Test hooks (FIRLS_TEST_* bits; 0 clears them): forced conditions
