@@ -99,7 +99,8 @@ int forward(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0) {
 }
 
 // Inference: the whole network in one kernel (activations stay on chip),
-// one persistent workgroup per compute unit looping over 16 x 16 tiles.
+// one persistent workgroup per compute unit looping over the image blocks
+// it streams down row by row.
 int forward_fused(firls_cnn* c, hipStream_t st, int batch, const void* zf, void* x0) {
   static int cus = 0;
   if (!cus) {
@@ -116,8 +117,7 @@ int forward_fused(firls_cnn* c, hipStream_t st, int batch, const void* zf, void*
   }
   a.n = c->n;
   a.batch = batch;
-  const int tiles = batch * (c->n / 16) * (c->n / 16);
-  CHK(launch_net_fwd(a, std::min(tiles, cus), st));
+  CHK(launch_net_fwd(a, std::min(net_fwd_items(c->n, batch), cus), st));
   return FIRLS_OK;
 }
 

@@ -1,17 +1,35 @@
-// Inference of the whole warm-start network in one kernel.
+// Inference of the whole warm-start network in one kernel, streamed down
+// the image row by row.
 //
-// The five 3x3 layers run back to back on a 16 x 16 output tile with the
-// intermediate activations kept in LDS: layer l (1..5) produces a tile of
-// side 16 + 2 (5 - l) around the output tile, so every layer reads only
-// what the previous one left on chip, and the image is read once (zf) and
-// written once (x0).  Outside the image every activation is zero, exactly
-// the "same" zero padding of the layer-by-layer network.  bf16 activations
-// and weights, FP32 accumulation on v_mfma_f32_16x16x32_bf16: lane l holds
-// A[l%16][8(l/16) .. +7] (weights: out channel, 8 in channels), B[8(l/16)
-// .. +7][l%16] (8 channels of one pixel) and D[4(l/16)+j][l%16] (four out
-// channels of that pixel).  The first layer stacks its 9 taps x 2 channels
-// into one K = 32 product.  Workgroups loop over tiles, so the weights are
-// staged in LDS once per workgroup.
+// A workgroup owns an output block of BH rows by SW columns of one image
+// (BH, SW in {32, 64, 128}, the largest that divide n) and walks it from top
+// to bottom.  Every layer keeps the last four rows it produced in an LDS
+// ring buffer: at step t layer l (1..5) computes row R0 - 4 + t - 2 (l - 1)
+// of its output from rows r - 1 .. r + 1 of the layer below, written at the
+// three steps before, while that layer writes its fourth ring row, so one
+// barrier per step orders everything.  Rows are computed once (no vertical
+// recomputation between neighbouring tiles); only 5 columns on each side are
+// recomputed (layer widths SW + 8, +6, +4, +2, SW).  Outside the image every
+// activation is zero, the "same" zero padding of the layer-by-layer network.
+//
+// Sixteen waves: four per 32 -> 32 layer (2, 3, 4) and four for layers 1
+// and 5 (and the input rows).  Each wave keeps its layers' weights in
+// registers for the whole kernel and takes every fourth 16-pixel block of
+// its layer's row.  Waves w and w + 4k share a SIMD (w mod 4), so each SIMD
+// runs one wave of every role, with the block offsets rotated by role so the
+// rows' odd ninth blocks land on different SIMDs.  bf16 activations and weights, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16: lane (q = l / 16, m = l % 16) holds
+// A[m][8q .. 8q + 7] (weights: output channel m of the block, 8 input
+// channels), B[8q .. 8q + 7][m] (8 input channels of pixel m) and
+// D[4q + j][m] (four output channels of pixel m).
+//
+// An activation pixel is 64 bytes: 32 channels in the order
+// 16a + 4q + j -> 8q + 4a + j, so lane (q, m) of a layer's output writes its
+// two blocks' four channels (a = 0, 1) as one 16-byte chunk, and chunk q of
+// pixel p sits at chunk position q ^ ((p >> 1) & 3): the eight lanes that
+// read or write at once (eight consecutive pixels, one chunk each) cover all
+// eight 16-byte bank groups of a 128-byte bank row.  The weights are loaded
+// in the same input-channel order.
 #include <hip/hip_runtime.h>
 
 #include "cnn_types.h"
@@ -26,219 +44,313 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-constexpr int FT = 16;            // output tile side
-constexpr int FPS = 40;           // LDS pixel stride (bf16) of 32-channel activations
-constexpr int NW = 8;             // waves per workgroup
-constexpr int UB = 2;             // 16-pixel blocks per wave and pass
-constexpr int IN_W = FT + 10;     // input tile side (5-pixel halo)
-constexpr int A_PIX = (FT + 8) * (FT + 8);   // layer-1 output tile (24 x 24)
-constexpr int B_PIX = (FT + 6) * (FT + 6);   // layer-2 output tile (22 x 22)
-constexpr int W32 = 9 * 32 * 32;              // bf16 weights of a 32 -> 32 layer
-constexpr int W5 = 9 * 16 * 32;               // last layer (16 padded outputs)
+constexpr int SNW = 16;                 // waves per workgroup
+constexpr int SNT = SNW * 64;
+constexpr int WPL = 4;                  // waves per layer role
+constexpr int RING = 4;                 // rows kept per layer
+constexpr int HALO = 5;                 // columns recomputed on each side of the strip (input)
+constexpr int MAXSW = 128;              // widest strip
+constexpr int MAXB = (MAXSW + 2 * 4 + 15) / 16;   // 16-pixel blocks of the widest layer row (9)
+constexpr int ROWPX = MAXB * 16;        // pixel slots of a ring row (144)
+constexpr int PXB = 64;                 // bytes of a 32-channel bf16 pixel
+constexpr size_t OFF_IN = 0;                                   // input ring: RING x ROWPX x (re, im) bf16
+constexpr size_t OFF_ACT = (size_t)RING * ROWPX * 4;            // layer l ring: OFF_ACT + (l - 1) * ACT_RING
+constexpr size_t ACT_RING = (size_t)RING * ROWPX * PXB;
+// A row's last block reads up to two pixels past the row's ROWPX slots (its
+// lanes beyond the row width are discarded); the tail keeps those reads of
+// the last ring row inside the allocation.
+constexpr size_t LDS_TAIL = 2 * PXB;
+constexpr size_t LDS_BYTES = OFF_ACT + 4 * ACT_RING + LDS_TAIL;
 
-constexpr size_t OFF_IN = 0;                                   // uint32 [IN_W^2]
-constexpr size_t OFF_A = (OFF_IN + IN_W * IN_W * 4 + 15) / 16 * 16;
-constexpr size_t OFF_B = OFF_A + (size_t)A_PIX * FPS * 2;
-constexpr size_t OFF_W = OFF_B + (size_t)B_PIX * FPS * 2;     // 3 x W32 then W5
-constexpr size_t LDS_BYTES = OFF_W + (size_t)(3 * W32 + W5) * 2;
+// ring slot of row r (r > -64)
+__device__ __forceinline__ int slot(int r) { return (r + 64) & (RING - 1); }
 
-// Weights sit in LDS as rows of 32 in-channels (four 16-byte chunks); chunk
-// c of row r is stored at position c ^ ((r >> 1) & 3), so the eight rows a
-// group of lanes reads at once fall into distinct banks.
-__device__ __forceinline__ int wswz(int row, int chunk) { return row * 4 + (chunk ^ ((row >> 1) & 3)); }
+// byte offset of 16-byte chunk q of pixel p within a ring row
+__device__ __forceinline__ int chunk_off(int p, int q) { return p * PXB + ((q ^ ((p >> 1) & 3)) << 4); }
 
 // ReLU of a float through its bit pattern: every negative value (sign bit
 // set) maps to +0 by a signed integer max
 __device__ __forceinline__ float relu(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
 
-// ReLU (zero outside the image) of four consecutive channels (bias already
-// in the accumulator) as bf16
-__device__ __forceinline__ void put4(unsigned short* dst, const f4& v, bool inside) {
-  const f2v lo = {relu(v[0]), relu(v[1])};
-  const f2v hi = {relu(v[2]), relu(v[3])};
-  uint2 pk;
-  pk.x = inside ? __builtin_bit_cast(unsigned int, __builtin_convertvector(lo, bf2)) : 0u;
-  pk.y = inside ? __builtin_bit_cast(unsigned int, __builtin_convertvector(hi, bf2)) : 0u;
-  *reinterpret_cast<uint2*>(dst) = pk;
+__device__ __forceinline__ unsigned int pack2(float a, float b) {
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector(f2v{a, b}, bf2));
 }
 
 // (r, c) inside the n x n image
 __device__ __forceinline__ bool in_image(int r, int c, int n) { return (unsigned)r < (unsigned)n && (unsigned)c < (unsigned)n; }
 
-// One 32 -> 32 layer from an LDS tile of side WIN to one of side WIN - 2,
-// whose top-left pixel is (gr0, gc0) in the image.
-template <int WIN>
-__device__ __forceinline__ void layer32(const unsigned short* in, unsigned short* out, const uint4* w,
-                                        const float* bias, int gr0, int gc0, int n) {
-  constexpr int WOUT = WIN - 2, NPIX = WOUT * WOUT, NBLK = (NPIX + 15) / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, q = lane >> 4;
-  bf8 wf[9][2];
+// A-operand fragment of a 32 -> COUT_PAD layer: output channel o, input
+// channels 16 (e / 4) + 4 q + e % 4 for e = 0..7 (packed [9][COUT_PAD][32])
+__device__ __forceinline__ bf8 load_w32(const unsigned short* w, int cout_pad, int t, int o, int q) {
+  const unsigned short* row = w + ((size_t)t * cout_pad + o) * 32;
+  const uint2 lo = *reinterpret_cast<const uint2*>(row + 4 * q);
+  const uint2 hi = *reinterpret_cast<const uint2*>(row + 16 + 4 * q);
+  return __builtin_bit_cast(bf8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+// Lane offsets of tap column dx (0..2) within a 16-pixel block: pixel
+// 16 b + m + dx of a ring row sits at 1024 b + sw[dx] (the swizzle depends
+// only on the pixel's position in its block), so a block's nine reads are a
+// row offset plus one of three per-lane offsets plus a constant.
+struct TapOffsets {
+  int sw[3];
+  __device__ __forceinline__ TapOffsets(int m, int q) {
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+    for (int dx = 0; dx < 3; ++dx) sw[dx] = chunk_off(m + dx, q);
+  }
+};
+
+// One row of a 32 -> 32 layer (2, 3 or 4): blocks b0, b0 + WPL, ... of the
+// row's nblk blocks, one at a time (both output blocks of 16 channels share
+// each activation read; the next tap's read is issued before this tap's
+// products).  in_row[dy] is the LDS offset of input row r - 1 + dy.
+__device__ __forceinline__ void conv_row(const unsigned char* lds, const int (&in_row)[3], const bf8 (&wf)[9][2],
+                                         const f4 (&bo)[2], const TapOffsets& to, int b0, int nblk, int width, int m,
+                                         unsigned char* out_row, int gr, int gc0, int n, bool row_inside) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) wf[t][a] = __builtin_bit_cast(bf8, w[wswz(t * 32 + a * 16 + l16, q)]);
-  f4 bo[2];
+  for (int u = 0; u < 3; ++u) {
+    const int b = b0 + u * WPL;
+    if (b >= nblk) break;
+    const int j = b * 16 + m;
+    const unsigned char* blk = lds + b * 16 * PXB;
+    f4 acc[2] = {bo[0], bo[1]};
+    if (row_inside) {
+      bf8 cur = *reinterpret_cast<const bf8*>(blk + in_row[0] + to.sw[0]);
 #pragma unroll
-  for (int a = 0; a < 2; ++a) bo[a] = *reinterpret_cast<const f4*>(bias + 16 * a + 4 * q);
-  for (int blk = UB * wave; blk < NBLK; blk += UB * NW) {
-    int p[UB], base[UB];
-    bool inside[UB];
+      for (int t = 0; t < 9; ++t) {
+        bf8 nxt = cur;
+        if (t < 8) {
+          const int tn = t + 1;
+          nxt = *reinterpret_cast<const bf8*>(blk + in_row[tn / 3] + to.sw[tn % 3]);
+        }
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      p[u] = blk + u < NBLK ? (blk + u) * 16 + l16 : NPIX;
-      const int pc = p[u] < NPIX ? p[u] : NPIX - 1;
-      const int i = pc / WOUT, j = pc - i * WOUT;
-      base[u] = (i * WIN + j) * FPS + 8 * q;
-      inside[u] = in_image(gr0 + i, gc0 + j, n);
+        for (int a = 0; a < 2; ++a) acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[t][a], cur, acc[a], 0, 0, 0);
+        cur = nxt;
+      }
     }
-    f4 acc[UB][2];
+    if (j >= width) continue;
+    const bool inside = row_inside && in_image(gr, gc0 + j, n);
+    uint4 v;
+    v.x = inside ? pack2(relu(acc[0][0]), relu(acc[0][1])) : 0u;
+    v.y = inside ? pack2(relu(acc[0][2]), relu(acc[0][3])) : 0u;
+    v.z = inside ? pack2(relu(acc[1][0]), relu(acc[1][1])) : 0u;
+    v.w = inside ? pack2(relu(acc[1][2]), relu(acc[1][3])) : 0u;
+    *reinterpret_cast<uint4*>(out_row + b * 16 * PXB + to.sw[0]) = v;
+  }
+}
+
+// Layer 5 (32 -> 2, outputs padded to 16: one output block): the wave's
+// blocks one at a time, the next tap's activation read issued before this
+// tap's product; then x0 = zf + f(zf) (channels 0, 1 in rows 0, 1 of D,
+// lanes q = 0).  (Three interleaved chains measured 40% slower: the other
+// waves on the SIMD already hide the chain's latency.)
+__device__ __forceinline__ void conv_row_last(const unsigned char* lds, const int (&in_row)[3], const bf8 (&wf)[9],
+                                              const f4& bo, const TapOffsets& to, int b0, int nblk, int width, int q,
+                                              int m, const float2 (&zf)[3], float2* x0_row) {
 #pragma unroll
-    for (int u = 0; u < UB; ++u)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) acc[u][a] = bo[a];
+  for (int u = 0; u < 3; ++u) {
+    const int b = b0 + u * WPL;
+    if (b >= nblk) break;
+    const unsigned char* blk = lds + b * 16 * PXB;
+    f4 acc = bo;
+    bf8 cur = *reinterpret_cast<const bf8*>(blk + in_row[0] + to.sw[0]);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      bf8 bop[UB];
-#pragma unroll
-      for (int u = 0; u < UB; ++u)
-        bop[u] = *reinterpret_cast<const bf8*>(in + base[u] + ((t / 3) * WIN + t % 3) * FPS);
-#pragma unroll
-      for (int u = 0; u < UB; ++u)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) acc[u][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[t][a], bop[u], acc[u][a], 0, 0, 0);
+      bf8 nxt = cur;
+      if (t < 8) nxt = *reinterpret_cast<const bf8*>(blk + in_row[(t + 1) / 3] + to.sw[(t + 1) % 3]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[t], cur, acc, 0, 0, 0);
+      cur = nxt;
     }
-#pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      if (p[u] < NPIX)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) put4(out + p[u] * FPS + 16 * a + 4 * q, acc[u][a], inside[u]);
-    }
+    const int j = b * 16 + m;
+    if (j < width && q == 0) x0_row[j] = make_float2(zf[u].x + acc[0], zf[u].y + acc[1]);
   }
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(NW * 64) void k_net_fwd(NetArgs A) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  unsigned int* xin = reinterpret_cast<unsigned int*>(smem + OFF_IN);
-  unsigned short* bufA = reinterpret_cast<unsigned short*>(smem + OFF_A);
-  unsigned short* bufB = reinterpret_cast<unsigned short*>(smem + OFF_B);
-  uint4* wl = reinterpret_cast<uint4*>(smem + OFF_W);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, q = lane >> 4;
-  const int n = A.n, tpr = n / FT, tpi = tpr * tpr;
-  const int ntiles = tpi * A.batch;
-
-  // weights of layers 2..5 into LDS, once per workgroup (16 B per thread)
-  for (int l = 0; l < 4; ++l) {
-    const int rows = l < 3 ? 9 * 32 : 9 * 16;
-    const uint4* src = static_cast<const uint4*>(A.w[l + 1]);
-    for (int i = tid; i < rows * 4; i += NW * 64) wl[l * (W32 / 8) + wswz(i >> 2, i & 3)] = src[i];
+// Geometry of one launch: strips of SW columns, bands of BH = SW rows.
+struct NetGeo {
+  int n, SW, BH, strips, bands, items;
+  __device__ __forceinline__ int width(int l) const { return SW + 2 * (5 - l); }   // layer l's row
+  __device__ __forceinline__ int nblocks(int l) const { return (width(l) + 15) / 16; }
+  __device__ __forceinline__ void item(int it, int& img, int& R0, int& c0) const {
+    img = it / (strips * bands);
+    const int rest = it - img * strips * bands, band = rest / strips;
+    R0 = band * BH;
+    c0 = (rest - band * strips) * SW;
   }
-  // first layer: taps x channels stacked, k = 2 t + c < 18 (the rest zero);
-  // lane group q holds the taps 4q .. 4q + 3, one input pixel (2 channels,
-  // one uint32 of the input tile) each
+};
+
+__device__ __forceinline__ int ring_row(int l, int r) {   // LDS offset of row r of layer l's ring (l = 1..4)
+  return (int)(OFF_ACT + (size_t)(l - 1) * ACT_RING + (size_t)slot(r) * ROWPX * PXB);
+}
+
+// Waves 0-2: the input rows, layer 1 (2 -> 32, the 9 taps x 2 channels
+// stacked into K = 32) and layer 5 (32 -> 2) with x0 = zf + f(zf).
+__device__ __forceinline__ void net_role_io(const NetArgs& A, const NetGeo& G, unsigned char* smem, int sub, int q,
+                                            int m) {
+  const int tid = threadIdx.x, n = G.n;
+  unsigned int* in_ring = reinterpret_cast<unsigned int*>(smem + OFF_IN);
   bf8 w1f[2];
+  {
+    const unsigned short* w1 = static_cast<const unsigned short*>(A.w[0]);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = 8 * q + e, t = k >> 1, c = k & 1;
-      const unsigned short* w1 = static_cast<const unsigned short*>(A.w[0]);
-      w1f[a][e] = __builtin_bit_cast(__bf16, k < 18 ? w1[(t * 32 + a * 16 + l16) * 16 + c] : (unsigned short)0);
-    }
-  int toff[4];
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * q + e, t = k >> 1, c = k & 1;
+        w1f[a][e] = __builtin_bit_cast(__bf16, k < 18 ? w1[(t * 32 + a * 16 + m) * 16 + c] : (unsigned short)0);
+      }
+  }
+  const f4 b1[2] = {*reinterpret_cast<const f4*>(A.b[0] + 4 * q), *reinterpret_cast<const f4*>(A.b[0] + 16 + 4 * q)};
+  bf8 w5[9];
+  {
+    const unsigned short* w = static_cast<const unsigned short*>(A.w[4]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w5[t] = load_w32(w, 16, t, m, q);
+  }
+  const TapOffsets to(m, q);
+  const f4 b5 = *reinterpret_cast<const f4*>(A.b[4] + 4 * q);
+  // layer-1 taps of this lane group: taps 4q .. 4q + 3 (those below 9)
+  int dyo[4], dxo[4];
   bool tok[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int t = 4 * q + m;
-    tok[m] = t < 9;
-    toff[m] = tok[m] ? (t / 3) * IN_W + t % 3 : 0;
+  for (int mm = 0; mm < 4; ++mm) {
+    const int tt = 4 * q + mm;
+    tok[mm] = tt < 9;
+    dyo[mm] = tok[mm] ? tt / 3 - 1 : 0;
+    dxo[mm] = tok[mm] ? tt % 3 : 0;
   }
-  f4 b1[2];
+  for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+    int img, R0, c0;
+    G.item(it, img, R0, c0);
+    const float2* zf = static_cast<const float2*>(A.zf) + (size_t)img * n * n;
+    float2* x0 = static_cast<float2*>(A.x0) + (size_t)img * n * n;
+    // Input rows (columns c0 - 5 .. c0 + SW + 4; thread tid owns column
+    // tid) go through registers: the row a step needs is fetched two steps
+    // ahead and written to its ring slot one step ahead, so the global
+    // load's latency overlaps a step of work.  zf of the layer-5 row is
+    // fetched a step ahead as well.  Zero outside the image.
+    const int gcol = c0 - HALO + tid;
+    const bool in_col = tid < G.width(0);
+    auto fetch_in = [&](int r) -> float2 {
+      return in_col && in_image(r, gcol, n) ? zf[(size_t)r * n + gcol] : make_float2(0.f, 0.f);
+    };
+    auto put_in = [&](int r, float2 z) {
+      if (in_col) in_ring[slot(r) * ROWPX + tid] = pack2(z.x, z.y);
+    };
+    float2 z5[3] = {};
+    auto fetch_z5 = [&](int r) {
+      if (q != 0 || (unsigned)r >= (unsigned)n) return;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) b1[a] = *reinterpret_cast<const f4*>(A.b[0] + 16 * a + 4 * q);
-  const f4 b5 = *reinterpret_cast<const f4*>(A.b[4] + 4 * q);
+      for (int u = 0; u < 3; ++u) {
+        const int j = (sub + u * WPL) * 16 + m;
+        if (j < G.width(5)) z5[u] = zf[(size_t)r * n + c0 + j];
+      }
+    };
+    __syncthreads();   // the previous item's last reads of the rings are done
+    put_in(R0 - 5, fetch_in(R0 - 5));
+    put_in(R0 - 4, fetch_in(R0 - 4));
+    put_in(R0 - 3, fetch_in(R0 - 3));
+    float2 next_in = fetch_in(R0 - 2);
+    __syncthreads();
+    const int steps = G.BH + 12;
+    for (int t = 0; t < steps; ++t) {
+      if (t <= G.BH + 6) {   // the next step's layer-1 row needs input row R0 - 2 + t
+        put_in(R0 - 2 + t, next_in);
+        next_in = fetch_in(R0 - 1 + t);
+      }
+      if (t == 11) fetch_z5(R0);
+      const int r1 = R0 - 4 + t;
+      if (t <= G.BH + 7) {
+        const int nb = G.nblocks(1), w1w = G.width(1);
+        unsigned char* out = smem + ring_row(1, r1);
+        const bool row_in = (unsigned)r1 < (unsigned)n;
+        for (int b = sub; b < nb; b += WPL) {
+          const int j = b * 16 + m;
+          f4 acc[2] = {b1[0], b1[1]};
+          if (row_in) {
+            unsigned int raw[4];
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm)
+              raw[mm] = tok[mm] ? in_ring[slot(r1 + dyo[mm]) * ROWPX + j + dxo[mm]] : 0u;
+            const bf8 bop = __builtin_bit_cast(bf8, make_uint4(raw[0], raw[1], raw[2], raw[3]));
+#pragma unroll
+            for (int a = 0; a < 2; ++a) acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[a], bop, acc[a], 0, 0, 0);
+          }
+          if (j < w1w) {
+            const bool inside = row_in && in_image(r1, c0 - 4 + j, n);
+            uint4 v;
+            v.x = inside ? pack2(relu(acc[0][0]), relu(acc[0][1])) : 0u;
+            v.y = inside ? pack2(relu(acc[0][2]), relu(acc[0][3])) : 0u;
+            v.z = inside ? pack2(relu(acc[1][0]), relu(acc[1][1])) : 0u;
+            v.w = inside ? pack2(relu(acc[1][2]), relu(acc[1][3])) : 0u;
+            *reinterpret_cast<uint4*>(out + b * 16 * PXB + to.sw[0]) = v;
+          }
+        }
+      }
+      const int r5 = R0 - 12 + t;
+      if (t >= 12) {
+        const int in_row[3] = {ring_row(4, r5 - 1), ring_row(4, r5), ring_row(4, r5 + 1)};
+        conv_row_last(smem, in_row, w5, b5, to, sub, G.nblocks(5), G.width(5), q, m, z5, x0 + (size_t)r5 * n + c0);
+        fetch_z5(r5 + 1);   // for the next step (past the last row: nothing)
+      }
+      __syncthreads();
+    }
+  }
+}
 
-  // The input tile of the next tile is fetched into registers while the
-  // current one is computed (IN_PER values per thread, zero outside).
-  constexpr int IN_PER = (IN_W * IN_W + NW * 64 - 1) / (NW * 64);
-  unsigned int pre[IN_PER];
-  auto fetch = [&](int tile) {
-    const int img = tile / tpi, tl = tile - img * tpi;
-    const int r0 = (tl / tpr) * FT, c0 = (tl - (tl / tpr) * tpr) * FT;
-    const float2* zf = static_cast<const float2*>(A.zf) + (size_t)img * n * n;
+// Waves 3-11: layer l = 2, 3 or 4 (32 -> 32), row r = R0 - 4 + t - 2 (l - 1)
+// at step t.
+__device__ __forceinline__ void net_role_conv(const NetArgs& A, const NetGeo& G, unsigned char* smem, int l, int sub,
+                                              int q, int m) {
+  bf8 wf[9][2];
+  f4 bo[2];
+  {
+    const unsigned short* w = static_cast<const unsigned short*>(A.w[l - 1]);
 #pragma unroll
-    for (int e = 0; e < IN_PER; ++e) {
-      const int i = tid + e * NW * 64;
-      const int gr = r0 - 5 + i / IN_W, gc = c0 - 5 + i % IN_W;
-      unsigned int v = 0;
-      if (i < IN_W * IN_W && gr >= 0 && gr < n && gc >= 0 && gc < n) {
-        const float2 z = zf[(size_t)gr * n + gc];
-        v = __builtin_bit_cast(unsigned int, __builtin_convertvector(f2v{z.x, z.y}, bf2));
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) wf[t][a] = load_w32(w, 32, t, 16 * a + m, q);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) bo[a] = *reinterpret_cast<const f4*>(A.b[l - 1] + 16 * a + 4 * q);
+  }
+  const TapOffsets to(m, q);
+  const int first = 3 * l - 3, last = first + G.BH - 1 + 2 * (5 - l);
+  for (int it = blockIdx.x; it < G.items; it += gridDim.x) {
+    int img, R0, c0;
+    G.item(it, img, R0, c0);
+    __syncthreads();
+    __syncthreads();
+    const int steps = G.BH + 12;
+    for (int t = 0; t < steps; ++t) {
+      const int r = R0 - 4 + t - 2 * (l - 1);
+      if (t >= first && t <= last) {
+        const int in_row[3] = {ring_row(l - 1, r - 1), ring_row(l - 1, r), ring_row(l - 1, r + 1)};
+        conv_row(smem, in_row, wf, bo, to, sub, G.nblocks(l), G.width(l), m, smem + ring_row(l, r), r,
+                 c0 - (5 - l), G.n, (unsigned)r < (unsigned)G.n);
       }
-      pre[e] = v;
-    }
-  };
-  if (blockIdx.x < ntiles) fetch(blockIdx.x);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int img = tile / tpi, tl = tile - img * tpi;
-    const int r0 = (tl / tpr) * FT, c0 = (tl - (tl / tpr) * tpr) * FT;
-    const float2* zf = static_cast<const float2*>(A.zf) + (size_t)img * n * n;
-    __syncthreads();   // the previous tile's last reads of the LDS are done
-#pragma unroll
-    for (int e = 0; e < IN_PER; ++e) {
-      const int i = tid + e * NW * 64;
-      if (i < IN_W * IN_W) xin[i] = pre[e];
-    }
-    if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);
-    __syncthreads();
-    // layer 1: 2 -> 32 on the 24 x 24 tile at (r0 - 4, c0 - 4)
-    {
-      constexpr int WOUT = FT + 8, NPIX = WOUT * WOUT;
-      for (int blk = wave; blk < NPIX / 16; blk += NW) {
-        const int p = blk * 16 + l16, i = p / WOUT, j = p % WOUT;
-        uint4 raw;
-        raw.x = tok[0] ? xin[i * IN_W + j + toff[0]] : 0u;
-        raw.y = tok[1] ? xin[i * IN_W + j + toff[1]] : 0u;
-        raw.z = tok[2] ? xin[i * IN_W + j + toff[2]] : 0u;
-        raw.w = tok[3] ? xin[i * IN_W + j + toff[3]] : 0u;
-        const bf8 bop = __builtin_bit_cast(bf8, raw);
-        const bool inside = in_image(r0 - 4 + i, c0 - 4 + j, n);
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-          put4(bufA + p * FPS + 16 * a + 4 * q, __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[a], bop, b1[a], 0, 0, 0),
-               inside);
-      }
-    }
-    __syncthreads();
-    layer32<FT + 8>(bufA, bufB, wl, A.b[1], r0 - 3, c0 - 3, n);
-    __syncthreads();
-    layer32<FT + 6>(bufB, bufA, wl + W32 / 8, A.b[2], r0 - 2, c0 - 2, n);
-    __syncthreads();
-    layer32<FT + 4>(bufA, bufB, wl + 2 * (W32 / 8), A.b[3], r0 - 1, c0 - 1, n);
-    __syncthreads();
-    // layer 5: 32 -> 2 (outputs padded to 16) on the 16 x 16 tile, plus zf
-    {
-      constexpr int WIN = FT + 2;
-      const uint4* w5 = wl + 3 * (W32 / 8);
-      float2* x0 = static_cast<float2*>(A.x0) + (size_t)img * n * n;
-      for (int blk = wave; blk < FT * FT / 16; blk += NW) {
-        const int p = blk * 16 + l16, i = p / FT, j = p % FT;
-        f4 acc = b5;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const bf8 wv = __builtin_bit_cast(bf8, w5[wswz(t * 16 + l16, q)]);
-          const bf8 bop = *reinterpret_cast<const bf8*>(bufB + ((i + t / 3) * WIN + j + t % 3) * FPS + 8 * q);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, bop, acc, 0, 0, 0);
-        }
-        if (q == 0) {
-          const size_t g = (size_t)(r0 + i) * n + c0 + j;
-          const float2 z = zf[g];
-          x0[g] = make_float2(z.x + acc[0], z.y + acc[1]);
-        }
-      }
+      __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(SNT) void k_net_fwd(NetArgs A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, q = lane >> 4;
+  NetGeo G;
+  G.n = A.n;
+  G.SW = A.n % 128 == 0 ? 128 : (A.n % 64 == 0 ? 64 : 32);
+  G.BH = G.SW;
+  G.strips = A.n / G.SW;
+  G.bands = A.n / G.BH;
+  G.items = A.batch * G.strips * G.bands;
+  // roles by wave (uniform per wave): waves 0-3 input rows and layers 1, 5;
+  // waves 4k .. 4k + 3 layer k + 1.  Both paths pass the same number of
+  // barriers per work item (two, then one per step).
+  const int simd = wave & 3, k = wave >> 2, sub = (simd + k) & 3;
+  if (k == 0) net_role_io(A, G, smem, sub, q, m);
+  else net_role_conv(A, G, smem, k + 1, sub, q, m);
 }
 
 size_t net_fwd_lds_bytes() { return LDS_BYTES; }
@@ -250,8 +362,14 @@ hipError_t launch_net_fwd(const NetArgs& a, int grid, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_net_fwd, dim3(grid), dim3(NW * 64), LDS_BYTES, st, a);
+  hipLaunchKernelGGL(k_net_fwd, dim3(grid), dim3(SNT), LDS_BYTES, st, a);
   return hipGetLastError();
+}
+
+// Work items of one launch (one per output block of BH x SW pixels).
+int net_fwd_items(int n, int batch) {
+  const int SW = n % 128 == 0 ? 128 : (n % 64 == 0 ? 64 : 32);
+  return batch * (n / SW) * (n / SW);
 }
 
 }  // namespace cnn

@@ -100,6 +100,7 @@ struct ChooseArgs {
 
 hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs& a, hipStream_t st);
 hipError_t launch_net_fwd(const NetArgs& a, int grid, hipStream_t st);
+int net_fwd_items(int n, int batch);
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs& a, int chunks, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_pack(const PackArgs& a, hipStream_t st);
