@@ -262,8 +262,6 @@ def traffic_record():
     """Measured HBM bytes per pixel of each PCG kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel
     sources (else None)."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", "firls_pcg_256_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -273,10 +271,22 @@ def traffic_record():
             rec = json.loads(line.split(":", 1)[1])
     if rec is None:
         return None
+    return rec if pcg_source_sha() == rec["kernel_source_sha"] else None
+
+
+def pcg_source_sha():
+    """Hash of the sources the FIRLS kernels and their launches are built
+    from (every file under csrc/ except the network's cnn_* and the dense
+    GEMM's)."""
+    import glob
+    import hashlib
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1411_5057_amd", "csrc", "*"))):
+        b = os.path.basename(f)
+        if b.startswith("cnn") or b.startswith("gemm_dense"):
+            continue
         h.update(open(f, "rb").read())
-    return rec if h.hexdigest()[:16] == rec["kernel_source_sha"] else None
+    return h.hexdigest()[:16]
 
 
 def gap_stats(fe, fstar):
