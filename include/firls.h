@@ -149,6 +149,14 @@ typedef struct {
  *               reports 10 to 30 sufficient).
  *   outer_tol   tau: stop once (F_eps^{k-1} - F_eps^k) <= tau F_eps^k; 0
  *               runs max_outer solves.
+ *   pcg_rtol    eta in [0, 1): the PCG stopping criterion of Algorithms 2
+ *               and 3, which the paper leaves open, read as a relative
+ *               preconditioned-residual test: a solve stops after iteration
+ *               j once <r_j, P^{-1} r_j> <= eta^2 <r_0, P^{-1} r_0>
+ *               (x keeps that iterate; the report counts the iterations
+ *               taken).  0 runs exactly pcg_iters iterations per solve.  The
+ *               launches of the remaining iterations still run (their steps
+ *               are zero), so the exit changes results, not time.
  *   precond     FIRLS_PC_*.
  *   workspace   optional caller-owned device buffer (256-byte aligned) of
  *               workspace_bytes >= firls_workspace_bytes(cfg) bytes for the
@@ -167,6 +175,7 @@ typedef struct {
   int32_t max_outer;
   int32_t pcg_iters;
   double outer_tol;
+  double pcg_rtol;
   int32_t precond;
   void* workspace;
   size_t workspace_bytes;

@@ -407,6 +407,7 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.precond = h->cfg.precond;
   P.eps = h->cfg.eps;
   P.tau = h->cfg.outer_tol;
+  P.eta2 = h->cfg.pcg_rtol * h->cfg.pcg_rtol;
   P.test_flags = h->test_flags;
   // rounding slack of the monotone-objective check: F_eps is summed in FP64
   // from FP32 (or FP64) terms
@@ -1503,6 +1504,7 @@ int firls_create(const firls_config* cfg, firls_handle** out) {
   if (cfg->max_outer < 0) return fail(FIRLS_E_INVALID, "max_outer must be >= 0");
   if (cfg->pcg_iters < 1 || cfg->pcg_iters > KMAX) return fail(FIRLS_E_INVALID, "pcg_iters must be in 1..64");
   if (!(cfg->outer_tol >= 0.0)) return fail(FIRLS_E_INVALID, "outer_tol must be >= 0");
+  if (!(cfg->pcg_rtol >= 0.0 && cfg->pcg_rtol < 1.0)) return fail(FIRLS_E_INVALID, "pcg_rtol must be in [0, 1)");
   if (cfg->precond != FIRLS_PC_PAPER && cfg->precond != FIRLS_PC_JACOBI && cfg->precond != FIRLS_PC_NONE)
     return fail(FIRLS_E_INVALID, "precond must be FIRLS_PC_PAPER, FIRLS_PC_JACOBI or FIRLS_PC_NONE");
   if (cfg->workspace && (reinterpret_cast<uintptr_t>(cfg->workspace) & 255))

@@ -23,7 +23,7 @@ __device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& 
       S.rho = D.rho_fixed;
       S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
       S.active = 1;
-      S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
+      S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = S.pcg_stop = 0;
     }
     return;
   }
@@ -47,7 +47,7 @@ __device__ void init_slice(const SliceDesc& D, const uint8_t* mask, SliceState& 
     S.rho = cnt / (double)total;
     S.Fe = S.F = S.data = S.Fe_prev = S.rel = 0.0;
     S.active = 1;
-    S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = 0;
+    S.outer = S.pcg = S.status = S.converged = S.evals = S.pend = S.pcg_stop = 0;
     bool dc = true;
     for (int c = 0; D.need_dc && c < D.C; ++c) dc = dc && mask[(size_t)c * n * n] != 0;
     if (!dc) {

@@ -131,14 +131,36 @@ __device__ __forceinline__ void precond_tile(cplx<T> (&v)[16], const T* dg, int 
   else precond_tile_k<NEED_Z, N, PC_NONE>(v, dg, L, col, rho, lam, acc);
 }
 
-// alpha = <r, z> / <p, S p> of a PCG step of slice s.  For HPD S, <p, S p>
-// is positive whenever the residual is not zero (then <r, z> > 0 and p != 0),
-// so a non-positive (or NaN) <p, S p> with <r, z> > 0 is a breakdown: the
-// first workgroup records FIRLS_E_BREAKDOWN, which stops the slice at its
-// next outer check, and the step is taken as zero.  A zero residual (both
-// zero) is the ordinary end of the iteration: a zero step.  The test hook
-// TEST_BREAKDOWN turns <p, S p> negative.
-__device__ __forceinline__ double pcg_alpha(const Params& P, Blk B, double rz, double pq) {
+// Early exit of the PCG solve (the PCG stopping criterion of Algorithms 2
+// and 3, which the paper leaves open, read as a relative preconditioned-
+// residual test): the first iteration j >= 1 whose <r_j, z_j> is at most
+// eta^2 <r_0, z_0>, or 0.  Every kernel that forms a step decides from
+// the same <r_j, z_j> partials (written by earlier launches of the solve),
+// so all workgroups agree without communicating.
+__device__ __forceinline__ int pcg_stop_at(const Params& P, const SliceDesc& D, int k) {
+  if (!(P.eta2 > 0.0)) return 0;
+  const double lim = P.eta2 * slot_sum(slot_ptr(D, SLOT_RZ0), P.nrz);
+  for (int j = 1; j <= k; ++j)
+    if (slot_sum(slot_ptr(D, SLOT_RZ0 + j), P.nrz) <= lim) return j;
+  return 0;
+}
+
+// alpha = <r_k, z_k> / <p_k, S p_k> of PCG step k of slice s.  For HPD S,
+// <p, S p> is positive whenever the residual is not zero (then <r, z> > 0
+// and p != 0), so a non-positive (or NaN) <p, S p> with <r, z> > 0 is a
+// breakdown: the first workgroup records FIRLS_E_BREAKDOWN, which stops the
+// slice at its next outer check, and the step is taken as zero.  A zero
+// residual (both zero) is the ordinary end of the iteration: a zero step.
+// After the early exit every later step is zero (x and r stay at the
+// iterate of the exit), and the first workgroup records how many
+// iterations the solve took.  The test hook TEST_BREAKDOWN turns <p, S p>
+// negative.
+__device__ __forceinline__ double pcg_alpha(const Params& P, Blk B, int k, double rz, double pq) {
+  const int stop = pcg_stop_at(P, P.desc[B.s], k);
+  if (stop) {
+    if (B.x == 0 && threadIdx.x == 0) P.state[B.s].pcg_stop = stop;
+    return 0.0;
+  }
   if (P.test_flags & TEST_BREAKDOWN) pq = -fabs(pq);
   if (pq > 0.0) return rz / pq;
   if (rz > 0.0 && B.x == 0 && threadIdx.x == 0 && P.state[B.s].status >= 0) P.state[B.s].status = ST_E_BREAKDOWN;
@@ -161,6 +183,10 @@ __device__ __forceinline__ void outer_check_wg(const Params& P, int s) {
   const double F = data + D.lambda * r0;
   const bool first = S.evals == 0;
   const double prev = S.Fe;
+  // the solve before this check (counted as K iterations when it started)
+  // may have stopped early
+  if (!first && S.pcg_stop > 0) S.pcg -= P.K - S.pcg_stop;
+  S.pcg_stop = 0;
   S.Fe_prev = first ? Fe : prev;
   S.rel = first ? 0.0 : (prev - Fe) / Fe;
   S.Fe = Fe;
@@ -304,7 +330,7 @@ __device__ __forceinline__ void rowfwd_body(const Params& P, const Blk B) {
     if (pend) {
       const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
       const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-      al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
+      al = (T)pcg_alpha(P, Blk{B.x, s_}, P.k, rz, pq);
     }
     const C* p = static_cast<const C*>(D.p) + off;
     T* sqL = reinterpret_cast<T*>(smem);           // ROWS * N values
@@ -436,7 +462,7 @@ __device__ __forceinline__ void rowfwd_body(const Params& P, const Blk B) {
       const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k - 1), P.nrz);
       const double pqo = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k - 1), P.npq);
       const double qqo = slot_sum(slot_ptr(D, SLOT_QQ0 + P.k - 1), P.nrz);
-      const double ald = pcg_alpha(P, Blk{B.x, s_}, rzo, pqo);
+      const double ald = pcg_alpha(P, Blk{B.x, s_}, P.k - 1, rzo, pqo);
       const double rzn = ald * ald * qqo - rzo;
       const T al = (T)ald;
       const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -883,7 +909,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   const double rzo = slot_sum(slot_ptr(D, SLOT_RZ0 + k - 1), P.nrz);
   const double pqo = slot_sum_coherent(slot_ptr(D, SLOT_PQ0 + k - 1), P.npq);
   const double qqo = slot_sum_coherent(slot_ptr(D, SLOT_QQ0 + k - 1), P.nrz);
-  const double ald = pcg_alpha(P, Blk{B.x, s_}, rzo, pqo);
+  const double ald = pcg_alpha(P, Blk{B.x, s_}, k - 1, rzo, pqo);
   const double rzn = ald * ald * qqo - rzo;
   const T al = (T)ald;
   const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
@@ -987,7 +1013,7 @@ __device__ __forceinline__ void update_haar_body(const Params& P, const Blk B) {
   const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
+  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, P.k, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   C* r = static_cast<C*>(D.r[0]) + off;
   const C* p = static_cast<const C*>(D.p) + off;
@@ -1040,7 +1066,7 @@ __device__ __forceinline__ void last_x_body(const Params& P, const Blk B) {
   const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
+  const T al = (T)pcg_alpha(P, Blk{B.x, s_}, P.k, rz, pq);
   C* x = static_cast<C*>(D.x) + off;
   const C* p = static_cast<const C*>(D.p) + off;
   // E elements per thread, CH at a time with their loads ahead of their
@@ -1189,7 +1215,7 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
     const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
-    al = (T)pcg_alpha(P, Blk{B.x, s_}, rz, pq);
+    al = (T)pcg_alpha(P, Blk{B.x, s_}, P.k, rz, pq);
   }
   const C* q = static_cast<const C*>(D.q) + cb;
   // coupling weights: slots that hold identity rows (tvb) couple nothing

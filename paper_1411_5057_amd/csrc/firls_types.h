@@ -103,6 +103,8 @@ struct SliceState {
   int32_t evals;     // objective evaluations done
   int32_t pend;      // x += alpha p of the last PCG iteration not yet applied
                      // (folded into the next residual row pass)
+  int32_t pcg_stop;  // PCG iterations the current solve took when its early
+                     // exit fired (0: none yet); the outer check books it
 };
 
 // One slot refill of a streamed batch (a sub-batch whose slots take the
@@ -202,6 +204,7 @@ struct Params {
   double eps;
   double tau;
   double mono_slack;     // outer check: F_eps may exceed its previous value by this fraction (rounding)
+  double eta2;           // PCG early exit: stop once <r_j, z_j> <= eta2 <r_0, z_0> (0: run all K)
   void* out;             // op entry points: extra output
   int32_t* stop_flags;   // host-mapped word per slice, (evaluations << 1) | active,
                          // written by the outer check (null: not written)

@@ -67,7 +67,7 @@ class firls_config(ctypes.Structure):
     _fields_ = [("n_shapes", ctypes.c_int32), ("shapes", ctypes.POINTER(firls_shape)),
                 ("max_slices", ctypes.c_int32), ("prec", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
-                ("outer_tol", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("outer_tol", ctypes.c_double), ("pcg_rtol", ctypes.c_double), ("precond", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -506,7 +506,8 @@ class Solver:
 
     def __init__(self, shapes: Sequence[Shape], *, prec: str = "fp32", max_slices: int = 1,
                  eps: float = 1e-10, max_outer: int = 50, pcg_iters: int = 20,
-                 outer_tol: float = 0.0, precond: int = FIRLS_PC_PAPER, workspace=None):
+                 outer_tol: float = 0.0, pcg_rtol: float = 0.0, precond: int = FIRLS_PC_PAPER,
+                 workspace=None):
         """workspace: None (the library allocates its own), True (a torch
         buffer of firls_workspace_bytes(cfg) is allocated here and handed
         over), or a contiguous uint8 torch tensor on the GPU of at least
@@ -522,6 +523,7 @@ class Solver:
         cfg.max_outer = max_outer
         cfg.pcg_iters = pcg_iters
         cfg.outer_tol = outer_tol
+        cfg.pcg_rtol = pcg_rtol
         cfg.precond = precond
         self.workspace = None
         if workspace is not None and workspace is not False:

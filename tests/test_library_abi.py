@@ -117,3 +117,31 @@ def test_workspace_bytes_from_the_configuration():
     assert F.firls_workspace_bytes(cfg) == 3 * (4 * 2 * 524288 + 2 * 524288 + 8 * 65536 + 8192 + 197 * 512 * 8)
     cfg.max_slices = 0
     assert F.firls_workspace_bytes(cfg) == 0
+
+
+def test_create_validates_the_configuration_before_any_device_call():
+    """Out-of-range settings are rejected by firls_create itself with
+    FIRLS_E_INVALID and a message, before it touches a device (so this runs
+    without one): pcg_rtol must lie in [0, 1), pcg_iters in 1..64, eps > 0."""
+    import ctypes
+    from paper_1411_5057_amd import firls as F
+    shapes = (F.firls_shape * 1)(F.Shape(64, "haar", 3).c())
+
+    def create(**kw):
+        cfg = F.firls_config()
+        cfg.n_shapes, cfg.shapes, cfg.max_slices, cfg.prec = 1, shapes, 1, F.FIRLS_FP32
+        cfg.eps, cfg.max_outer, cfg.pcg_iters = 1e-10, 5, 10
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        h = ctypes.c_void_p()
+        rc = F.load().firls_create(ctypes.byref(cfg), ctypes.byref(h))
+        assert not h.value
+        return rc, F.load().firls_last_error().decode()
+
+    for bad in (-0.1, 1.0, 2.0, float("nan")):
+        rc, msg = create(pcg_rtol=bad)
+        assert rc == F.FIRLS_E_INVALID and "pcg_rtol" in msg, (bad, rc, msg)
+    rc, msg = create(pcg_iters=65)
+    assert rc == F.FIRLS_E_INVALID and "pcg_iters" in msg
+    rc, msg = create(eps=0.0)
+    assert rc == F.FIRLS_E_INVALID and "eps" in msg
