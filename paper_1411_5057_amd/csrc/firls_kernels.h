@@ -1187,11 +1187,14 @@ __global__ __launch_bounds__(NT) void k_group_d(Params P) {
 // Each workgroup owns a TV_TR x TV_TC tile and recomputes a two-pixel halo
 // of r (and a three-pixel halo of the weights) in LDS.  In UP_STEP mode
 // the residual is read from r[k & 1] and written to r[(k + 1) & 1], so a
-// halo never sees a neighbour's update.
+// halo never sees a neighbour's update; x and p of the thread's own pixels
+// are loaded first, so their latency overlaps the preconditioner.
 template <typename T, int MODE>
 __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   using C = cplx<T>;
   constexpr int H = 2, RR = TV_TR + 2 * H, RC = TV_TC + 2 * H, WR = RR + 1, WC = RC + 1;
+  constexpr int OUT = TV_TR * TV_TC / NT;   // pixels per thread
+  static_assert(OUT * NT == TV_TR * TV_TC, "whole tile per workgroup");
   __shared__ C rn[RR * RC];
   __shared__ C y[RR * RC];
   __shared__ T av[RR * RC];
@@ -1211,6 +1214,18 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   const C* rin = static_cast<const C*>(D.r[par]) + cb;
   const T* d1 = static_cast<const T*>(D.d) + cb;
   const T* d2 = static_cast<const T*>(D.d) + (size_t)P.C * n * n + cb;
+  C* x = static_cast<C*>(D.x) + cb;
+  const C* p = static_cast<const C*>(D.p) + cb;
+  C xv[OUT], pv[OUT];
+  if constexpr (MODE == UP_STEP) {
+#pragma unroll
+    for (int e = 0; e < OUT; ++e) {
+      const int i = threadIdx.x + e * NT;
+      const size_t g = (size_t)(r0 + i / TV_TC) * n + (c0 + i % TV_TC);
+      xv[e] = x[g];
+      pv[e] = p[g];
+    }
+  }
   T al = (T)0;
   if constexpr (MODE != UP_INIT) {
     const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
@@ -1269,10 +1284,10 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   __syncthreads();
   C* z = static_cast<C*>(D.z) + cb;
   C* rout = static_cast<C*>(D.r[par ^ 1]) + cb;
-  C* x = static_cast<C*>(D.x) + cb;
-  const C* p = static_cast<const C*>(D.p) + cb;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < TV_TR * TV_TC; i += NT) {
+#pragma unroll
+  for (int e = 0; e < OUT; ++e) {
+    const int i = threadIdx.x + e * NT;
     const int lr = H + i / TV_TC, lc = H + i % TV_TC;
     const int o = lr * RC + lc;
     const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
@@ -1286,7 +1301,7 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
     acc += cdot(rn[o], zz);
     if (MODE == UP_STEP) {
       rout[g] = rn[o];
-      x[g] = x[g] + p[g] * al;
+      x[g] = xv[e] + pv[e] * al;
     }
   }
 #undef W1P
