@@ -234,19 +234,34 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 // order to these slots.
 __device__ __forceinline__ bool tv_cut(int tvb, int i, int n) { return tvb && i == n - 1; }
 
-// lambda (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c) without lambda:
+// (D1^T W1 D1 + D2^T W2 D2) v at pixel (r, c), lambda left out:
 //   s1(r) W1[r] (v[r] - v[r+1]) + W1[r-1] (v[r] - s1(r-1) v[r-1]) + (same along c)
+// tv_gather loads what one pixel needs (so a caller can issue the loads of
+// several pixels before using any), tv_combine forms the value.
 template <typename T>
-__device__ __forceinline__ cplx<T> tv_normal(const cplx<T>* v, const T* w1, const T* w2, int n, int r, int c,
-                                             int tvb) {
+struct TvNb {
+  cplx<T> v0, vrp, vrm, vcp, vcm;
+  T a, b, e, f;
+};
+template <typename T>
+__device__ __forceinline__ TvNb<T> tv_gather(const cplx<T>* v, const T* w1, const T* w2, int n, int r, int c, int tvb) {
   const int rp = r + 1 == n ? 0 : r + 1, rm = r == 0 ? n - 1 : r - 1;
   const int cp = c + 1 == n ? 0 : c + 1, cm = c == 0 ? n - 1 : c - 1;
-  const cplx<T> v0 = v[r * n + c];
-  const T a = tv_cut(tvb, r, n) ? (T)0 : w1[r * n + c], b = w1[rm * n + c];
-  const T e = tv_cut(tvb, c, n) ? (T)0 : w2[r * n + c], f = w2[r * n + cm];
-  const cplx<T> vrm = tv_cut(tvb, rm, n) ? cplx<T>{(T)0, (T)0} : v[rm * n + c];
-  const cplx<T> vcm = tv_cut(tvb, cm, n) ? cplx<T>{(T)0, (T)0} : v[r * n + cm];
-  return (v0 - v[rp * n + c]) * a + (v0 - vrm) * b + (v0 - v[r * n + cp]) * e + (v0 - vcm) * f;
+  TvNb<T> g;
+  g.v0 = v[r * n + c];
+  g.vrp = v[rp * n + c];
+  g.vcp = v[r * n + cp];
+  g.a = tv_cut(tvb, r, n) ? (T)0 : w1[r * n + c];
+  g.b = w1[rm * n + c];
+  g.e = tv_cut(tvb, c, n) ? (T)0 : w2[r * n + c];
+  g.f = w2[r * n + cm];
+  g.vrm = tv_cut(tvb, rm, n) ? cplx<T>{(T)0, (T)0} : v[rm * n + c];
+  g.vcm = tv_cut(tvb, cm, n) ? cplx<T>{(T)0, (T)0} : v[r * n + cm];
+  return g;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> tv_combine(const TvNb<T>& g) {
+  return (g.v0 - g.vrp) * g.a + (g.v0 - g.vrm) * g.b + (g.v0 - g.vcp) * g.e + (g.v0 - g.vcm) * g.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -538,11 +553,32 @@ __device__ __forceinline__ void rowfwd_body(const Params& P, const Blk B) {
         }
       }
     } else {
+      // p = z + beta p over the band, eight pixels per thread at a time with
+      // their loads ahead of the stores (the compiler cannot prove that p
+      // and z do not overlap, and would otherwise wait for every load)
       const C* z = static_cast<const C*>(D.z) + off;
-      for (int i = threadIdx.x; i < ROWS * N; i += NT) {
-        const C pn = P.k > 0 ? z[i] + p[i] * bt : z[i];
-        p[i] = pn;
-        lds[Lay::at(i / N, i % N)] = pn;
+      constexpr int PER = ROWS * N / NT, CH = 8;
+      static_assert(PER * NT == ROWS * N, "whole band per workgroup");
+#pragma unroll
+      for (int e0 = 0; e0 < PER; e0 += CH) {
+        C zv[CH], pv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = threadIdx.x + (e0 + u) * NT;
+          if (e0 + u < PER) {
+            zv[u] = z[i];
+            pv[u] = P.k > 0 ? p[i] : C{(T)0, (T)0};
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = threadIdx.x + (e0 + u) * NT;
+          if (e0 + u < PER) {
+            const C pn = P.k > 0 ? zv[u] + pv[u] * bt : zv[u];
+            p[i] = pn;
+            lds[Lay::at(i / N, i % N)] = pn;
+          }
+        }
       }
     }
     if (!P.nofft) {   // a dense sensing matrix takes p itself, not its row FFT
@@ -769,7 +805,7 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
       const T* w2 = static_cast<const T*>(D.d) + (P.C + ch) * NN;
       auto emit = [&](int l, int q, C val) {
         const int i = l * N + q;
-        const C o = val + tv_normal<T>(vch, w1, w2, N, lrow0 + l, q, P.tvb) * (lam * sgn);
+        const C o = val + tv_combine(tv_gather<T>(vch, w1, w2, N, lrow0 + l, q, P.tvb)) * (lam * sgn);
         out[i] = o;
         if (SP) acc += cdot(v[i], o);
       };
