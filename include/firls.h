@@ -154,9 +154,9 @@ typedef struct {
  *               preconditioned-residual test: a solve stops after iteration
  *               j once <r_j, P^{-1} r_j> <= eta^2 <r_0, P^{-1} r_0>
  *               (x keeps that iterate; the report counts the iterations
- *               taken).  0 runs exactly pcg_iters iterations per solve.  The
- *               launches of the remaining iterations still run (their steps
- *               are zero), so the exit changes results, not time.
+ *               taken); the launches of the remaining iterations return at
+ *               once for that slice.  0 runs exactly pcg_iters iterations
+ *               per solve.
  *   precond     FIRLS_PC_*.
  *   workspace   optional caller-owned device buffer (256-byte aligned) of
  *               workspace_bytes >= firls_workspace_bytes(cfg) bytes for the

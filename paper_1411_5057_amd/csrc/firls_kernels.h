@@ -167,6 +167,19 @@ __device__ __forceinline__ double pcg_alpha(const Params& P, Blk B, int k, doubl
   return 0.0;
 }
 
+// A PCG launch whose work belongs to step k (it computes alpha_k, or feeds
+// only <p_k, S p_k>) does nothing once the early exit has removed that
+// step: every later step is zero, and nothing after the solve reads what
+// these launches would write (the next residual pass recomputes r, z, p
+// from x).  The first workgroup records the exit, as pcg_alpha would.
+// Uniform over the workgroup, so it may return before any barrier.
+__device__ __forceinline__ bool pcg_skip(const Params& P, const SliceDesc& D, int s, int bx, int k) {
+  if (!(P.eta2 > 0.0) || k < 1) return false;
+  const int stop = pcg_stop_at(P, D, k);
+  if (stop && bx == 0 && threadIdx.x == 0) P.state[s].pcg_stop = stop;
+  return stop != 0;
+}
+
 // Objective of the current x and the outer stopping rule of slice s (one
 // workgroup; every thread takes part in the sums).  F_eps = data + lambda
 // sum sqrt(s_g + eps); stop when (F_eps^{prev} - F_eps) <= tau F_eps after
@@ -320,6 +333,9 @@ __device__ __forceinline__ void rowfwd_body(const Params& P, const Blk B) {
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[2 * NT / 64];
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if constexpr (MODE == RF_STEP_HAAR || MODE == RF_PCG_HAAR || MODE == RF_PCG_Z) {
+    if (pcg_skip(P, D, s_, B.x, MODE == RF_STEP_HAAR ? P.k - 1 : P.k)) return;
+  }
   const size_t off = (size_t)B.x * ROWS * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
   C* t = static_cast<C*>(D.t);
@@ -602,6 +618,9 @@ __device__ __forceinline__ void col_body(const Params& P, const Blk B) {
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if constexpr (MODE == COL_SP || MODE == COL_SP_PQ) {
+    if (pcg_skip(P, D, s_, B.x, P.k)) return;
+  }
   // workgroup = (contrast ch, strip): strips of all contrasts in turn
   constexpr int STRIPS = N / COLS;
   const int ch = B.x / STRIPS, strip = B.x - ch * STRIPS;
@@ -701,6 +720,9 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if constexpr (MODE == RI_SP_HAAR || MODE == RI_SP_TV) {
+    if (pcg_skip(P, D, s_, B.x, P.k)) return;
+  }
   const int row0 = B.x * ROWS;
   const size_t off = (size_t)row0 * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
@@ -866,6 +888,13 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   __shared__ double red[NT / 64];
   __shared__ int timed_out;
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if (pcg_skip(P, D, s_, B.x, P.k - 1)) {
+    // still counted at the slice's barrier, so later launches' targets hold
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(slot_wptr(D, SLOT_SYNC)) + P.k, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   const int row0 = B.x * ROWS;
   const size_t off = (size_t)row0 * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
@@ -1046,6 +1075,7 @@ __device__ __forceinline__ void update_haar_body(const Params& P, const Blk B) {
   using U = Units<N, ROWS>;
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if (pcg_skip(P, D, s_, B.x, P.k)) return;
   const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
@@ -1099,6 +1129,7 @@ __device__ __forceinline__ void last_x_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if (pcg_skip(P, D, s_, B.x, P.k)) return;
   const size_t off = (size_t)B.x * ROWS * N;
   const double rz = slot_sum(slot_ptr(D, SLOT_RZ0 + P.k), P.nrz);
   const double pq = slot_sum(slot_ptr(D, SLOT_PQ0 + P.k), P.npq);
@@ -1238,6 +1269,9 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   __shared__ T w2[WR * WC];
   __shared__ double red[NT / 64];
   FIRLS_SLICE_PROLOGUE_S(B.s)
+  if constexpr (MODE == UP_STEP) {
+    if (pcg_skip(P, D, s_, B.x, P.k)) return;
+  }
   const int n = P.n;
   const int tiles_x = n / TV_TC;
   const int ty = B.x / tiles_x, tx = B.x - ty * tiles_x;
