@@ -1274,7 +1274,12 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   }
   const int n = P.n;
   const int tiles_x = n / TV_TC;
-  const int ty = B.x / tiles_x, tx = B.x - ty * tiles_x;
+  // Workgroup i runs on XCD i mod 8, each XCD with its own L2: the tiles
+  // are dealt out so each XCD gets a contiguous run of them (whole tile
+  // rows), and neighbouring tiles, whose halos overlap, share an L2.
+  const int tiles = P.nrz;
+  const int tile = (tiles & 7) ? B.x : (B.x & 7) * (tiles >> 3) + (B.x >> 3);
+  const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
   // tiles run over the rows of all contrasts; a tile lies in one contrast,
   // whose image (and D1, D2 weights) the pointers below select
   const int ch = (ty * TV_TR) / n;
@@ -1379,7 +1384,7 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
 #undef W2P
 #undef W2M
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[B.x] = tot;
+  if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + (MODE == UP_STEP ? P.k + 1 : 0))[tile] = tot;
 }
 template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_update_tv(Params P) {
