@@ -3,7 +3,9 @@
 Data: tree-group 256^2 problems (20% VD mask, sigma 0.01, 4-level Haar,
 quadtree-pair groups, lambda 0.035) on seeds [seed0, seed0 + n_train) plus a
 validation set; inputs are the zero-filled images A^H b, labels the FIRLS
-solutions run to a tight tolerance.  Training runs the library's own
+solutions run to a tight tolerance.  The default loss is the squared error
+on the k-space entries the solve-time data-consistency step keeps from the
+network (the unsampled ones).  Training runs the library's own
 forward, backward and Adam kernels (firls_cnn_train_step).  Writes the
 float32 parameters (firls ABI order) and a JSON record next to them.
 
@@ -82,6 +84,9 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 4))
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "warmstart_256"))
+    ap.add_argument("--loss", choices=("image", "dc"), default="dc",
+                    help="image: squared error to the FIRLS solution; dc: the same on the k-space entries the "
+                         "data-consistency step keeps from the network (the unsampled ones)")
     a = ap.parse_args()
 
     import torch
@@ -103,9 +108,29 @@ def main():
     outer = np.array([r["outer_iters"] for r in reps])
     print(f"labels: {len(reps)} FIRLS solves in {time.time() - t1:.1f} s, outer mean {outer.mean():.1f} "
           f"max {outer.max()}", flush=True)
-    del b, m
+    del b
 
     net = F.Net(256, a.batch, he_init(a.init_seed))
+    # With the data-consistency loss the target of a batch is
+    # x* + A^H A (x0 - x*), x0 the network's current output: the squared
+    # error to it is ||(I - A^H A)(x0 - x*)||^2 = ||(1 - m) F (x0 - x*)||^2 / N,
+    # the error on the unsampled entries only (A^H A by the library's
+    # operator with a vanishing regulariser weight).
+    op = F.Solver([shape], prec="fp32", max_slices=1, eps=1e-10) if a.loss == "dc" else None
+    zero = torch.zeros(256, 256, dtype=torch.complex64, device="cuda")
+    x0b = torch.empty(a.batch, 256, 256, dtype=torch.complex64, device="cuda")
+    qb = torch.empty_like(x0b)
+
+    def target(idx_or_slice, zfb, lab):
+        if op is None:
+            return lab
+        nb = zfb.shape[0]
+        net.forward(zfb, x0b[:nb])
+        r = (x0b[:nb] - lab).contiguous()
+        mb = m[idx_or_slice]
+        for i in range(nb):
+            op.system(mb[i], 1e-30, zero, r[i], qb[i])
+        return (lab + qb[:nb]).contiguous()
     rs = np.random.default_rng(a.init_seed)
     ntr = a.train
     steps_per_epoch = ntr // a.batch
@@ -118,7 +143,7 @@ def main():
         losses = []
         for c in range(ntr, ntr + a.val, a.batch):
             e = min(c + a.batch, ntr + a.val)
-            _, l = net.gradients(zf[c:e], label[c:e])
+            _, l = net.gradients(zf[c:e], target(slice(c, e), zf[c:e], label[c:e]))
             losses.append(l * (e - c))
         return float(np.sum(losses) / a.val)
 
@@ -130,7 +155,8 @@ def main():
         for k in range(steps_per_epoch):
             idx = torch.from_numpy(np.sort(perm[k * a.batch:(k + 1) * a.batch])).cuda()
             lr = a.lr * 0.5 * (1.0 + math.cos(math.pi * step / total))
-            tot += net.train_step(zf.index_select(0, idx).contiguous(), label.index_select(0, idx).contiguous(), lr)
+            zfb = zf.index_select(0, idx).contiguous()
+            tot += net.train_step(zfb, target(idx, zfb, label.index_select(0, idx).contiguous()), lr)
             step += 1
         vl = val_loss()
         history.append({"epoch": ep + 1, "train_loss": tot / steps_per_epoch, "val_loss": vl})
@@ -141,7 +167,7 @@ def main():
     rec = {"image": 256, "workload": "tree-group 256^2, 20% VD, sigma 0.01, L=4, lambda 0.035",
            "train_seeds": [a.seed0, a.seed0 + a.train], "val_seeds": [a.seed0 + a.train, a.seed0 + a.train + a.val],
            "labels": {"pcg_iters": 20, "outer_tol": a.label_tau, "max_outer": a.label_outer},
-           "batch": a.batch, "epochs": a.epochs, "lr": a.lr, "schedule": "cosine",
+           "batch": a.batch, "epochs": a.epochs, "lr": a.lr, "schedule": "cosine", "loss": a.loss,
            "initial_val_loss": base, "history": history, "seconds": time.time() - t0}
     with open(a.out + ".json", "w") as f:
         json.dump(rec, f, indent=1)
