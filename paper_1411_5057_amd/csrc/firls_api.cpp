@@ -581,7 +581,7 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
     int rc = launch_weights(h, s, P, c, st);
     if (rc || (rc = launch_dense_residual(h, s, P, c, st))) return rc;
     if (s.psi == PSI_HAAR) {
-      KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
+      KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[P.p0_prep ? RI_R0_HAAR_P0 : RI_R0_HAAR], P, rows, st);
     } else {
       KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_TV], P, rows, st);
       KLAUNCH(h, FIRLS_PROF_R0_UPDATE, pk->update_tv[UP_INIT], P, dim3(P.nrz, c), st);
@@ -594,13 +594,13 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
     P.k = h->cfg.pcg_iters - 1;
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQW_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
-    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[P.p0_prep ? RI_R0_HAAR_P0 : RI_R0_HAAR], P, rows, st);
   } else if (s.psi == PSI_HAAR) {
     KLAUNCH(h, FIRLS_PROF_R0_ROWFWD, s.sk->rowfwd[RF_SQ_HAAR], P, rows, st);
     KLAUNCH(h, FIRLS_PROF_GROUP_W, pk->group_w, P, dim3(P.nreg, c), st);
     KLAUNCH(h, FIRLS_PROF_GROUP_D, pk->group_d, P, dim3((s.n_coef + 4 * NT - 1) / (4 * NT), c), st);
     KLAUNCH(h, FIRLS_PROF_R0_COL, s.sk->col[COL_R0], P, dim3(s.col_wgs(h->fp64), c), st);
-    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[RI_R0_HAAR], P, rows, st);
+    KLAUNCH(h, FIRLS_PROF_R0_ROWINV, s.sk->rowinv[P.p0_prep ? RI_R0_HAAR_P0 : RI_R0_HAAR], P, rows, st);
   } else {
     int rc = launch_weights(h, s, P, c, st);
     if (rc) return rc;
@@ -720,7 +720,9 @@ bool multi_class_of(const firls_handle* h, const Shape& S, Launcher fn, int& cls
   for (int m = 0; m < 7; ++m)
     if (hit(sk->rowfwd[m], MC_ROWFWD, m)) return true;
   for (int m = 0; m < 5; ++m)
-    if (hit(sk->col[m], MC_COL, m) || hit(sk->rowinv[m], MC_ROWINV, m)) return true;
+    if (hit(sk->col[m], MC_COL, m)) return true;
+  for (int m = 0; m < 6; ++m)
+    if (hit(sk->rowinv[m], MC_ROWINV, m)) return true;
   return hit(sk->pcg_pair, MC_PAIR, 0) || hit(sk->psi_sq_haar, MC_PSI_SQ_HAAR, 0) ||
          hit(sk->update_haar, MC_UPDATE_HAAR, 0) || hit(sk->last_x, MC_LAST_X, 0) ||
          hit(pk->psi_sq_tv, MC_PSI_SQ_TV, 0) || hit(pk->group_w, MC_GROUP_W, 0) || hit(pk->group_d, MC_GROUP_D, 0) ||

@@ -79,6 +79,7 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowinv<T, N, RI_SP_TV>, b);
   allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
+  allow_lds(k_rowinv<T, N, RI_R0_HAAR_P0>, b);
   // FP32 only: in FP64 the two phases' registers would not fit four
   // workgroups per CU
   constexpr bool pair = Units<N, band_rows(N)>::PER == 1 && sizeof(T) == 4;
@@ -101,6 +102,7 @@ SizeKernels make_size_kernels() {
   k.rowinv[RI_SP_TV] = L_rowinv<T, N, RI_SP_TV>;
   k.rowinv[RI_R0_HAAR] = L_rowinv<T, N, RI_R0_HAAR>;
   k.rowinv[RI_R0_TV] = L_rowinv<T, N, RI_R0_TV>;
+  k.rowinv[RI_R0_HAAR_P0] = L_rowinv<T, N, RI_R0_HAAR_P0>;
   k.psi_sq_haar = L_psi_sq_haar<T, N>;
   k.last_x = L_last_x<T, N>;
   k.update_haar = L_update_haar<T, N>;

@@ -733,7 +733,7 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
     fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, gsrc, [&](int l, int q, C v) { x[l * N + q] = v; });
   } else {
     constexpr bool SP = (MODE == RI_SP_HAAR || MODE == RI_SP_TV);
-    constexpr bool HAAR = (MODE == RI_SP_HAAR || MODE == RI_R0_HAAR);
+    constexpr bool HAAR = (MODE == RI_SP_HAAR || MODE == RI_R0_HAAR || MODE == RI_R0_HAAR_P0);
     // v: the vector the regulariser acts on; out: q (S p) or r (A^H b - S x)
     const C* vfull = static_cast<const C*>(SP ? D.p : D.x);
     const C* v = vfull + off;
@@ -794,7 +794,7 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
           // only the fused step (paper's preconditioner) uses <q, P^{-1} q>,
           // and not after the last iteration
           if (P.precond == PC_PAPER && !P.q_dead) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
-        } else if (P.p0_prep) {
+        } else if constexpr (MODE == RI_R0_HAAR_P0) {
           // the first PCG iteration's start: z0 = P^{-1} r0, p0 = z0, whose
           // row FFTs follow from this thread's own LDS cells (already read)
           precond_tile_paper<true>(w, dv, P.L, col, rho, lam, acc2);
@@ -812,7 +812,7 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
         const double t2 = block_sum(acc2, red);
         if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[B.x] = t2;
       }
-      if (!SP && P.p0_prep) {
+      if constexpr (MODE == RI_R0_HAAR_P0) {
         __syncthreads();
         C* tout = static_cast<C*>(D.t);
         fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},

@@ -27,7 +27,7 @@ using Launcher = hipError_t (*)(const Params&, dim3, hipStream_t);
 struct SizeKernels {
   Launcher rowfwd[7];
   Launcher col[5];
-  Launcher rowinv[5];
+  Launcher rowinv[6];
   Launcher psi_sq_haar;
   Launcher last_x;
   Launcher update_haar;

@@ -47,7 +47,10 @@ enum Precond : int { PC_PAPER = 0, PC_JACOBI = 1, PC_NONE = 2 };
 enum RowFwdMode : int { RF_PLAIN = 0, RF_PCG_HAAR = 1, RF_PCG_Z = 2, RF_STEP_HAAR = 3, RF_SQ_HAAR = 4,
                         RF_SQW_HAAR = 5, RF_PEN_HAAR = 6 };
 enum ColMode : int { COL_SP = 0, COL_R0 = 1, COL_AHB = 2, COL_DC = 3, COL_SP_PQ = 4 };
-enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4 };
+// RI_R0_HAAR_P0: the Haar residual pass that also forms z0 = P^{-1} r0 with
+// the paper's preconditioner, p0 and its row FFT (its own instantiation,
+// so it carries no registers for the other preconditioners).
+enum RowInvMode : int { RI_PLAIN = 0, RI_SP_HAAR = 1, RI_SP_TV = 2, RI_R0_HAAR = 3, RI_R0_TV = 4, RI_R0_HAAR_P0 = 5 };
 enum UpdMode : int { UP_INIT = 0, UP_STEP = 1 };
 // Dense sensing matrix products (batched over the slices of a launch):
 //   G_ATB   x = A^T b            (zero-filled start)
@@ -184,7 +187,7 @@ struct Params {
   int32_t fold_x;        // the last PCG step's x += alpha p rides in the next residual row pass
   int32_t q_dead;        // PCG row inverse: nothing reads this q or <q, P^-1 q> (last iteration of the fused step)
   int32_t test_flags;    // test hooks (TEST_*): conditions forced from the host so the error paths run
-  int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs
+  int32_t p0_prep;       // the residual's row-inverse pass also forms z0, p0 = z0 and its row FFTs (host: picks RI_R0_HAAR_P0)
   int32_t check_r0;      // ... and its first workgroup runs the outer check (Haar)
   int32_t K;             // PCG iterations per outer iteration
   int32_t Tmax;

@@ -19,7 +19,7 @@ void fill_multi_f64_col(MultiKernels& k) {
   allow_multi_lds(km_rowinv<double, M>, most_r);        \
   k.fn[MC_ROWINV][M] = LM_rowinv_f64<M>;
   FIRLS_COL(COL_SP) FIRLS_COL(COL_R0) FIRLS_COL(COL_SP_PQ)
-  FIRLS_INV(RI_SP_HAAR) FIRLS_INV(RI_SP_TV) FIRLS_INV(RI_R0_HAAR) FIRLS_INV(RI_R0_TV)
+  FIRLS_INV(RI_SP_HAAR) FIRLS_INV(RI_SP_TV) FIRLS_INV(RI_R0_HAAR) FIRLS_INV(RI_R0_TV) FIRLS_INV(RI_R0_HAAR_P0)
 #undef FIRLS_COL
 #undef FIRLS_INV
 }
