@@ -73,10 +73,10 @@ def solve_all(F, torch, shape, b, m, lam, *, max_outer, tau, chunk=256):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=12000)
+    ap.add_argument("--train", type=int, default=4000)
     ap.add_argument("--val", type=int, default=256)
     ap.add_argument("--seed0", type=int, default=30000)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--label-tau", type=float, default=1e-7)

@@ -164,7 +164,7 @@ def test_network_gradients_256():
 def test_trained_network_saves_outer_iterations():
     """What the trained network gains over the method without it: 32 fresh
     seeds (20000-20031, disjoint from the training and validation seeds
-    30000-42255) solved at the benchmark setting from the learned start and
+    30000-34255) solved at the benchmark setting from the learned start and
     from A^H b.  Every result is within 1e-4 of the optimum where it is
     stored (seeds 20000-20015), and the learned start needs fewer outer
     iterations on average."""
