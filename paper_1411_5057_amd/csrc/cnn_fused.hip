@@ -17,7 +17,9 @@
 // registers for the whole kernel and takes every fourth 16-pixel block of
 // its layer's row.  Waves w and w + 4k share a SIMD (w mod 4), so each SIMD
 // runs one wave of every role, with the block offsets rotated by role so the
-// rows' odd ninth blocks land on different SIMDs.  bf16 activations and weights, FP32 accumulation on
+// rows' odd ninth blocks land on different SIMDs.  Each role runs its own
+// step loop (same barrier count), so registers are allocated per role.
+// bf16 activations and weights, FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16: lane (q = l / 16, m = l % 16) holds
 // A[m][8q .. 8q + 7] (weights: output channel m of the block, 8 input
 // channels), B[8q .. 8q + 7][m] (8 input channels of pixel m) and
@@ -185,7 +187,7 @@ __device__ __forceinline__ int ring_row(int l, int r) {   // LDS offset of row r
   return (int)(OFF_ACT + (size_t)(l - 1) * ACT_RING + (size_t)slot(r) * ROWPX * PXB);
 }
 
-// Waves 0-2: the input rows, layer 1 (2 -> 32, the 9 taps x 2 channels
+// Waves 0-3: the input rows, layer 1 (2 -> 32, the 9 taps x 2 channels
 // stacked into K = 32) and layer 5 (32 -> 2) with x0 = zf + f(zf).
 __device__ __forceinline__ void net_role_io(const NetArgs& A, const NetGeo& G, unsigned char* smem, int sub, int q,
                                             int m) {
@@ -300,7 +302,7 @@ __device__ __forceinline__ void net_role_io(const NetArgs& A, const NetGeo& G, u
   }
 }
 
-// Waves 3-11: layer l = 2, 3 or 4 (32 -> 32), row r = R0 - 4 + t - 2 (l - 1)
+// Waves 4-15: layer l = 2, 3 or 4 (32 -> 32), row r = R0 - 4 + t - 2 (l - 1)
 // at step t.
 __device__ __forceinline__ void net_role_conv(const NetArgs& A, const NetGeo& G, unsigned char* smem, int l, int sub,
                                               int q, int m) {
