@@ -411,6 +411,7 @@ def run_workload(a, torch, F):
     solver = F.Solver(shapes, prec=prec, max_slices=B, max_outer=a.max_outer, pcg_iters=K, outer_tol=a.tau,
                       eps=1e-10)
     items = items_for(cdt)
+    solver.set_paired(not a.no_pair)
     if a.sub_batch >= 0:
         solver.set_chunk(a.sub_batch)
         solver.set_graphs(a.launch != "direct")
@@ -420,6 +421,8 @@ def run_workload(a, torch, F):
         chunk = a.sub_batch
     else:
         chunk = solver.autotune(items) if not a.no_tune else 0
+        if a.no_pair:
+            solver.set_paired(False)
     batch = solver.prepare(items)
     run = lambda: (solver.solve_batched(batch), None)
     dt, (reps, _), _ = timed(solver, run, a.steps, a.warmup, False, torch)
@@ -439,13 +442,14 @@ def run_workload(a, torch, F):
                       "max_outer": a.max_outer, "prec": prec, "sub_batch": chunk,
                       "launch": "graphs" if solver.graphs else "direct",
                       "schedule": ["per_shape", "across", "largest_first"][solver.schedule],
+                      "paired": solver.paired,
                       "shapes": [f"{n}x{n} {psi}" for (n, psi, _) in keys]},
            "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
            "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
            "converged_frac": float(np.mean([r["converged"] for r in reps]))}
     if prof:
         pcg_cls = ("rowfwd", "col", "rowinv", "update", "last_x")
-        paired = prec == "fp32"
+        paired = prec == "fp32" and solver.paired
         tot_bytes, cls_bytes = 0.0, {}
         for i, (n, psi, _) in enumerate(keys):
             ps = per_shape[i]
@@ -532,6 +536,8 @@ def main():
         solver.set_graphs(a.launch != "direct")
     else:
         chunk = solver.autotune(items) if not a.no_tune else 0
+        if a.no_pair:
+            solver.set_paired(False)
     use_learned = not a.no_learned and os.path.exists(a.weights) and n == 256
     net = F.Net(n, min(B, 64), np.fromfile(a.weights, dtype="<f4")) if use_learned else None
 
@@ -569,7 +575,7 @@ def main():
                    "n": n, "slices": B, "pcg_iters": K, "tau": a.tau, "max_outer": a.max_outer,
                    "start": "learned" if use_learned else "zero-filled", "sub_batch": chunk,
                    "launch": "graphs" if solver.graphs else "direct",
-                   "precond": a.precond},
+                   "paired": solver.paired, "precond": a.precond},
         "outer_iters_mean": float(outer.mean()), "outer_iters_max": int(outer.max()),
         "pcg_iters_per_s": float(pcg.sum() * a.steps / dt),
         "converged_frac": float(np.mean([r["converged"] for r in reps])),

@@ -357,6 +357,9 @@ int firls_set_graphs(firls_handle* h, int32_t enable);
  * so q stays on chip (default).  enable = 0 runs them as two launches;
  * results are bitwise the same. */
 int firls_set_paired(firls_handle* h, int32_t enable);
+/* 1 if the paired pass is enabled (firls_set_paired, firls_autotune), else 0;
+ * FIRLS_E_INVALID for a null handle. */
+int firls_get_paired(const firls_handle* h);
 
 /* Test hook for the paired pass's error path: while enabled, its barrier
  * waits for one workgroup more than the slice has and gives up after a few
@@ -403,15 +406,17 @@ int firls_set_chunk(firls_handle* h, int32_t chunk);
 
 /* Time a few outer iterations of these slices for candidate sub-batch sizes
  * (whole batch, 256, 128, 64, 32), each with graph replay and with direct
- * launches and, for a batch of several masked-FFT shapes, each schedule
- * (FIRLS_SCHED_*), and keep the fastest: the sub-batch size is written to
- * *chosen and the launch mode (1 graphs, 0 direct) to *graphs (either may
- * be NULL), and all three stay set on the handle as firls_set_chunk,
- * firls_set_graphs and firls_set_schedule would set them
- * (firls_get_schedule reads the schedule).  Every x is restored afterwards; on an
- * error the handle keeps its earlier settings.  With the environment
- * variable FIRLS_TUNE_CACHE naming a file, a previous choice for the same
- * shape mix and batch size is reused, and new choices are appended. */
+ * launches, for a batch of several masked-FFT shapes each schedule
+ * (FIRLS_SCHED_*), and where a shape can use it with and without the paired
+ * PCG pass, and keep the fastest: the sub-batch size is written to *chosen
+ * and the launch mode (1 graphs, 0 direct) to *graphs (either may be NULL),
+ * and all four stay set on the handle as firls_set_chunk, firls_set_graphs,
+ * firls_set_schedule and firls_set_paired would set them
+ * (firls_get_schedule and firls_get_paired read the last two).  Every x
+ * is restored afterwards; on an error the handle keeps its earlier
+ * settings.  With the environment variable FIRLS_TUNE_CACHE naming a file,
+ * a previous choice for the same shape mix and batch size is reused, and
+ * new choices are appended (one line each: key|chunk|graphs|schedule|paired). */
 int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_slice* slices, int32_t* chosen,
                    int32_t* graphs);
 

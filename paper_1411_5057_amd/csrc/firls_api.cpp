@@ -2075,6 +2075,8 @@ int firls_set_schedule(firls_handle* h, int32_t schedule) {
 
 int firls_get_schedule(const firls_handle* h) { return h ? h->schedule : FIRLS_E_INVALID; }
 
+int firls_get_paired(const firls_handle* h) { return h ? (h->use_pair ? 1 : 0) : FIRLS_E_INVALID; }
+
 int firls_set_chunk(firls_handle* h, int32_t chunk) {
   if (!h || chunk < 0) return fail(FIRLS_E_INVALID, "bad argument");
   h->chunk = chunk;
@@ -2093,7 +2095,7 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
   }
   // cache key: the batch's shape mix, precision, PCG length and batch size
   std::ostringstream ks;
-  ks << "prec=" << (h->fp64 ? 64 : 32) << " K=" << h->cfg.pcg_iters << " slices=" << n_slices;
+  ks << "v2 prec=" << (h->fp64 ? 64 : 32) << " K=" << h->cfg.pcg_iters << " slices=" << n_slices;
   {
     std::vector<int> cnt(h->shapes.size(), 0);
     for (int i = 0; i < n_slices; ++i) cnt[slices[i].shape_id]++;
@@ -2106,14 +2108,16 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     std::ifstream in(cache);
     std::string line;
     while (std::getline(in, line)) {
-      // key|chunk|graphs|schedule
-      const size_t b3 = line.rfind('|');
+      // key|chunk|graphs|schedule|paired
+      const size_t b4 = line.rfind('|');
+      const size_t b3 = b4 == std::string::npos || b4 == 0 ? std::string::npos : line.rfind('|', b4 - 1);
       const size_t b2 = b3 == std::string::npos || b3 == 0 ? std::string::npos : line.rfind('|', b3 - 1);
       const size_t b1 = b2 == std::string::npos || b2 == 0 ? std::string::npos : line.rfind('|', b2 - 1);
       if (b1 != std::string::npos && line.substr(0, b1) == key) {
         h->chunk = std::atoi(line.c_str() + b1 + 1);
         h->use_graphs = std::atoi(line.c_str() + b2 + 1) != 0;
         h->schedule = std::atoi(line.c_str() + b3 + 1);
+        h->use_pair = std::atoi(line.c_str() + b4 + 1) != 0;
         drop_graphs(h);
         if (chosen) *chosen = h->chunk;
         if (graphs) *graphs = h->use_graphs ? 1 : 0;
@@ -2159,6 +2163,16 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     }
     if (present >= 2 && !dense) scheds = {FIRLS_SCHED_PER_SHAPE, FIRLS_SCHED_ACROSS, FIRLS_SCHED_ACROSS_LARGEST_FIRST};
   }
+  // the paired PCG pass (row inverse of one iteration and the step of the
+  // next in one launch) against the two launches, where a shape has it
+  std::vector<int> pairs = {h->use_pair ? 1 : 0};
+  for (int i = 0; i < n_slices; ++i) {
+    const Shape& S = h->shapes[slices[i].shape_id];
+    if (S.psi == PSI_HAAR && !S.dense && S.sk->pcg_pair && h->cfg.precond == FIRLS_PC_PAPER) {
+      pairs = {1, 0};
+      break;
+    }
+  }
   std::vector<int> cands = {0};
   for (int c : {256, 128, 64, 32})
     if (c < n_slices) cands.push_back(c);
@@ -2166,21 +2180,23 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
   const int T = std::max(1, std::min(3, h->cfg.max_outer));
   double best = 1e300;
   int best_c = 0, best_s = FIRLS_SCHED_PER_SHAPE;
-  bool best_g = true;
+  bool best_g = true, best_p = h->use_pair;
   const int chunk0 = h->chunk, sched0 = h->schedule;
-  const bool graphs0 = h->use_graphs;
+  const bool graphs0 = h->use_graphs, pair0 = h->use_pair;
   const bool prof = h->profiling;
   h->profiling = false;
-  const int per_c = 2 * (int)scheds.size();
+  const int per_p = 2 * (int)scheds.size(), per_c = per_p * (int)pairs.size();
   for (int trial = 0; trial < per_c * (int)cands.size(); ++trial) {
     if (rc) break;
     const int c = cands[trial / per_c];
+    const bool pr = pairs[(trial % per_c) / per_p] != 0;
     const bool g = trial % 2 == 0;
-    const int sc = scheds[(trial % per_c) / 2];
+    const int sc = scheds[(trial % per_p) / 2];
     h->chunk = c;
     h->use_graphs = g;
-    if (h->schedule != sc) {
+    if (h->schedule != sc || h->use_pair != pr) {
       h->schedule = sc;
+      h->use_pair = pr;
       drop_graphs(h);
     }
     double t = 0.0;
@@ -2198,6 +2214,7 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
       best_c = c;
       best_g = g;
       best_s = sc;
+      best_p = pr;
     }
   }
   h->profiling = prof;
@@ -2210,20 +2227,22 @@ int firls_autotune(firls_handle* h, void* stream, int32_t n_slices, const firls_
     h->chunk = chunk0;
     h->use_graphs = graphs0;
     h->schedule = sched0;
+    h->use_pair = pair0;
     drop_graphs(h);
     return rc;
   }
   h->chunk = best_c;
   h->use_graphs = best_g;
-  if (h->schedule != best_s) {
+  if (h->schedule != best_s || h->use_pair != best_p) {
     h->schedule = best_s;
+    h->use_pair = best_p;
     drop_graphs(h);
   }
   if (chosen) *chosen = best_c;
   if (graphs) *graphs = best_g ? 1 : 0;
   if (cache) {
     std::ofstream out(cache, std::ios::app);
-    out << key << "|" << best_c << "|" << (best_g ? 1 : 0) << "|" << best_s << "\n";
+    out << key << "|" << best_c << "|" << (best_g ? 1 : 0) << "|" << best_s << "|" << (best_p ? 1 : 0) << "\n";
   }
   return FIRLS_OK;
 }

@@ -51,7 +51,7 @@ EXPORTED = (
     "firls_cnn_param_count", "firls_cnn_create", "firls_cnn_destroy", "firls_cnn_set_params",
     "firls_cnn_get_params", "firls_cnn_forward", "firls_cnn_gradients", "firls_cnn_train_step",
     "firls_solve_batched_learned", "firls_set_graphs", "firls_set_chunk", "firls_set_paired", "firls_test_sync_timeout", "firls_test_hooks", "firls_autotune",
-    "firls_set_schedule", "firls_get_schedule",
+    "firls_set_schedule", "firls_get_schedule", "firls_get_paired",
 )
 PROF_CLASSES = 15
 
@@ -227,6 +227,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "firls_test_hooks": ([vp, i32], ctypes.c_int),
         "firls_set_schedule": ([vp, i32], ctypes.c_int),
         "firls_get_schedule": ([vp], ctypes.c_int),
+        "firls_get_paired": ([vp], ctypes.c_int),
         "firls_autotune": ([vp, vp, i32, ctypes.POINTER(firls_slice), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                            ctypes.c_int),
         "firls_cnn_param_count": ([], ctypes.c_int32),
@@ -672,14 +673,20 @@ class Solver:
     def schedule(self) -> int:
         return _check(load().firls_get_schedule(self.handle), "firls_get_schedule")
 
+    @property
+    def paired(self) -> bool:
+        """Whether the paired PCG pass is on (set_paired, autotune)."""
+        return _check(load().firls_get_paired(self.handle), "firls_get_paired") == 1
+
     def test_hooks(self, flags: int):
         """Test hooks (FIRLS_TEST_* bits; 0 clears them): forced conditions
         that make the error paths run."""
         _check(load().firls_test_hooks(self.handle, int(flags)), "firls_test_hooks")
 
     def autotune(self, items: List[dict], stream=None) -> int:
-        """Picks the sub-batch size (returned) and the launch mode (kept in
-        ``self.graphs``: True for graph replay) for these slices."""
+        """Picks the sub-batch size (returned), the launch mode (kept in
+        ``self.graphs``: True for graph replay), the mixed-batch schedule and
+        whether the paired PCG pass runs (``self.paired``) for these slices."""
         arr = slice_array(items, None, self.shapes, self.prec)
         chosen, graphs = ctypes.c_int32(), ctypes.c_int32()
         _check(load().firls_autotune(self.handle, _stream(stream), len(items), _as(arr, firls_slice),

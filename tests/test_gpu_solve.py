@@ -266,7 +266,7 @@ def test_chunked_batches_and_autotune():
         assert torch.equal(a["x"], b["x"])
     before = [it["x"].clone() for it in parts]
     chosen = s.autotune(parts)
-    assert chosen in (0, 32) and isinstance(s.graphs, bool)
+    assert chosen in (0, 32) and isinstance(s.graphs, bool) and isinstance(s.paired, bool)
     for a, b in zip(before, parts):
         assert torch.equal(a, b["x"])
     # the tuned sub-batch size and launch mode give the same results
@@ -274,6 +274,33 @@ def test_chunked_batches_and_autotune():
     assert [r["F_eps"] for r in r2] == [r["F_eps"] for r in r0]
     for a, b in zip(whole, parts):
         assert torch.equal(a["x"], b["x"])
+
+
+def test_autotune_cache_restores_every_setting(tmp_path, monkeypatch):
+    """With FIRLS_TUNE_CACHE set, the autotuner appends its choice (sub-batch,
+    launch mode, schedule, paired pass) and a second handle with other
+    settings reads all four back without a new line."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 60 + i, psi="haar", levels=4, groups="quadtree", lam=0.035,
+                                sigma=0.01, frac=0.2) for i in range(40)]
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FIRLS_TUNE_CACHE", str(cache))
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=40, max_outer=5, pcg_iters=10)
+    chosen = s.autotune(_batch(torch, probs))
+    first = (chosen, s.graphs, s.schedule, s.paired)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("v2 ")
+    assert lines[0].split("|")[1:] == [str(chosen), str(int(s.graphs)), str(s.schedule), str(int(s.paired))]
+    s.close()
+    s2 = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=40, max_outer=5, pcg_iters=10)
+    s2.set_graphs(not first[1])
+    s2.set_paired(not first[3])
+    s2.set_chunk(7)
+    chosen2 = s2.autotune(_batch(torch, probs))
+    assert (chosen2, s2.graphs, s2.schedule, s2.paired) == first
+    assert cache.read_text().splitlines() == lines
+    s2.close()
 
 
 def test_prepared_batch_matches_item_lists():
