@@ -643,8 +643,10 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     } else {
       KLAUNCH(h, FIRLS_PROF_COL, s.sk->col[haar ? COL_SP_PQ : COL_SP], P, dim3(s.col_wgs(h->fp64), c), st);
     }
-    // the fused step reads q of iterations 0 .. K-2 only
-    if (!pair || k == K - 1) {
+    // the fused step reads q of iterations 0 .. K-2 only; the paired pass
+    // of the last iteration also forms that iteration's <p, S p> partials,
+    // so with K >= 2 no row-inverse launch is left
+    if (!pair || K == 1) {
       P.q_dead = fused && k == K - 1 ? 1 : 0;
       KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
       P.q_dead = 0;

@@ -749,7 +749,12 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
       // A^H A part into LDS (row inverse FFT, or with a dense sensing matrix
       // the product A^T A v in t, row-major), then lambda Phi^T (d * Phi v)
       // in registers
-      if (P.nofft) {
+      // q of the fused step's last iteration is never read (the next
+      // residual pass needs only alpha and p): that launch forms only
+      // lambda sum d |Phi p|^2, with no transform of t
+      const bool q_dead = SP && P.q_dead;
+      if (q_dead) {
+      } else if (P.nofft) {
         const C* av = static_cast<const C*>(D.t) + off;
         for (int i = threadIdx.x; i < ROWS * N; i += NT) lds[Lay::at(i / N, i % N)] = av[i];
         __syncthreads();
@@ -779,21 +784,19 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
           if (SP) acc += (double)(ld * cabs2t(w[s]));
           w[s] = w[s] * (ld * sgn);
         }
+        if (q_dead) continue;
         haar_col<true>(w, P.L, col);
-        // q of the fused step's last iteration is never read: the next
-        // residual pass needs only alpha (from the sums) and p
-        const bool keep = !(SP && P.q_dead);
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const C o = lds[Lay::at(row + s, col)] + w[s];
-          if (keep) out[(row + s) * N + col] = o;
+          out[(row + s) * N + col] = o;
           w[s] = o;
         }
         // <o, P^{-1} o>: <q, P^{-1} q> for the beta recurrence, or <r0, z0>
         if constexpr (SP) {
           // only the fused step (paper's preconditioner) uses <q, P^{-1} q>,
           // and not after the last iteration
-          if (P.precond == PC_PAPER && !P.q_dead) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
+          if (P.precond == PC_PAPER) precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
         } else if constexpr (MODE == RI_R0_HAAR_P0) {
           // the first PCG iteration's start: z0 = P^{-1} r0, p0 = z0, whose
           // row FFTs follow from this thread's own LDS cells (already read)
@@ -808,7 +811,7 @@ __device__ __forceinline__ void rowinv_body(const Params& P, const Blk B) {
           precond_tile<false, N>(w, d + row * N + col, P.L, col, rho, lam, P.precond, acc2);
         }
       }
-      if (!(SP && P.q_dead)) {
+      if (!q_dead) {
         const double t2 = block_sum(acc2, red);
         if (threadIdx.x == 0) slot_wptr(D, SP ? SLOT_QQ0 + P.k : SLOT_RZ0)[B.x] = t2;
       }
@@ -860,7 +863,9 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 //   a barrier among the workgroups of the slice (their partials complete
 //      alpha and the beta recurrence);
 //   B: x += alpha p, r -= alpha q, z = P^{-1} r, <r, z>, p_k = z + beta p,
-//      and the row FFT of p_k.
+//      and the row FFT of p_k; in the last iteration (k = K - 1) also the
+//      partials of lambda sum d |Phi p_k|^2, so that no row-inverse launch
+//      follows (the column pass adds ||A p_k||^2).
 // q waits in the thread's own LDS cells across the barrier (where A^H A p
 // was), so it never goes through memory, and d in registers; B reads p
 // again (keeping it in registers as well would spill).  The barrier counts arrivals in the
@@ -978,6 +983,12 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   const double rzn = ald * ald * qqo - rzo;
   const T al = (T)ald;
   const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
+  // in the last iteration no launch inverts p_k's rows (its q is never
+  // read): this one also sums lambda d |Phi p_k|^2, the regulariser's part
+  // of <p_k, S p_k>, after its row FFT, from the p it wrote and d read
+  // back (held through the FFT they would spill), in the row-inverse
+  // pass's order
+  const bool last = k == P.K - 1;
   double acc = 0.0;
   if (mine) {
     // the tile column's indices again, opaque to the compiler, so the
@@ -1027,6 +1038,28 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   asm volatile("" : "+v"(tid));
   fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
                                        [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; }, tid);
+  if (last) {
+    double accq = 0.0;
+    int u = threadIdx.x;
+    asm volatile("" : "+v"(u));
+    if (u < U::COUNT) {   // the tile column of Units, from the opaque index
+      const int cb = u % N, rb = (u / N) * 16;
+      const C* pk = static_cast<const C*>(D.p) + off;
+      const T* dk = static_cast<const T*>(D.d) + off;
+      const T lk = (T)D.lambda;
+      C v[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) v[s] = pk[(rb + s) * N + cb];
+      haar_col<false>(v, P.L, cb);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const T ld = lk * dk[(rb + s) * N + cb];
+        accq += (double)(ld * cabs2t(v[s]));
+      }
+    }
+    const double tq = block_sum(accq, red);
+    if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + k)[B.x] = tq;
+  }
 }
 template <typename T, int N>
 __global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
