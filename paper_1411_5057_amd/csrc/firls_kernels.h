@@ -985,11 +985,11 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   const T bs = (T)(rzo > 0.0 && rzn > 0.0 ? rzn / rzo : 0.0);
   // in the last iteration no launch inverts p_k's rows (its q is never
   // read): this one also sums lambda d |Phi p_k|^2, the regulariser's part
-  // of <p_k, S p_k>, after its row FFT, from the p it wrote and d read
-  // back (held through the FFT they would spill), in the row-inverse
-  // pass's order
+  // of <p_k, S p_k>, in the row-inverse pass's order, from the thread's
+  // own LDS cells of p_k and d read again (keeping d and p_k in registers
+  // through the p stores would spill), before the closing row FFT
   const bool last = k == P.K - 1;
-  double acc = 0.0;
+  double acc = 0.0, accq = 0.0;
   if (mine) {
     // the tile column's indices again, opaque to the compiler, so the
     // addresses of A are not kept alive through the barrier for reuse here
@@ -1030,6 +1030,23 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
       p[(rb + s) * N + cb] = pn;
       lds[a] = pn;
     }
+    if (last) {
+      // the tile column once more from an opaque index, so no address of
+      // the loops above stays live into this one
+      int u = threadIdx.x;
+      asm volatile("" : "+v"(u));
+      const int c2 = u % N, r2 = (u / N) * 16;
+      const T* dk = static_cast<const T*>(D.d) + off;
+      C w[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) w[s] = lds[Lay::at(r2 + s, c2)];
+      haar_col<false>(w, P.L, c2);
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const T ld = lam * dk[(r2 + s) * N + c2];
+        accq += (double)(ld * cabs2t(w[s]));
+      }
+    }
   }
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) slot_wptr(D, SLOT_RZ0 + k)[B.x] = tot;
@@ -1039,24 +1056,6 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   fft_lines<T, N, ROWS, ROWMAP, false>(lds, tw, LdsIO<T, N>{lds},
                                        [&](int l, int q, C val) { t[t_index<T, N>(row0 + l, q)] = val; }, tid);
   if (last) {
-    double accq = 0.0;
-    int u = threadIdx.x;
-    asm volatile("" : "+v"(u));
-    if (u < U::COUNT) {   // the tile column of Units, from the opaque index
-      const int cb = u % N, rb = (u / N) * 16;
-      const C* pk = static_cast<const C*>(D.p) + off;
-      const T* dk = static_cast<const T*>(D.d) + off;
-      const T lk = (T)D.lambda;
-      C v[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) v[s] = pk[(rb + s) * N + cb];
-      haar_col<false>(v, P.L, cb);
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const T ld = lk * dk[(rb + s) * N + cb];
-        accq += (double)(ld * cabs2t(v[s]));
-      }
-    }
     const double tq = block_sum(accq, red);
     if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + k)[B.x] = tq;
   }
