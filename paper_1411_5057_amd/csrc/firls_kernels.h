@@ -1294,6 +1294,7 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   constexpr int H = 2, RR = TV_TR + 2 * H, RC = TV_TC + 2 * H, WR = RR + 1, WC = RC + 1;
   constexpr int OUT = TV_TR * TV_TC / NT;   // pixels per thread
   static_assert(OUT * NT == TV_TR * TV_TC, "whole tile per workgroup");
+  static_assert((RC - 2) % 2 == 0, "as many black as red cells in an interior row");
   __shared__ C rn[RR * RC];
   __shared__ C y[RR * RC];
   __shared__ T av[RR * RC];
@@ -1323,6 +1324,8 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   const T* d2 = static_cast<const T*>(D.d) + (size_t)P.C * n * n + cb;
   C* x = static_cast<C*>(D.x) + cb;
   const C* p = static_cast<const C*>(D.p) + cb;
+  // region cell (lr, lc) is red when (par0 + lr + lc) is even
+  const int par0 = (r0 + c0) & 1;
   C xv[OUT], pv[OUT];
   if constexpr (MODE == UP_STEP) {
 #pragma unroll
@@ -1379,14 +1382,16 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
   }
   __syncthreads();
   const int pc = P.precond;
-  for (int i = threadIdx.x; pc == PC_PAPER && i < (RR - 2) * (RC - 2); i += NT) {
-    const int lr = 1 + i / (RC - 2), lc = 1 + i % (RC - 2);
-    const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
-    if (!red_cell) {
-      const int o = lr * RC + lc;
-      const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
-      y[o] = (rn[o] + s * lam) * ((T)1 / av[o]);
-    }
+  // the black cells of the interior only (half of each row), so no lane
+  // idles on a red one
+  constexpr int BPR = (RC - 2) / 2;   // black cells per interior row
+  for (int i = threadIdx.x; pc == PC_PAPER && i < (RR - 2) * BPR; i += NT) {
+    const int row = i / BPR;
+    const int lr = 1 + row;
+    const int lc = 1 + ((par0 + lr) & 1) + 2 * (i - row * BPR);
+    const int o = lr * RC + lc;
+    const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
+    y[o] = (rn[o] + s * lam) * ((T)1 / av[o]);
   }
   __syncthreads();
   C* z = static_cast<C*>(D.z) + cb;
@@ -1397,7 +1402,7 @@ __device__ __forceinline__ void update_tv_body(const Params& P, const Blk B) {
     const int i = threadIdx.x + e * NT;
     const int lr = H + i / TV_TC, lc = H + i % TV_TC;
     const int o = lr * RC + lc;
-    const bool red_cell = ((r0 - H + lr + c0 - H + lc) & 1) == 0;
+    const bool red_cell = ((par0 + lr + lc) & 1) == 0;
     C zz = pc == PC_PAPER ? y[o] : (pc == PC_JACOBI ? rn[o] * ((T)1 / av[o]) : rn[o]);
     if (pc == PC_PAPER && red_cell) {
       const C s = y[o + RC] * W1P(lr, lc) + y[o - RC] * W1M(lr, lc) + y[o + 1] * W2P(lr, lc) + y[o - 1] * W2M(lr, lc);
