@@ -615,8 +615,11 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
 
 // K PCG iterations.  Haar with the paper's preconditioner: 3 launches per
 // iteration (the update of one iteration rides in the row pass of the
-// next) and x += alpha p at the end; Haar with the Jacobi or identity
-// preconditioner, and TV: 4 launches per iteration in the textbook order.
+// next) and x += alpha p at the end; with the paired pass 2 (the row
+// inverse rides in the next step's launch, and the last iteration's
+// <p, S p> share in its own): 2K - 1 in all when the residual pass has
+// prepared p0.  Haar with the Jacobi or identity preconditioner, and TV:
+// 4 launches per iteration in the textbook order.
 int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
   const int C = strip_cols(h->fp64);
