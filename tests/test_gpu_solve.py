@@ -369,17 +369,19 @@ def test_streamed_slots_match_whole_batch(psi):
                 assert torch.equal(a["x"], b["x"]), (graphs, chunk)
 
 
-@pytest.mark.parametrize("n", [64, 256])
-def test_paired_pcg_pass_matches_two_launches(n):
+@pytest.mark.parametrize("n,K", [(64, 4), (256, 4), (64, 1), (64, 2)])
+def test_paired_pcg_pass_matches_two_launches(n, K):
     """The paired PCG pass (row inverse of iteration k - 1 and the step of
-    iteration k in one launch, with a barrier among a slice's workgroups)
-    gives bitwise the results of the two separate launches, over slices
-    that stop at different outer iterations."""
+    iteration k in one launch, with a barrier among a slice's workgroups;
+    its last launch also forms the last iteration's <p, S p> share) gives
+    bitwise the results of the two separate launches, over slices that
+    stop at different outer iterations.  K = 1 has no paired launch (the
+    last row inverse runs alone), K = 2 one, which is also the last."""
     torch = torch_cuda()
     from paper_1411_5057_amd import firls as F
     probs = [synth.make_problem(n, 160 + i, psi="haar", levels=4, groups="quadtree", lam=0.035 * (1 + i % 3),
                                 sigma=0.01, frac=0.2) for i in range(5)]
-    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=5, max_outer=30, pcg_iters=4, outer_tol=1e-4)
+    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=5, max_outer=30, pcg_iters=K, outer_tol=1e-4)
     runs = []
     for paired in (False, True):
         s.set_paired(paired)
