@@ -42,18 +42,21 @@ HBM_PEAK_GBS = 8000.0
 #   col    : read t, mask bits; write t
 #   rowinv : read t, p, d; write q
 #   update : read x, p, q, r, d; write x, r
-def bytes_per_px(cls: str, K: int, fused: bool = True) -> float:
+def bytes_per_px(cls: str, K: int, fused: bool = True, last_rowinv_only: bool = False) -> float:
     """Algorithmic HBM bytes per pixel of one launch of a kernel class.
     ``fused``: the paper's preconditioner, whose residual passes also carry
     the last PCG step's x update and the first one's z0, p0 and row FFT.
     The paired pass (the row inverse of iteration k - 1 in the launch of
     step k: "update", read t, p, x, r, d; write x, r, p, t, also 68 B)
     leaves no row-inverse launch for K >= 2: the last iteration's sum
-    lambda sum d |Phi p|^2 rides in its own launch as well."""
+    lambda sum d |Phi p|^2 rides in its own launch as well, except in
+    launches across shapes, which keep that iteration's row inverse
+    (``last_rowinv_only``: read p and d, 12 B)."""
     if not fused and cls in ("r0_rowfwd", "r0_rowinv"):
         return {"r0_rowfwd": 20.0, "r0_rowinv": 28.0}[cls]
     if fused and cls == "rowinv":
-        return 28.0 - 16.0 / K    # the last iteration reads only p and d (12 B)
+        # K launches per solve, the last reading only p and d (12 B)
+        return 12.0 if last_rowinv_only else 28.0 - 16.0 / K
     return {
         "rowfwd": 28.0,        # first iteration: read r, d; write p, t
         "col": 16.125,         # read t, mask bits; write t
@@ -239,13 +242,14 @@ def roofline_of(prof, n, K, dt, slices, fused=True):
     ``slices`` solves of the instrumented step each start with one residual
     pass that has no x update to fold in."""
     npx = n * n
-    tot_bytes = sum(bytes_per_px(c, K, fused) * v["slice_launches"] * npx for c, v in prof.items())
+    lro = last_rowinv_only(prof)
+    tot_bytes = sum(bytes_per_px(c, K, fused, lro) * v["slice_launches"] * npx for c, v in prof.items())
     if prof.get("r0_rowfwd", {}).get("launches", 0) and not prof.get("last_x", {}).get("launches", 0):
         tot_bytes -= 16.0 * npx * slices
     pcg_cls = {c: v for c, v in prof.items() if c in ("rowfwd", "col", "rowinv", "update", "last_x")}
     dom = max(pcg_cls, key=lambda c: pcg_cls[c]["ms"])
     v = prof[dom]
-    per_launch_bytes = bytes_per_px(dom, K, fused) * npx * v["slice_launches"] / v["launches"]
+    per_launch_bytes = bytes_per_px(dom, K, fused, lro) * npx * v["slice_launches"] / v["launches"]
     avg_s = v["ms"] / v["launches"] / 1e3
     ach = per_launch_bytes / avg_s / 1e9
     tr = traffic_record()
@@ -351,7 +355,15 @@ def run_dense(a, torch, F):
     solver.close()
 
 
-def psi_bytes_per_px(cls: str, psi: str, K: int, prec: str) -> float:
+def last_rowinv_only(ps: dict) -> bool:
+    """Whether a profile's row-inverse launches are only those of the last
+    PCG iterations (one per solve: the paired pass across shapes) rather
+    than one per iteration, from the slice counts of the two classes."""
+    ri, co = ps.get("rowinv", {}).get("slice_launches", 0), ps.get("col", {}).get("slice_launches", 0)
+    return 0 < ri < 0.75 * co
+
+
+def psi_bytes_per_px(cls: str, psi: str, K: int, prec: str, last_only: bool = False) -> float:
     """Algorithmic HBM bytes per pixel of one launch of a kernel class for
     one shape kind (the paper's preconditioner).  FP64 doubles every vector
     and real array (the mask bits stay 1 bit per pixel).  TV, per PCG
@@ -363,7 +375,7 @@ def psi_bytes_per_px(cls: str, psi: str, K: int, prec: str) -> float:
     (read r and both weights, write z: 24)."""
     sc = 2.0 if prec == "fp64" else 1.0
     if psi == "haar":
-        b = bytes_per_px(cls, K, True)
+        b = bytes_per_px(cls, K, True, last_only)
         return (b - 0.125) * sc + 0.125 if cls == "col" else b * sc
     tv = {"rowfwd": 32.0 - 8.0 / K, "col": 16.125, "rowinv": 32.0, "update": 64.0, "psi_sq": 16.0,
           "group_w": 12.0, "group_d": 16.0, "r0_rowfwd": 16.0, "r0_col": 25.0, "r0_rowinv": 32.0,
@@ -453,7 +465,8 @@ def run_workload(a, torch, F):
         for i, (n, psi, _) in enumerate(keys):
             ps = per_shape[i]
             for c, v in ps.items():
-                bb = psi_bytes_per_px(c, "haar" if psi == "haar" else "tv", K, prec) * n * n * v["slice_launches"]
+                bb = psi_bytes_per_px(c, "haar" if psi == "haar" else "tv", K, prec,
+                                      last_rowinv_only(ps)) * n * n * v["slice_launches"]
                 tot_bytes += bb
                 cls_bytes[c] = cls_bytes.get(c, 0.0) + bb
         dom = max((c for c in prof if c in pcg_cls and prof[c]["launches"]), key=lambda c: prof[c]["ms"])

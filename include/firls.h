@@ -351,7 +351,7 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
  * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
 
-/* Haar with the paper's preconditioner (FP32, image sides up to 256): the row
+/* Haar with the paper's preconditioner (image sides up to 256): the row
  * inverse pass of PCG iteration k - 1 and the step of iteration k run in
  * one launch, the workgroups of a slice meeting at a barrier in between,
  * so q stays on chip (default).  enable = 0 runs them as two launches;

@@ -648,8 +648,10 @@ int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st)
     }
     // the fused step reads q of iterations 0 .. K-2 only; the paired pass
     // of the last iteration also forms that iteration's <p, S p> partials,
-    // so with K >= 2 no row-inverse launch is left
-    if (!pair || K == 1) {
+    // so with K >= 2 no row-inverse launch is left, except in a sequence
+    // recorded for launches across shapes, whose paired kernel leaves that
+    // sum to the row inverse
+    if (!pair || (k == K - 1 && (K == 1 || h->rec_seq))) {
       P.q_dead = fused && k == K - 1 ? 1 : 0;
       KLAUNCH(h, FIRLS_PROF_ROWINV, s.sk->rowinv[haar ? RI_SP_HAAR : RI_SP_TV], P, rows, st);
       P.q_dead = 0;

@@ -80,9 +80,8 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
   allow_lds(k_rowinv<T, N, RI_R0_HAAR_P0>, b);
-  // FP32 only: in FP64 the two phases' registers would not fit four
-  // workgroups per CU
-  constexpr bool pair = Units<N, band_rows(N)>::PER == 1 && sizeof(T) == 4;
+  // both precisions (FP64 at two workgroups per CU, as its fused step)
+  constexpr bool pair = Units<N, band_rows(N)>::PER == 1;
   if constexpr (pair) allow_lds(k_pcg_pair<T, N>, b);
   SizeKernels k{};
   k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;

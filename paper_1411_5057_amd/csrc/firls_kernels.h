@@ -863,9 +863,11 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 //   a barrier among the workgroups of the slice (their partials complete
 //      alpha and the beta recurrence);
 //   B: x += alpha p, r -= alpha q, z = P^{-1} r, <r, z>, p_k = z + beta p,
-//      and the row FFT of p_k; in the last iteration (k = K - 1) also the
-//      partials of lambda sum d |Phi p_k|^2, so that no row-inverse launch
-//      follows (the column pass adds ||A p_k||^2).
+//      and the row FFT of p_k; with LAST_SUM, in the last iteration
+//      (k = K - 1) also the partials of lambda sum d |Phi p_k|^2, so that
+//      no row-inverse launch follows (the column pass adds ||A p_k||^2).
+//      The launch across shapes leaves LAST_SUM out (its register budget
+//      is tighter) and keeps that iteration's row-inverse launch.
 // q waits in the thread's own LDS cells across the barrier (where A^H A p
 // was), so it never goes through memory, and d in registers; B reads p
 // again (keeping it in registers as well would spill).  The barrier counts arrivals in the
@@ -876,12 +878,13 @@ __global__ __launch_bounds__(NT) void k_rowinv(Params P) {
 // order and a slice's bands are consecutive, so the workgroups that wait
 // never hold back one that a slice still needs.  The wait is bounded: past
 // the limit the slice is marked FIRLS_E_SYNC and the workgroup goes on.
-// Four workgroups per CU, as the other row passes (without the bound the
-// compiler takes registers for only two).  The closing row FFT is laid out
+// Four workgroups per CU in FP32, as the other row passes (without the
+// bound the compiler takes registers for only two); two in FP64, as the
+// FP64 fused step.  The closing row FFT is laid out
 // from a thread index the compiler cannot see through, so its addresses
 // are recomputed there rather than kept live from phase A, which would
 // not fit the 128 registers of that occupancy and spill.
-template <typename T, int N>
+template <typename T, int N, bool LAST_SUM>
 __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   constexpr int ROWS = band_rows(N);
   using C = cplx<T>;
@@ -988,7 +991,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   // of <p_k, S p_k>, in the row-inverse pass's order, from the thread's
   // own LDS cells of p_k and d read again (keeping d and p_k in registers
   // through the p stores would spill), before the closing row FFT
-  const bool last = k == P.K - 1;
+  const bool last = LAST_SUM && k == P.K - 1;
   double acc = 0.0, accq = 0.0;
   if (mine) {
     // the tile column's indices again, opaque to the compiler, so the
@@ -1061,8 +1064,8 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   }
 }
 template <typename T, int N>
-__global__ __launch_bounds__(NT, 4) void k_pcg_pair(Params P) {
-  pcg_pair_body<T, N>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_pcg_pair(Params P) {
+  pcg_pair_body<T, N, true>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
 }
 
 

@@ -46,13 +46,14 @@ __global__ __launch_bounds__(NT) void km_rowinv(MultiArgs A) {
 }
 
 // the paired PCG pass exists where a thread holds one tile column (sides up
-// to 256) in FP32
+// to 256); here without the last iteration's regulariser sum (the sequence
+// recorded for launches across shapes keeps that iteration's row inverse)
 #define FIRLS_PAIR_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
 template <typename T>
-__global__ __launch_bounds__(NT, 4) void km_pair(MultiArgs A) {
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void km_pair(MultiArgs A) {
   FIRLS_MULTI_PROLOGUE
   switch (P.n) {
-#define FIRLS_CASE(NN) case NN: pcg_pair_body<T, NN>(P, B); break;
+#define FIRLS_CASE(NN) case NN: pcg_pair_body<T, NN, false>(P, B); break;
     FIRLS_PAIR_SIZES(FIRLS_CASE)
 #undef FIRLS_CASE
   }

@@ -1,4 +1,4 @@
-// Launches across shapes: the paired PCG pass (FP32), the Haar update
+// Launches across shapes: the paired PCG pass, the Haar update
 // kernels of the textbook PCG order, the TV and group kernels and the outer
 // check (both precisions), and the LDS sizes of every class.
 #include "firls_inst.h"
@@ -20,10 +20,8 @@ hipError_t LM_prec(const MultiArgs& A, int items, size_t lds, hipStream_t st) {
 
 template <typename T>
 void fill_multi_misc(MultiKernels& k) {
-  if constexpr (sizeof(T) == 4) {
-    allow_multi_lds(km_pair<T>, lds_bytes<T, 256>());
-    k.fn[MC_PAIR][0] = LM_pair<T>;
-  }
+  allow_multi_lds(km_pair<T>, lds_bytes<T, 256>());
+  k.fn[MC_PAIR][0] = LM_pair<T>;
   k.fn[MC_PSI_SQ_HAAR][0] = LM_haar<T, MC_PSI_SQ_HAAR>;
   k.fn[MC_UPDATE_HAAR][0] = LM_haar<T, MC_UPDATE_HAAR>;
   k.fn[MC_LAST_X][0] = LM_haar<T, MC_LAST_X>;

@@ -209,11 +209,10 @@ def test_full_size_tree_config():
     check(p, "fp32", 5, 20)
 
 
-def _batch(torch, probs):
-    from paper_1411_5057_amd import firls as F
+def _batch(torch, probs, prec="fp32"):
     items = []
     for p in probs:
-        b = dev_complex(p.b, "fp32")
+        b = dev_complex(p.b, prec)
         items.append(dict(b=b, mask=dev_mask(p.mask), x=torch.zeros_like(b), lam=p.lam))
     return items
 
@@ -369,8 +368,9 @@ def test_streamed_slots_match_whole_batch(psi):
                 assert torch.equal(a["x"], b["x"]), (graphs, chunk)
 
 
-@pytest.mark.parametrize("n,K", [(64, 4), (256, 4), (64, 1), (64, 2)])
-def test_paired_pcg_pass_matches_two_launches(n, K):
+@pytest.mark.parametrize("n,K,prec", [(64, 4, "fp32"), (256, 4, "fp32"), (64, 1, "fp32"), (64, 2, "fp32"),
+                                       (64, 4, "fp64"), (256, 4, "fp64")])
+def test_paired_pcg_pass_matches_two_launches(n, K, prec):
     """The paired PCG pass (row inverse of iteration k - 1 and the step of
     iteration k in one launch, with a barrier among a slice's workgroups;
     its last launch also forms the last iteration's <p, S p> share) gives
@@ -381,11 +381,11 @@ def test_paired_pcg_pass_matches_two_launches(n, K):
     from paper_1411_5057_amd import firls as F
     probs = [synth.make_problem(n, 160 + i, psi="haar", levels=4, groups="quadtree", lam=0.035 * (1 + i % 3),
                                 sigma=0.01, frac=0.2) for i in range(5)]
-    s = F.Solver([shape_of(probs[0])], prec="fp32", max_slices=5, max_outer=30, pcg_iters=K, outer_tol=1e-4)
+    s = F.Solver([shape_of(probs[0])], prec=prec, max_slices=5, max_outer=30, pcg_iters=K, outer_tol=1e-4)
     runs = []
     for paired in (False, True):
         s.set_paired(paired)
-        items = _batch(torch, probs)
+        items = _batch(torch, probs, prec)
         runs.append((s.solve_batched(items), items))
     (r0, i0), (r1, i1) = runs
     assert r1 == r0
