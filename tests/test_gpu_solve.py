@@ -393,6 +393,29 @@ def test_paired_pcg_pass_matches_two_launches(n, K, prec):
         assert torch.equal(a["x"], b["x"])
 
 
+def test_paired_pass_over_several_rounds_of_workgroups():
+    """A paired launch larger than the GPU holds at once (FP64 at two
+    workgroups per CU: 640 slices of 64^2 are 2560 workgroups against 512
+    resident) still meets at every slice's barrier and gives bitwise the
+    two-launch results."""
+    torch = torch_cuda()
+    from paper_1411_5057_amd import firls as F
+    probs = [synth.make_problem(64, 190 + i, psi="haar", levels=4, groups="quadtree", lam=0.035 * (1 + i % 3),
+                                sigma=0.01, frac=0.2) for i in range(8)]
+    ns = 640
+    s = F.Solver([shape_of(probs[0])], prec="fp64", max_slices=ns, max_outer=4, pcg_iters=4, outer_tol=1e-4)
+    runs = []
+    for paired in (False, True):
+        s.set_paired(paired)
+        items = _batch(torch, [probs[i % len(probs)] for i in range(ns)], "fp64")
+        runs.append((s.solve_batched(items), items))
+    (r0, i0), (r1, i1) = runs
+    assert all(r["status"] >= 0 for r in r1)
+    assert r1 == r0
+    for a, b in zip(i0, i1):
+        assert torch.equal(a["x"], b["x"])
+
+
 def test_paired_barrier_timeout_reports_an_error():
     """The paired pass's in-kernel barrier is bounded: with the test hook
     (one arrival more than can come, a short spin limit) every kernel still
