@@ -40,8 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel must stream:
 #   rowfwd : read r, d, p; write p, t         (p not read at k = 0)
 #   col    : read t, mask bits; write t
-#   rowinv : read t, p, d; write q
-#   update : read x, p, q, r, d; write x, r
+#   rowinv : read t, p, d; write q            (the last iteration: read p, d)
+#   update : the fused step, read x, p, q, r, d; write x, r, p, t; or the
+#            paired pass, read t, p, d, x, r; write x, r, p, t
 def bytes_per_px(cls: str, K: int, fused: bool = True, last_rowinv_only: bool = False) -> float:
     """Algorithmic HBM bytes per pixel of one launch of a kernel class.
     ``fused``: the paper's preconditioner, whose residual passes also carry
