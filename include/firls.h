@@ -351,11 +351,11 @@ int firls_solve_batched_learned(firls_handle* h, firls_cnn* net, void* stream, i
  * own stream, ordered after the null stream's earlier work. */
 int firls_set_graphs(firls_handle* h, int32_t enable);
 
-/* Haar with the paper's preconditioner (image sides up to 256): the row
- * inverse pass of PCG iteration k - 1 and the step of iteration k run in
- * one launch, the workgroups of a slice meeting at a barrier in between,
- * so q stays on chip (default).  enable = 0 runs them as two launches;
- * results are bitwise the same. */
+/* Haar with the paper's preconditioner (FP32: every side; FP64: sides up
+ * to 256): the row inverse pass of PCG iteration k - 1 and the step of
+ * iteration k run in one launch, the workgroups of a slice meeting at a
+ * barrier in between, so q stays on chip (default).  enable = 0 runs them
+ * as two launches; results are bitwise the same. */
 int firls_set_paired(firls_handle* h, int32_t enable);
 /* 1 if the paired pass is enabled (firls_set_paired, firls_autotune), else 0;
  * FIRLS_E_INVALID for a null handle. */

@@ -730,7 +730,9 @@ bool multi_class_of(const firls_handle* h, const Shape& S, Launcher fn, int& cls
     if (hit(sk->col[m], MC_COL, m)) return true;
   for (int m = 0; m < 6; ++m)
     if (hit(sk->rowinv[m], MC_ROWINV, m)) return true;
-  return hit(sk->pcg_pair, MC_PAIR, 0) || hit(sk->psi_sq_haar, MC_PSI_SQ_HAAR, 0) ||
+  // the paired pass of sides above 256 (two tile columns per thread) has a
+  // kernel of its own across shapes
+  return hit(sk->pcg_pair, MC_PAIR, S.n > 256 ? 1 : 0) || hit(sk->psi_sq_haar, MC_PSI_SQ_HAAR, 0) ||
          hit(sk->update_haar, MC_UPDATE_HAAR, 0) || hit(sk->last_x, MC_LAST_X, 0) ||
          hit(pk->psi_sq_tv, MC_PSI_SQ_TV, 0) || hit(pk->group_w, MC_GROUP_W, 0) || hit(pk->group_d, MC_GROUP_D, 0) ||
          hit(pk->update_tv[UP_INIT], MC_UPDATE_TV, UP_INIT) || hit(pk->update_tv[UP_STEP], MC_UPDATE_TV, UP_STEP) ||

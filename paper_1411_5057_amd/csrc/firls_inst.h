@@ -80,8 +80,9 @@ SizeKernels make_size_kernels() {
   allow_lds(k_rowinv<T, N, RI_R0_HAAR>, b);
   allow_lds(k_rowinv<T, N, RI_R0_TV>, b);
   allow_lds(k_rowinv<T, N, RI_R0_HAAR_P0>, b);
-  // both precisions (FP64 at two workgroups per CU, as its fused step)
-  constexpr bool pair = Units<N, band_rows(N)>::PER == 1;
+  // one tile column per thread in both precisions (FP64 at two workgroups
+  // per CU, as its fused step); two in FP32 (sides 384 and 512)
+  constexpr bool pair = Units<N, band_rows(N)>::PER == 1 || (Units<N, band_rows(N)>::PER == 2 && sizeof(T) == 4);
   if constexpr (pair) allow_lds(k_pcg_pair<T, N>, b);
   SizeKernels k{};
   k.rowfwd[RF_PLAIN] = L_rowfwd<T, N, RF_PLAIN>;

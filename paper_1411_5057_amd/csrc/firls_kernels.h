@@ -890,7 +890,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   using C = cplx<T>;
   using Lay = LdsLayout<N>;
   using U = Units<N, ROWS>;
-  static_assert(U::PER == 1, "one tile column per thread");
+  static_assert(U::PER <= 2, "one or two tile columns per thread");
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   __shared__ double red[NT / 64];
@@ -907,30 +907,31 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   const size_t off = (size_t)row0 * N;
   const C* tw = lds_twiddles<T, N, ROWS>(lds, P.tw);
   const int k = P.k;
-  const bool mine = U::valid(0);
-  const int col = U::col(0), row = U::row(0);
   const T* d = static_cast<const T*>(D.d) + off;
   const T rho = (T)P.state[s_].rho, lam = (T)D.lambda;
   C* p = static_cast<C*>(D.p) + off;
-  // d of the thread's tile column stays in registers from A to B
-  T dv[16];
+  // d of the thread's tile columns stays in registers from A to B
+  T dv[U::PER][16];
   // A: the row inverse of iteration k - 1
   {
     const C* tin = static_cast<const C*>(D.t);
     fft_lines<T, N, ROWS, ROWMAP, true>(lds, tw, [&](int l, int q) { return tin[t_index<T, N>(row0 + l, q)]; },
                                         LdsIO<T, N>{lds});
     double acc = 0.0, acc2 = 0.0;
-    if (mine) {
+#pragma unroll
+    for (int ku = 0; ku < U::PER; ++ku) {
+      if (!U::valid(ku)) continue;
+      const int col = U::col(ku), row = U::row(ku);
       C w[16];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         w[s] = p[(row + s) * N + col];
-        dv[s] = d[(row + s) * N + col];
+        dv[ku][s] = d[(row + s) * N + col];
       }
       haar_col<false>(w, P.L, col);
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        const T ld = lam * dv[s];
+        const T ld = lam * dv[ku][s];
         acc += (double)(ld * cabs2t(w[s]));
         w[s] = w[s] * ld;
       }
@@ -941,7 +942,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
         w[s] = lds[a] + w[s];
         lds[a] = w[s];
       }
-      precond_tile_paper<false>(w, dv, P.L, col, rho, lam, acc2);
+      precond_tile_paper<false>(w, dv[ku], P.L, col, rho, lam, acc2);
     }
     // the partials other workgroups read in B go out as device-coherent
     // stores; nothing else crosses workgroups, so the barrier needs no
@@ -993,10 +994,12 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
   // through the p stores would spill), before the closing row FFT
   const bool last = LAST_SUM && k == P.K - 1;
   double acc = 0.0, accq = 0.0;
-  if (mine) {
+#pragma unroll
+  for (int ku = 0; ku < U::PER; ++ku) {
+    if (!U::valid(ku)) continue;
     // the tile column's indices again, opaque to the compiler, so the
     // addresses of A are not kept alive through the barrier for reuse here
-    int cb = col, rb = row;
+    int cb = U::col(ku), rb = U::row(ku);
     asm volatile("" : "+v"(cb), "+v"(rb));
     C* x = static_cast<C*>(D.x) + off;
     C* r = static_cast<C*>(D.r[0]) + off;
@@ -1025,7 +1028,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
         r[g] = v[s0 + u];
       }
     }
-    precond_tile_paper<true>(v, dv, P.L, cb, rho, lam, acc);
+    precond_tile_paper<true>(v, dv[ku], P.L, cb, rho, lam, acc);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int a = Lay::at(rb + s, cb);
@@ -1036,7 +1039,7 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
     if (last) {
       // the tile column once more from an opaque index, so no address of
       // the loops above stays live into this one
-      int u = threadIdx.x;
+      int u = threadIdx.x + ku * NT;
       asm volatile("" : "+v"(u));
       const int c2 = u % N, r2 = (u / N) * 16;
       const T* dk = static_cast<const T*>(D.d) + off;
@@ -1063,8 +1066,15 @@ __device__ __forceinline__ void pcg_pair_body(const Params& P, const Blk B) {
     if (threadIdx.x == 0) slot_wptr(D, SLOT_PQ0 + k)[B.x] = tq;
   }
 }
+// Workgroups per CU of the paired pass: four in FP32 with one tile column
+// per thread, two in FP64 or with two tile columns per thread (sides 384
+// and 512, whose row passes hold two workgroups per CU anyway).
 template <typename T, int N>
-__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void k_pcg_pair(Params P) {
+constexpr int pair_wgs_per_cu() {
+  return sizeof(T) == 4 && Units<N, band_rows(N)>::PER == 1 ? 4 : 2;
+}
+template <typename T, int N>
+__global__ __launch_bounds__(NT, (pair_wgs_per_cu<T, N>())) void k_pcg_pair(Params P) {
   pcg_pair_body<T, N, true>(P, Blk{(int)blockIdx.x, P.list[blockIdx.y]});
 }
 

@@ -58,6 +58,16 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) void km_pair(MultiArgs 
 #undef FIRLS_CASE
   }
 }
+// FP32 sides 384 and 512 (two tile columns per thread, two workgroups per
+// CU): mode 1 of the paired class
+template <typename T>
+__global__ __launch_bounds__(NT, 2) void km_pair_wide(MultiArgs A) {
+  FIRLS_MULTI_PROLOGUE
+  switch (P.n) {
+    case 384: pcg_pair_body<T, 384, false>(P, B); break;
+    case 512: pcg_pair_body<T, 512, false>(P, B); break;
+  }
+}
 
 template <typename T, int CLS>
 __global__ __launch_bounds__(NT) void km_haar(MultiArgs A) {

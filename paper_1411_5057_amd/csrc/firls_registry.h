@@ -31,7 +31,7 @@ struct SizeKernels {
   Launcher psi_sq_haar;
   Launcher last_x;
   Launcher update_haar;
-  Launcher pcg_pair;   // null where a thread holds more than one tile column (sides above 256)
+  Launcher pcg_pair;   // null in FP64 where a thread holds more than one tile column (sides above 256)
 };
 
 // Kernels that depend on the precision only.

@@ -9,6 +9,10 @@ template <typename T>
 hipError_t LM_pair(const MultiArgs& A, int items, size_t lds, hipStream_t st) {
   return launch_multi_kernel(km_pair<T>, A, items, lds, st);
 }
+template <typename T>
+hipError_t LM_pair_wide(const MultiArgs& A, int items, size_t lds, hipStream_t st) {
+  return launch_multi_kernel(km_pair_wide<T>, A, items, lds, st);
+}
 template <typename T, int CLS>
 hipError_t LM_haar(const MultiArgs& A, int items, size_t lds, hipStream_t st) {
   return launch_multi_kernel(km_haar<T, CLS>, A, items, lds, st);
@@ -22,6 +26,10 @@ template <typename T>
 void fill_multi_misc(MultiKernels& k) {
   allow_multi_lds(km_pair<T>, lds_bytes<T, 256>());
   k.fn[MC_PAIR][0] = LM_pair<T>;
+  if constexpr (sizeof(T) == 4) {
+    allow_multi_lds(km_pair_wide<T>, lds_bytes<T, 512>());
+    k.fn[MC_PAIR][1] = LM_pair_wide<T>;
+  }
   k.fn[MC_PSI_SQ_HAAR][0] = LM_haar<T, MC_PSI_SQ_HAAR>;
   k.fn[MC_UPDATE_HAAR][0] = LM_haar<T, MC_UPDATE_HAAR>;
   k.fn[MC_LAST_X][0] = LM_haar<T, MC_LAST_X>;

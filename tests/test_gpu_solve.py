@@ -369,14 +369,15 @@ def test_streamed_slots_match_whole_batch(psi):
 
 
 @pytest.mark.parametrize("n,K,prec", [(64, 4, "fp32"), (256, 4, "fp32"), (64, 1, "fp32"), (64, 2, "fp32"),
-                                       (64, 4, "fp64"), (256, 4, "fp64")])
+                                       (384, 4, "fp32"), (512, 4, "fp32"), (64, 4, "fp64"), (256, 4, "fp64")])
 def test_paired_pcg_pass_matches_two_launches(n, K, prec):
     """The paired PCG pass (row inverse of iteration k - 1 and the step of
     iteration k in one launch, with a barrier among a slice's workgroups;
     its last launch also forms the last iteration's <p, S p> share) gives
     bitwise the results of the two separate launches, over slices that
     stop at different outer iterations.  K = 1 has no paired launch (the
-    last row inverse runs alone), K = 2 one, which is also the last."""
+    last row inverse runs alone), K = 2 one, which is also the last; at
+    sides 384 and 512 (FP32) a thread holds two tile columns."""
     torch = torch_cuda()
     from paper_1411_5057_amd import firls as F
     probs = [synth.make_problem(n, 160 + i, psi="haar", levels=4, groups="quadtree", lam=0.035 * (1 + i % 3),
