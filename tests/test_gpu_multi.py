@@ -23,8 +23,10 @@ MATCH_TOL = {"fp32": 1e-5, "fp64": 1e-12}
 
 
 def mixed(prec):
-    """Haar (tree groups) at sides 64, 96, 128, 192, 256 and 384 (the last
-    without the paired pass) and TV at 64 and 128, two slices of some."""
+    """Haar (tree groups) at sides 64, 96, 128, 192, 256 and 384 (in FP32
+    the paired pass with two tile columns per thread, its own kernel across
+    shapes; in FP64 the two-launch form) and TV at 64 and 128, two slices
+    of some."""
     probs = []
     for i, n in enumerate((64, 96, 128, 192, 256, 384, 64, 128)):
         probs.append(synth.make_problem(n, 600 + i, psi="haar", levels=4, groups="quadtree",
@@ -58,11 +60,15 @@ def items(torch, probs, sid, prec):
     return out
 
 
+@pytest.mark.parametrize("paired", [True, False])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_schedules_agree(prec):
+def test_schedules_agree(prec, paired):
+    """Every schedule, with graph replay and direct launches, with the
+    paired PCG pass on and off, gives the per-shape results."""
     torch = torch_cuda()
     from paper_1411_5057_amd import firls as F
     s, probs, sid = setup(prec)
+    s.set_paired(paired)
     runs = {}
     for sched in (F.FIRLS_SCHED_PER_SHAPE, F.FIRLS_SCHED_ACROSS, F.FIRLS_SCHED_ACROSS_LARGEST_FIRST):
         for graphs in (False, True):
