@@ -98,7 +98,7 @@ def test_across_shapes_against_the_oracle():
     s.set_schedule(F.FIRLS_SCHED_ACROSS_LARGEST_FIRST)
     it = items(torch, probs, sid, "fp32")
     reps = s.solve_batched(it)
-    for i in (2, 5, 9):          # Haar 128 (paired), Haar 384 (unpaired), TV 128
+    for i in (2, 5, 9):          # Haar 128 (paired), Haar 384 (paired, two tile columns per thread), TV 128
         ops = Operators.from_problem(probs[i])
         ref = firls(ops, T, K)
         fe = ops.objective(to_np(it[i]["x"]))[0]
