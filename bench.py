@@ -167,30 +167,83 @@ def oracle_optima():
         return {int(r["seed"]): float(r["F_eps"]) for r in json.load(f)["optima"]}
 
 
-def cpu_baseline(n, tau, max_outer, K, seeds, gpu_x, gpu_fe, budget_s=12.0, max_slices=64):
-    """The FP64 oracle, untouched, on the first slices of the same workload
-    (the first seeds of the timed batch), one after another until about
-    ``budget_s`` seconds of solving have passed.  Each oracle result is also
-    the reference of the GPU's result for the same slice (plain start, same
-    K, tau and cap): the per-result error against the FP64 oracle."""
+def _oracle_share(job):
+    """One worker of the CPU baseline: the FP64 oracle, untouched, on its
+    share of the sampled slices, in a fresh interpreter (numpy and the
+    oracle only, one thread).  Returns per slice its solving time and the
+    errors of the GPU's result for it against the oracle's."""
+    n, tau, max_outer, K, share = job
     import synth
     from oracle.firls import Operators, firls
-    solved, outer, dt = 0, 0, 0.0
-    errs = []
-    while solved < min(max_slices, len(seeds)) and dt < budget_s:
-        ops = Operators.from_problem(synth.cfg1(seeds[solved], n=n))
+    out = []
+    for seed, x, fe_gpu, outer_gpu in share:
+        ops = Operators.from_problem(synth.cfg1(seed, n=n))
         t0 = time.perf_counter()
         rep = firls(ops, max_outer, K, tau=tau)
-        dt += time.perf_counter() - t0
-        x = gpu_x[solved].astype(np.complex128)
-        fe = ops.objective(x)[0]
-        errs.append({"seed": seeds[solved], "outer_gpu": int(gpu_fe[solved][1]), "outer_oracle": rep.outer_iters,
-                     "F_eps_rel_diff": abs(fe - rep.F_eps) / rep.F_eps,
-                     "F_eps_reported_vs_fp64": abs(gpu_fe[solved][0] - fe) / fe,
-                     "x_rel_l2": float(np.linalg.norm(x - rep.x) / np.linalg.norm(rep.x)),
-                     "x_max_rel": float(np.max(np.abs(x - rep.x)) / np.max(np.abs(rep.x)))})
-        solved += 1
-        outer += rep.outer_iters
+        dt = time.perf_counter() - t0
+        xd = x.astype(np.complex128)
+        fe = ops.objective(xd)[0]
+        out.append({"seed": seed, "seconds": dt, "pcg_oracle": rep.pcg_iters,
+                    "outer_gpu": int(outer_gpu), "outer_oracle": rep.outer_iters,
+                    "F_eps_rel_diff": abs(fe - rep.F_eps) / rep.F_eps,
+                    "F_eps_reported_vs_fp64": abs(fe_gpu - fe) / fe,
+                    "x_rel_l2": float(np.linalg.norm(xd - rep.x) / np.linalg.norm(rep.x)),
+                    "x_max_rel": float(np.max(np.abs(xd - rep.x)) / np.max(np.abs(rep.x)))})
+    return out
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, tau, max_outer, K, seeds, gpu_x, gpu_fe, per_worker=5, workers=None):
+    """The FP64 oracle, untouched, on the first slices of the same workload
+    (the first seeds of the timed batch) in a pool of worker processes, one
+    per host core (at most 16, the host share of one GPU), each solving
+    ``per_worker`` slices one after another.  Pool throughput = slices over
+    the slowest worker's solving time (the workers run at once); the
+    single-core time per solve is the mean.  Each oracle result is also the
+    reference of the GPU's result for the same slice (plain start, same K,
+    tau and cap): the per-result error against the FP64 oracle."""
+    import multiprocessing as mp
+    P = workers or max(1, min(os.cpu_count() or 1, 16))
+    ns = min(len(seeds), P * per_worker)
+    P = min(P, ns)
+    shares = [[] for _ in range(P)]
+    for i in range(ns):
+        shares[i % P].append((seeds[i], gpu_x[i], gpu_fe[i][0], gpu_fe[i][1]))
+    # the workers start as fresh interpreters (nothing of this process's
+    # GPU state), single-threaded
+    keep = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for v in keep:
+        os.environ[v] = "1"
+    jobs = [(n, tau, max_outer, K, sh) for sh in shares]
+    try:
+        with mp.get_context("spawn").Pool(P) as pool:
+            # bounded: a pool whose workers cannot start would wait forever
+            parts = pool.map_async(_oracle_share, jobs).get(timeout=600)
+    except Exception as e:   # no pool on this host: the same slices in this process
+        print(f"cpu baseline: worker pool unavailable ({e!r}); one process", file=sys.stderr)
+        P = 1
+        parts = [_oracle_share((n, tau, max_outer, K, [it for sh in shares for it in sh]))]
+    finally:
+        for v, old in keep.items():
+            if old is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = old
+    errs = sorted((e for part in parts for e in part), key=lambda e: e["seed"])
+    wall = max(sum(e["seconds"] for e in part) for part in parts)
+    solve_s = float(np.mean([e["seconds"] for e in errs]))
+    outer = float(np.mean([e["outer_oracle"] for e in errs]))
+    pcg_s = sum(e["pcg_oracle"] for e in errs) / wall
     same = [e for e in errs if e["outer_gpu"] == e["outer_oracle"]]
     per_result = {
         "slices": len(errs), "same_outer_count": len(same),
@@ -201,11 +254,14 @@ def cpu_baseline(n, tau, max_outer, K, seeds, gpu_x, gpu_fe, budget_s=12.0, max_
         "reported_F_eps_vs_fp64_max": max(e["F_eps_reported_vs_fp64"] for e in errs),
         "note": "GPU plain-start results against the FP64 oracle run from the same start with the same K, tau and "
                 "cap; x compared where both took the same number of outer iterations",
-        "per_slice": errs}
-    return {"value": solved / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solved} slices (seeds {seeds[0]}-{seeds[solved - 1]}) of the same workload, "
-                      f"{outer / solved:.1f} outer x {K} PCG on average, numpy FP64, single process; "
-                      f"{dt:.1f} s of solving"}, per_result
+        "per_slice": [{k: v for k, v in e.items() if k not in ("seconds", "pcg_oracle")} for e in errs]}
+    return {"value": len(errs) / wall, "unit": "solves/s", "cores": P, "kind": "oracle",
+            "single_core_s_per_solve": solve_s, "pcg_iters_per_s": pcg_s, "outer_iters_mean": outer,
+            "host": f"{host_cpu_model()}, nproc {os.cpu_count()}",
+            "sample": f"{len(errs)} slices (seeds {seeds[0]}-{seeds[len(errs) - 1]}) of the same workload, "
+                      f"{outer:.1f} outer x {K} PCG on average, numpy FP64, {P} single-threaded worker "
+                      f"processes of {per_worker} slices at most each; slowest worker {wall:.1f} s of solving"}, \
+        per_result
 
 
 def timed(solver, run, steps, warmup, profile, torch):
