@@ -73,3 +73,26 @@ def test_roofline_of_a_profile(bench, monkeypatch):
     # of each of the 500 slices has no x update to fold in (16 B/px less)
     tot = (16.125 * 51200 + 68.0 * 38400 + 36.0 * 12800) * n * n - 16.0 * n * n * 500
     assert gbs == pytest.approx(tot / 0.070 / 1e9)
+
+
+def test_cpu_baseline_pool():
+    """The oracle baseline in a pool of worker processes: every sampled
+    slice is solved once, the pool's rate and core count are reported, and
+    results handed in as the GPU's (here the oracle's own, in complex64)
+    compare to the oracle within single-precision rounding."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import numpy as np
+    import synth
+    from oracle.firls import Operators, firls
+    seeds = [20000, 20001, 20002]
+    xs, fes = [], []
+    for sd in seeds:
+        r = firls(Operators.from_problem(synth.cfg1(sd, n=64)), 4, 4, tau=8e-6)
+        xs.append(r.x.astype(np.complex64))
+        fes.append((r.F_eps, r.outer_iters))
+    cb, per = bench.cpu_baseline(64, 8e-6, 4, 4, seeds, xs, fes, per_worker=2, workers=2)
+    assert cb["cores"] == 2 and cb["kind"] == "oracle" and cb["value"] > 0
+    assert per["slices"] == 3 and per["same_outer_count"] == 3
+    assert sorted(e["seed"] for e in per["per_slice"]) == seeds
+    assert per["F_eps_rel_diff_max"] < 1e-6 and per["x_rel_l2_max_same_count"] < 1e-6
