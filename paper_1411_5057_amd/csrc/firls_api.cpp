@@ -52,7 +52,7 @@ struct Shape {
   int ell_gw = 0, ell_tw = 0;
   size_t pixels() const { return (size_t)C * n * n; }
   int row_wgs() const { return C * n / band_rows(n); }                  // row-pass workgroups
-  int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64)); }  // column-pass workgroups
+  int col_wgs(bool fp64) const { return C * (n / strip_cols(fp64, n)); }  // column-pass workgroups
   int64_t n_members = 0;
   int32_t* d_gptr = nullptr;
   int32_t* d_gidx = nullptr;
@@ -414,8 +414,8 @@ Params base_params(const firls_handle* h, const Shape& s, int shape_id, const in
   P.mono_slack = (h->test_flags & TEST_NONMONOTONE) ? -1.0 : (h->fp64 ? 1e-12 : 1e-6);
   const int R = band_rows(s.n);
   // partials per slot: one per workgroup, over the rows of every contrast
-  P.npq = s.C * (s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64) : 0));
-  P.ndata = s.C * (s.n / strip_cols(h->fp64));
+  P.npq = s.C * (s.n / R + (s.psi == PSI_HAAR ? s.n / strip_cols(h->fp64, s.n) : 0));
+  P.ndata = s.C * (s.n / strip_cols(h->fp64, s.n));
   P.nrz = s.C * (s.psi == PSI_HAAR ? s.n / R : (s.n / TV_TR) * (s.n / TV_TC));
   if (s.dense) {
     // the A x / A p products write one partial per row tile
@@ -622,7 +622,6 @@ int launch_prep(firls_handle* h, const Shape& s, const Params& P0, int c, hipStr
 // 4 launches per iteration in the textbook order.
 int launch_pcg(firls_handle* h, const Shape& s, Params P, int c, hipStream_t st) {
   const PrecKernels* pk = prec_kernels(h->fp64);
-  const int C = strip_cols(h->fp64);
   const bool haar = s.psi == PSI_HAAR;
   const bool fused = haar && h->cfg.precond == FIRLS_PC_PAPER;
   const dim3 rows(s.row_wgs(), c);
@@ -1325,7 +1324,7 @@ int upload_shape(firls_handle* h, const firls_shape& in, Shape& s) {
   if ((s.n_groups + GROUPS_PER_WG - 1) / GROUPS_PER_WG > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many groups");
   {
     // every partial-sum slot holds one value per workgroup of a pass
-    const int R = band_rows(n), sc = strip_cols(h->fp64);
+    const int R = band_rows(n), sc = strip_cols(h->fp64, n);
     const int most = std::max({s.C * (n / R + n / sc), s.C * (n / TV_TR) * (n / TV_TC) * (s.psi == PSI_TV)});
     if (most > PMAX) return fail(FIRLS_E_UNSUPPORTED, "too many contrasts for this image size");
   }
@@ -1803,7 +1802,6 @@ int firls_op_system(firls_handle* h, void* stream, int32_t shape_id, const uint8
   B.lambda = lambda;
   if ((rc = op_upload(h, st, 2))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int C = strip_cols(h->fp64);
   Params PA = base_params(h, s, shape_id, h->d_list);
   Params PB = base_params(h, s, shape_id, h->d_list + 1);
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
@@ -1843,7 +1841,6 @@ int firls_op_precond(firls_handle* h, void* stream, int32_t shape_id, const uint
   B.lambda = lambda;
   if ((rc = op_upload(h, st, 2))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int C = strip_cols(h->fp64);
   Params PA = base_params(h, s, shape_id, h->d_list);
   Params PB = base_params(h, s, shape_id, h->d_list + 1);
   LAUNCH(prec_kernels(h->fp64)->slice_init, PA, dim3(2), st);
@@ -1870,7 +1867,6 @@ int firls_op_objective(firls_handle* h, void* stream, int32_t shape_id, const vo
   A.lambda = lambda;
   if ((rc = op_upload(h, st, 1))) return rc;
   const Shape& s = h->shapes[shape_id];
-  const int C = strip_cols(h->fp64);
   Params P = base_params(h, s, shape_id, h->d_list);
   P.Tmax = 0;
   P.tau = 0.0;

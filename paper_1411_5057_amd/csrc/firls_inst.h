@@ -13,7 +13,7 @@ constexpr size_t lds_bytes() {
 }
 template <typename T, int N>
 constexpr size_t lds_col_bytes() {
-  return ((size_t)Geo<T>::COLS * LdsLayout<N>::LS + N) * sizeof(cplx<T>);
+  return ((size_t)Geo<T, N>::COLS * LdsLayout<N>::LS + N) * sizeof(cplx<T>);
 }
 
 template <class K>

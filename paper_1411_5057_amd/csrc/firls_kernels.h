@@ -32,8 +32,8 @@
 
 namespace firls {
 
-template <typename T> struct Geo {
-  static constexpr int COLS = strip_cols(sizeof(T) == 8);   // strip width of column passes
+template <typename T, int N> struct Geo {
+  static constexpr int COLS = strip_cols(sizeof(T) == 8, N);   // strip width of column passes
 };
 
 // The twiddle table exp(-2 pi i k / N), k < N, copied into LDS behind the
@@ -54,7 +54,7 @@ __device__ __forceinline__ const cplx<T>* lds_twiddles(cplx<T>* lds, const void*
 // rows of all contrasts (row = c n + local row).
 template <typename T, int N>
 __device__ __forceinline__ size_t t_index(int row, int col) {
-  constexpr int TS = Geo<T>::COLS;
+  constexpr int TS = Geo<T, N>::COLS;
   const int ch = row / N, lr = row - ch * N;
   return (size_t)ch * N * N + (size_t)(col / TS) * (N * TS) + (size_t)lr * TS + (col % TS);
 }
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(NT) void k_rowfwd(Params P) {
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
 __device__ __forceinline__ void col_body(const Params& P, const Blk B) {
-  constexpr int COLS = Geo<T>::COLS;
+  constexpr int COLS = Geo<T, N>::COLS;
   using C = cplx<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -627,10 +627,13 @@ __device__ __forceinline__ void col_body(const Params& P, const Blk B) {
   const int col0 = strip * COLS;
   const C* tw = lds_twiddles<T, N, COLS>(lds, P.tw);
   C* t = static_cast<C*>(D.t) + (size_t)ch * N * N + (size_t)strip * N * COLS;   // this strip's block
-  // sampled(c, row): bit of the packed mask word of this strip and row
-  const uint16_t* mw = D.mbits + (size_t)(col0 >> 4) * N * P.C + (size_t)ch * N;
-  const int sh0 = col0 & 15;
-  auto sampled = [&](int c, int row) { return (mw[row] >> (sh0 + c)) & 1u; };
+  // sampled(c, row): bit of column col0 + c in the packed mask word of its
+  // 16 columns and the row
+  const uint16_t* mw = D.mbits + (size_t)ch * N;
+  auto sampled = [&](int c, int row) {
+    const int gc = col0 + c;
+    return (mw[(size_t)(gc >> 4) * N * P.C + row] >> (gc & 15)) & 1u;
+  };
   auto gsrc = [&](int c, int row) { return t[row * COLS + c]; };
   auto gdst = [&](int c, int row, C v) { t[row * COLS + c] = v; };
   const T sn = (T)1 / (T)N;

@@ -17,7 +17,12 @@ __host__ __device__ constexpr int band_rows(int n) {
   return n >= 192 ? 16 : ((n == 128 || n == 96) ? 32 : n);
 }
 // Columns per workgroup of the column pass.
-__host__ __device__ constexpr int strip_cols(bool fp64) { return fp64 ? 8 : 16; }
+// Enough columns that the first FFT stage's butterflies fill the workgroup
+// at small sides (the whole image up to 64), 16 from 192 up (8 in FP64 above
+// 256), with a strip of at most about 70 KB of LDS.
+__host__ __device__ constexpr int strip_cols(bool fp64, int n) {
+  return n <= 64 ? n : (n <= 128 ? 32 : (fp64 && n > 256 ? 8 : 16));
+}
 
 // Slots of the per-slice FP64 partial-sum area.  Every slot holds up to
 // PMAX partials, each written by exactly one workgroup, and every consumer
